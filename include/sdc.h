@@ -1,0 +1,172 @@
+/*
+ * sdc.h -- C ABI of the MI355X (gfx950) inverse-free spectral split library.
+ *
+ * The library computes one step of the randomized spectral divide-and-conquer
+ * of Ballard, Demmel and Dumitriu, "Minimizing Communication for
+ * Eigenproblems and the Singular Value Decomposition" (arXiv 1011.3077):
+ *
+ *   - implicit repeated squaring (IRS, Alg. 3 of Sec. 3.1): repeated
+ *     Householder QR of the stacked 2n x n matrix [B_j; -A_j] = Q [R_j; 0]
+ *     and the updates A_{j+1} = Q12^T A_j, B_{j+1} = Q22^T B_j, until
+ *     ||R_j - R_{j-1}||_1 <= tau ||R_{j-1}||_1;
+ *   - the generalized randomized URV (GRURV, Alg. 2 on RURV, Alg. 1) that
+ *     extracts an orthogonal basis of the right (and left) deflating subspace
+ *     from (A_p + B_p)^{-1} A_p without inverses;
+ *   - the block form and split-point choice of RGNEP (Alg. 4) and RSEP
+ *     (Alg. 6): A_hat = Q_L^T A Q_R (and B_hat) with the block size k that
+ *     minimizes ||E21||_1/||A||_1 (+ ||F21||_1/||B||_1).
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are real, COLUMN-MAJOR, with a leading dimension >= n.
+ *   - Matrix pointers are DEVICE pointers (memory from hipMalloc or a torch
+ *     CUDA/HIP tensor) on the handle's device.  Inputs are never modified;
+ *     outputs are caller-allocated and written in full.
+ *   - Inputs and outputs are always FP64.  SDC_FP32_REFINE only changes the
+ *     internal arithmetic of the repeated squaring (FP32 with FP32
+ *     accumulation) and adds an FP64 refinement of the basis.
+ *   - Eigenvalues of the pencil A - lambda B are the roots of
+ *     det(A - lambda B) = 0.  The region's boundary is mapped to the unit
+ *     circle (Sec. 3.3): a half plane Re z < shift with scale s becomes the
+ *     pencil (A - (shift - s) B, A - (shift + s) B); a disk |z - c| < r
+ *     becomes (A - c B, r B).
+ *   - Ordering: the leading k_lead columns of Q (of Q_R) span the deflating
+ *     subspace of the eigenvalues OUTSIDE the region (the range of
+ *     (A_p + B_p)^{-1} A_p, Sec. 3.2), so A11 = A_hat[0:k, 0:k] holds the
+ *     outside eigenvalues and A22 the n_inside = n - k_lead inside ones.
+ *   - Negative status: outputs are undefined.  Positive status
+ *     (NOT_CONVERGED, NO_SPLIT, RANK_AMBIGUOUS): outputs hold the best split
+ *     found and *info is filled.
+ *   - Calls are synchronous with respect to the host and run on the stream
+ *     given to sdc_create.  A handle must not be used by two host threads at
+ *     once; use one handle per stream.
+ *   - Workspace is allocated by the library from device memory and kept in
+ *     the handle, capped by hbm_budget_bytes (0 = no cap).  A call whose
+ *     workspace would exceed the cap returns SDC_ERR_NOMEM.
+ */
+#ifndef SDC_H_
+#define SDC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sdc_handle_s* sdc_handle_t;
+
+typedef enum {
+    SDC_OK = 0,
+    SDC_NOT_CONVERGED = 1,   /* IRS hit maxit (Alg. 3 "until ... j > maxit") */
+    SDC_NO_SPLIT = 2,        /* every eigenvalue lies on one side of the curve */
+    SDC_RANK_AMBIGUOUS = 3,  /* retries exhausted without a split meeting split_tol */
+    SDC_ERR_INVALID = -1,    /* bad argument */
+    SDC_ERR_NOMEM = -2,      /* device allocation failed or budget exceeded */
+    SDC_ERR_DEVICE = -3,     /* a HIP runtime call failed */
+    SDC_ERR_NONFINITE = -4   /* NaN/Inf met in the iteration */
+} sdc_status_t;
+
+typedef enum { SDC_FP64 = 0, SDC_FP32_REFINE = 1 } sdc_prec_t;
+typedef enum { SDC_UNIT_DISK = 0, SDC_DISK = 1, SDC_HALFPLANE = 2 } sdc_region_kind_t;
+
+/* Splitting curve (Sec. 3.3): SDC_DISK |z - center| < radius;
+ * SDC_HALFPLANE Re z < shift with Moebius scale `scale` (> 0). */
+typedef struct {
+    int kind;
+    double center, radius;
+    double shift, scale;
+} sdc_region_t;
+
+typedef struct {
+    int prec;            /* sdc_prec_t */
+    double tau;          /* IRS tolerance; <= 0 -> sqrt(eps) of the iterate precision */
+    int maxit;           /* IRS iteration cap (Alg. 3); <= 0 -> 60 */
+    uint64_t seed;       /* key of the Gaussian draw; attempt a uses seed + a */
+    int max_retries;     /* extra GRURV draws after a failed split (default 2) */
+    double split_tol;    /* accept a split when e(k) <= split_tol; <= 0 -> 1e-10 */
+    const double* G;     /* optional DEVICE array of (max_retries+1)*2 column-major
+                            n x n Gaussian matrices, index [attempt*2 + side]
+                            (side 0 right, 1 left); NULL -> Philox4x32-10 draws */
+    int diagnostics;     /* nonzero: also compute info->orth_err (one more GEMM) */
+} sdc_opts_t;
+
+typedef struct {
+    int n;
+    int k_lead;          /* leading block size (eigenvalues outside) */
+    int n_inside;        /* n - k_lead: eigenvalues inside the region */
+    int iters_right;     /* IRS iterations p on (A, B) */
+    int iters_left;      /* IRS iterations p on (A^T, B^T) (pencils) */
+    int attempts;        /* Gaussian draws used (1 + retries) */
+    int refine_rounds;   /* FP64 refinement rounds (SDC_FP32_REFINE) */
+    int k_rho;           /* rank read off the GRURV diagonals */
+    double rconv_last;   /* last relative R change of the right-side IRS */
+    double e21_rel;      /* minimized ||E21||_1/||A||_1 (+ ||F21||_1/||B||_1) */
+    double orth_err;     /* ||Q^T Q - I||_F of Q (Q_R), if diagnostics */
+    double rank_gap;     /* ratio across the largest gap of the sorted diagonal ratios */
+    double ms;           /* wall time of the call in milliseconds */
+} sdc_info_t;
+
+/* Fill *opts with the defaults (FP64, tau = sqrt(eps), maxit 60, seed 0,
+ * 2 retries, split_tol 1e-10, no caller Gaussian). */
+void sdc_opts_default(sdc_opts_t* opts);
+
+/* Create a handle bound to `device` and `stream` (a hipStream_t; NULL = the
+ * null stream).  hbm_budget_bytes caps the workspace (0 = no cap).
+ * Returns SDC_ERR_DEVICE if the device cannot be used. */
+sdc_status_t sdc_create(sdc_handle_t* handle, int device, size_t hbm_budget_bytes, void* stream);
+
+/* Free the handle and its workspace.  NULL is accepted. */
+sdc_status_t sdc_destroy(sdc_handle_t handle);
+
+/* Human-readable name of a status code (static string). */
+const char* sdc_status_string(int status);
+
+/* Implicit repeated squaring alone (Alg. 3) on the mapped pencil of
+ * (A, B) for `region` (B == NULL means B = I).  With transpose != 0 it runs on
+ * (A^T, B^T) (the left side of Alg. 4).  Writes A_p, B_p (n x n, FP64, ld ldo)
+ * and, if R != NULL, the last R_j (n x n upper triangular, non-negative
+ * diagonal, ld ldo).  *p receives the iteration count and *rconv the last
+ * relative change ||R_j - R_{j-1}||_1/||R_{j-1}||_1.
+ * Returns SDC_OK or SDC_NOT_CONVERGED. */
+sdc_status_t sdc_irs(sdc_handle_t h, int n, const double* A, int lda, const double* B, int ldb,
+                     int transpose, sdc_region_t region, const sdc_opts_t* opts,
+                     double* Ap, double* Bp, double* R, int ldo, int* p, double* rconv);
+
+/* One split of a symmetric A with B = I (RSEP, Alg. 6, with the map of
+ * Sec. 3.3).  Q (n x n, orthogonal) and A_hat = sym(Q^T A Q) are written. */
+sdc_status_t sdc_split_sym(sdc_handle_t h, int n, const double* A, int lda, sdc_region_t region,
+                           const sdc_opts_t* opts, double* Q, int ldq, double* Ahat, int ldah,
+                           sdc_info_t* info);
+
+/* One split of a regular pencil (RGNEP, Alg. 4, with the map of Sec. 3.3).
+ * Q_L, Q_R (n x n, orthogonal), A_hat = Q_L^T A Q_R and B_hat = Q_L^T B Q_R
+ * are written; the split point minimizes ||E21||_1/||A||_1 + ||F21||_1/||B||_1. */
+sdc_status_t sdc_split_pencil(sdc_handle_t h, int n, const double* A, int lda, const double* B,
+                              int ldb, sdc_region_t region, const sdc_opts_t* opts, double* QL,
+                              int ldql, double* QR, int ldqr, double* Ahat, int ldah, double* Bhat,
+                              int ldbh, sdc_info_t* info);
+
+/* `count` independent symmetric splits of possibly different sizes, run in
+ * lockstep on the device (the problems are independent: Sec. 4.3 assigns
+ * subproblems to disjoint processor sets).  n, lda, regions, infos and the
+ * pointer arrays A, Q, Ahat are HOST arrays of length count whose elements are
+ * device pointers.  opts applies to every problem; problem i draws its
+ * Gaussians with seed opts->seed + i*1000003 so its result does not depend on
+ * the batch it runs in.  opts->G must be NULL.  statuses[i] receives problem
+ * i's status; the return value is SDC_OK unless an argument or device error
+ * occurred. */
+sdc_status_t sdc_split_sym_batched(sdc_handle_t h, int count, const int* n, const double* const* A,
+                                   const int* lda, const sdc_region_t* regions,
+                                   const sdc_opts_t* opts, double* const* Q, const int* ldq,
+                                   double* const* Ahat, const int* ldah, sdc_info_t* infos,
+                                   int* statuses);
+
+/* The Gaussian n x n matrix the library draws when opts->G is NULL:
+ * Philox4x32-10 keyed by `seed`, counter (e mod 2^32, e div 2^32, tag, 0) for
+ * the column-major element index e, then Box-Muller.  G is a device pointer. */
+sdc_status_t sdc_gaussian(sdc_handle_t h, int n, uint64_t seed, int tag, double* G, int ldg);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SDC_H_ */

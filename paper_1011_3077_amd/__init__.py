@@ -1,0 +1,209 @@
+"""Python binding of libsdc (include/sdc.h): the inverse-free spectral split
+step on MI355X (gfx950).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Matrices are torch float64 tensors on a HIP device; the library is
+column-major, so a tensor is handed over as the memory of its transpose and
+outputs are returned as transposed views of column-major buffers.
+
+If the compiled library is missing this module raises ImportError; there is
+no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsdc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} not built; run `python -m paper_1011_3077_amd.build`")
+lib = C.CDLL(LIB_PATH)
+
+SDC_OK, SDC_NOT_CONVERGED, SDC_NO_SPLIT, SDC_RANK_AMBIGUOUS = 0, 1, 2, 3
+SDC_ERR_INVALID, SDC_ERR_NOMEM, SDC_ERR_DEVICE, SDC_ERR_NONFINITE = -1, -2, -3, -4
+SDC_FP64, SDC_FP32_REFINE = 0, 1
+SDC_UNIT_DISK, SDC_DISK, SDC_HALFPLANE = 0, 1, 2
+
+EXPORTED = ["sdc_opts_default", "sdc_create", "sdc_destroy", "sdc_status_string", "sdc_irs",
+            "sdc_split_sym", "sdc_split_pencil", "sdc_split_sym_batched", "sdc_gaussian"]
+
+
+class Region(C.Structure):
+    _fields_ = [("kind", C.c_int), ("center", C.c_double), ("radius", C.c_double),
+                ("shift", C.c_double), ("scale", C.c_double)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("prec", C.c_int), ("tau", C.c_double), ("maxit", C.c_int), ("seed", C.c_uint64),
+                ("max_retries", C.c_int), ("split_tol", C.c_double), ("G", C.c_void_p),
+                ("diagnostics", C.c_int)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n", C.c_int), ("k_lead", C.c_int), ("n_inside", C.c_int), ("iters_right", C.c_int),
+                ("iters_left", C.c_int), ("attempts", C.c_int), ("refine_rounds", C.c_int),
+                ("k_rho", C.c_int), ("rconv_last", C.c_double), ("e21_rel", C.c_double),
+                ("orth_err", C.c_double), ("rank_gap", C.c_double), ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_P = C.c_void_p
+_I = C.c_int
+lib.sdc_opts_default.argtypes = [C.POINTER(Opts)]
+lib.sdc_opts_default.restype = None
+lib.sdc_create.argtypes = [C.POINTER(_P), _I, C.c_size_t, _P]
+lib.sdc_create.restype = _I
+lib.sdc_destroy.argtypes = [_P]
+lib.sdc_destroy.restype = _I
+lib.sdc_status_string.argtypes = [_I]
+lib.sdc_status_string.restype = C.c_char_p
+lib.sdc_irs.argtypes = [_P, _I, _P, _I, _P, _I, _I, Region, C.POINTER(Opts), _P, _P, _P, _I,
+                        C.POINTER(_I), C.POINTER(C.c_double)]
+lib.sdc_irs.restype = _I
+lib.sdc_split_sym.argtypes = [_P, _I, _P, _I, Region, C.POINTER(Opts), _P, _I, _P, _I, C.POINTER(Info)]
+lib.sdc_split_sym.restype = _I
+lib.sdc_split_pencil.argtypes = [_P, _I, _P, _I, _P, _I, Region, C.POINTER(Opts), _P, _I, _P, _I,
+                                 _P, _I, _P, _I, C.POINTER(Info)]
+lib.sdc_split_pencil.restype = _I
+lib.sdc_split_sym_batched.argtypes = [_P, _I, C.POINTER(_I), C.POINTER(_P), C.POINTER(_I),
+                                      C.POINTER(Region), C.POINTER(Opts), C.POINTER(_P), C.POINTER(_I),
+                                      C.POINTER(_P), C.POINTER(_I), C.POINTER(Info), C.POINTER(_I)]
+lib.sdc_split_sym_batched.restype = _I
+lib.sdc_gaussian.argtypes = [_P, _I, C.c_uint64, _I, _P, _I]
+lib.sdc_gaussian.restype = _I
+
+
+def status_string(s: int) -> str:
+    return lib.sdc_status_string(int(s)).decode()
+
+
+class SdcError(RuntimeError):
+    pass
+
+
+def _check(st: int) -> int:
+    if st < 0:
+        raise SdcError(status_string(st))
+    return st
+
+
+def region(kind: str = "unit_disk", center: float = 0.0, radius: float = 1.0, shift: float = 0.0,
+           scale: float = 1.0) -> Region:
+    k = {"unit_disk": SDC_UNIT_DISK, "disk": SDC_DISK, "halfplane": SDC_HALFPLANE}[kind]
+    return Region(k, center, radius, shift, scale)
+
+
+def opts(prec: int = SDC_FP64, tau: float = 0.0, maxit: int = 60, seed: int = 0, max_retries: int = 2,
+         split_tol: float = 1e-10, G=None, diagnostics: int = 0) -> Opts:
+    o = Opts()
+    lib.sdc_opts_default(C.byref(o))
+    o.prec, o.tau, o.maxit, o.seed = prec, tau, maxit, seed
+    o.max_retries, o.split_tol, o.diagnostics = max_retries, split_tol, diagnostics
+    o.G = None if G is None else G.data_ptr()
+    return o
+
+
+def _cm(t):
+    """Column-major device buffer of matrix t (n x n float64 torch tensor)."""
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.dim() == 2):
+        raise TypeError("expected a 2-D float64 tensor on a HIP device")
+    return t.t().contiguous()
+
+
+def _out(n, like):
+    import torch
+    return torch.empty((n, n), dtype=torch.float64, device=like.device)
+
+
+@dataclass
+class SplitResult:
+    status: int
+    info: dict
+    Q: object          # Q (symmetric) / Q_R (pencil), n x n torch tensor
+    QL: object
+    Ahat: object
+    Bhat: object
+
+
+class Handle:
+    """Owns an sdc handle bound to a device and (optionally) a torch stream."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0, stream=None):
+        import torch
+        self.device = device
+        s = stream.cuda_stream if stream is not None else torch.cuda.current_stream(device).cuda_stream
+        h = C.c_void_p()
+        _check(lib.sdc_create(C.byref(h), device, budget_bytes, C.c_void_p(s)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.sdc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- entry points (same names as the C ABI without the prefix) ---------
+    def irs(self, A, B=None, reg: Region | None = None, o: Opts | None = None, transpose: bool = False):
+        n = A.shape[0]
+        a = _cm(A)
+        b = _cm(B) if B is not None else None
+        ap, bp, r = _out(n, A), _out(n, A), _out(n, A)
+        p = C.c_int()
+        rc = C.c_double()
+        st = _check(lib.sdc_irs(self._h, n, a.data_ptr(), n, None if b is None else b.data_ptr(), n,
+                                int(transpose), reg or region(), C.byref(o or opts()), ap.data_ptr(),
+                                bp.data_ptr(), r.data_ptr(), n, C.byref(p), C.byref(rc)))
+        return st, ap.t(), bp.t(), r.t(), p.value, rc.value
+
+    def split_sym(self, A, reg: Region | None = None, o: Opts | None = None) -> SplitResult:
+        n = A.shape[0]
+        a = _cm(A)
+        q, ah = _out(n, A), _out(n, A)
+        info = Info()
+        st = _check(lib.sdc_split_sym(self._h, n, a.data_ptr(), n, reg or region(), C.byref(o or opts()),
+                                      q.data_ptr(), n, ah.data_ptr(), n, C.byref(info)))
+        return SplitResult(st, info.as_dict(), q.t(), None, ah.t(), None)
+
+    def split_pencil(self, A, B, reg: Region | None = None, o: Opts | None = None) -> SplitResult:
+        n = A.shape[0]
+        a, b = _cm(A), _cm(B)
+        ql, qr, ah, bh = _out(n, A), _out(n, A), _out(n, A), _out(n, A)
+        info = Info()
+        st = _check(lib.sdc_split_pencil(self._h, n, a.data_ptr(), n, b.data_ptr(), n, reg or region(),
+                                         C.byref(o or opts()), ql.data_ptr(), n, qr.data_ptr(), n,
+                                         ah.data_ptr(), n, bh.data_ptr(), n, C.byref(info)))
+        return SplitResult(st, info.as_dict(), qr.t(), ql.t(), ah.t(), bh.t())
+
+    def split_sym_batched(self, As, regs, o: Opts | None = None):
+        cnt = len(As)
+        cms = [_cm(a) for a in As]
+        outs_q = [_out(a.shape[0], a) for a in As]
+        outs_a = [_out(a.shape[0], a) for a in As]
+        ns = (_I * cnt)(*[a.shape[0] for a in As])
+        ptr_a = (_P * cnt)(*[c.data_ptr() for c in cms])
+        ptr_q = (_P * cnt)(*[q.data_ptr() for q in outs_q])
+        ptr_h = (_P * cnt)(*[q.data_ptr() for q in outs_a])
+        rg = (Region * cnt)(*regs)
+        infos = (Info * cnt)()
+        sts = (_I * cnt)()
+        _check(lib.sdc_split_sym_batched(self._h, cnt, ns, ptr_a, ns, rg, C.byref(o or opts()), ptr_q, ns,
+                                         ptr_h, ns, infos, sts))
+        return [SplitResult(sts[i], infos[i].as_dict(), outs_q[i].t(), None, outs_a[i].t(), None)
+                for i in range(cnt)]
+
+    def gaussian(self, n: int, seed: int, tag: int):
+        import torch
+        g = torch.empty((n, n), dtype=torch.float64, device=f"cuda:{self.device}")
+        _check(lib.sdc_gaussian(self._h, n, seed, tag, g.data_ptr(), n))
+        return g.t()

@@ -1,0 +1,481 @@
+// Supporting kernels of the split step on gfx950: batched MFMA GEMM, the
+// repeated-squaring set-up and per-iteration epilogue, element-wise
+// permutations (transposes, reversals J, sign fixes), norms, the split-point
+// search and the counter-based Gaussian draw.  Every kernel takes an array of
+// per-problem descriptors and uses blockIdx.z (or .y) as the problem index,
+// so independent problems of different sizes share one launch.
+#include "sdc_internal.hpp"
+#include "sdc_aux.hpp"
+#include "mfma.hpp"
+
+namespace sdc {
+
+// ---------------------------------------------------------------------------
+// Reductions (256-thread blocks, wave64)
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+__device__ inline double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    return v;
+}
+// Result valid in thread 0.
+__device__ inline double block_sum256(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double r = 0;
+    if (threadIdx.x == 0) r = sh[0] + sh[1] + sh[2] + sh[3];
+    return r;
+}
+// Non-negative doubles order like their bit patterns (NaN after +inf).
+__device__ inline void atomic_max_nonneg(double* addr, double v) {
+    atomicMax(reinterpret_cast<unsigned long long*>(addr), (unsigned long long)__double_as_longlong(v));
+}
+
+// ---------------------------------------------------------------------------
+// Batched GEMM on the matrix cores: 64x64 output tile per 256-thread block,
+// 2x2 waves of 32x32, K staged through LDS in chunks of 16.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm(const GemmDesc<T>* __restrict__ descs) {
+    using M = Mfma<T>;
+    typedef typename M::v4 v4;
+    const GemmDesc<T> d = descs[blockIdx.z];
+    if (!d.active) return;
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    if (m0 >= d.M || n0 >= d.N) return;
+    __shared__ T sA[16][64 + 4];
+    __shared__ T sB[16][64 + 4];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, gq = lane >> 4, ln = lane & 15;
+    const int wm = wave >> 1, wn = wave & 1;
+    v4 acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4{0, 0, 0, 0};
+    for (int k0 = 0; k0 < d.K; k0 += 16) {
+        for (int e = tid; e < 1024; e += 256) {
+            int m, k;
+            T va = 0;
+            if (!d.ta) {
+                m = e & 63; k = e >> 6;
+                if (m0 + m < d.M && k0 + k < d.K) va = d.A[(size_t)(k0 + k) * d.lda + m0 + m];
+            } else {
+                k = e & 15; m = e >> 4;
+                if (m0 + m < d.M && k0 + k < d.K) va = d.A[(size_t)(m0 + m) * d.lda + k0 + k];
+            }
+            sA[k][m] = va;
+            int n;
+            T vb = 0;
+            if (!d.tb) {
+                k = e & 15; n = e >> 4;
+                if (n0 + n < d.N && k0 + k < d.K) vb = d.B[(size_t)(n0 + n) * d.ldb + k0 + k];
+            } else {
+                n = e & 63; k = e >> 6;
+                if (n0 + n < d.N && k0 + k < d.K) vb = d.B[(size_t)(k0 + k) * d.ldb + n0 + n];
+            }
+            sB[k][n] = vb;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const T a0 = sA[kk * 4 + gq][wm * 32 + ln];
+            const T a1 = sA[kk * 4 + gq][wm * 32 + 16 + ln];
+            const T b0 = sB[kk * 4 + gq][wn * 32 + ln];
+            const T b1 = sB[kk * 4 + gq][wn * 32 + 16 + ln];
+            acc[0][0] = M::mma(a0, b0, acc[0][0]);
+            acc[0][1] = M::mma(a0, b1, acc[0][1]);
+            acc[1][0] = M::mma(a1, b0, acc[1][0]);
+            acc[1][1] = M::mma(a1, b1, acc[1][1]);
+        }
+        __syncthreads();
+    }
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            const int n = n0 + wn * 32 + j * 16 + ln;
+            if (n >= d.N) continue;
+            for (int v = 0; v < 4; ++v) {
+                const int m = m0 + wm * 32 + i * 16 + gq * 4 + v;
+                if (m >= d.M) continue;
+                T* cp = d.C + (size_t)n * d.ldc + m;
+                T r = d.alpha * acc[i][j][v];
+                if (d.beta != T(0)) r += d.beta * *cp;
+                *cp = r;
+            }
+        }
+}
+
+template <typename T>
+void gemm_batch(const GemmDesc<T>* d_descs, const GemmDesc<T>* h, int count, hipStream_t s) {
+    int M = 0, N = 0;
+    for (int i = 0; i < count; ++i)
+        if (h[i].active) {
+            M = M > h[i].M ? M : h[i].M;
+            N = N > h[i].N ? N : h[i].N;
+        }
+    if (M == 0 || N == 0) return;
+    hipLaunchKernelGGL(k_gemm<T>, dim3((N + 63) / 64, (M + 63) / 64, count), dim3(256), 0, s, d_descs);
+}
+template void gemm_batch<double>(const GemmDesc<double>*, const GemmDesc<double>*, int, hipStream_t);
+template void gemm_batch<float>(const GemmDesc<float>*, const GemmDesc<float>*, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Repeated squaring: set-up of W = [B0 A0 0; -A0 0 B0] (2n x 3n, ld 2n) from
+// the FP64 inputs and the region map, and the per-iteration epilogue.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_irs_init(const IrsInit<T>* __restrict__ descs) {
+    const IrsInit<T> d = descs[blockIdx.z];
+    const int n = d.n;
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= n || j >= n) return;
+    const double a = d.trans ? d.A[(size_t)i * d.lda + j] : d.A[(size_t)j * d.lda + i];
+    double b;
+    if (d.B) b = d.trans ? d.B[(size_t)i * d.ldb + j] : d.B[(size_t)j * d.ldb + i];
+    else b = (i == j) ? 1.0 : 0.0;
+    const T a0 = (T)(d.a1 * a + d.a2 * b);
+    const T b0 = (T)(d.b1 * a + d.b2 * b);
+    const size_t ld = 2 * (size_t)n;
+    T* W = d.W;
+    W[(size_t)j * ld + i] = b0;
+    W[(size_t)j * ld + n + i] = -a0;
+    W[(size_t)(n + j) * ld + i] = a0;
+    W[(size_t)(n + j) * ld + n + i] = T(0);
+    W[(size_t)(2 * n + j) * ld + i] = T(0);
+    W[(size_t)(2 * n + j) * ld + n + i] = b0;
+}
+
+template <typename T>
+void irs_init_batch(const IrsInit<T>* d, const IrsInit<T>* h, int count, hipStream_t s) {
+    int n = 0;
+    for (int i = 0; i < count; ++i) n = n > h[i].n ? n : h[i].n;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_irs_init<T>, dim3((n + 63) / 64, (n + 3) / 4, count), dim3(256), 0, s, d);
+}
+template void irs_init_batch<double>(const IrsInit<double>*, const IrsInit<double>*, int, hipStream_t);
+template void irs_init_batch<float>(const IrsInit<float>*, const IrsInit<float>*, int, hipStream_t);
+
+// One block per column j.  After the augmented QR, rows [0, n) of the first
+// block column hold R_j (diagonal as produced) and rows [n, 2n) of the second
+// and third block columns hold A_{j+1} and B_{j+1}.  This kernel
+//   * normalizes R_j to a non-negative diagonal (rows times sign(R_ii)),
+//   * accumulates max column sums of |R_j - R_{j-1}|, |R_{j-1}| and |R_j|
+//     in FP64 (the stopping test of Alg. 3, whatever the iterate precision),
+//   * stores R_j as the next R_{j-1},
+//   * rewrites W in place as [B_{j+1} A_{j+1} 0; -A_{j+1} 0 B_{j+1}].
+template <typename T>
+__global__ __launch_bounds__(256) void k_irs_post(const IrsDesc<T>* __restrict__ descs) {
+    __shared__ double sh[4];
+    const IrsDesc<T> d = descs[blockIdx.y];
+    if (!d.active) return;
+    const int n = d.n, j = blockIdx.x;
+    if (j >= n) return;
+    const size_t ld = 2 * (size_t)n;
+    T* W = d.W;
+    double diff = 0, ref = 0, cur = 0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        double r = 0;
+        if (i <= j) {
+            r = (double)W[(size_t)j * ld + i];
+            if (d.diag[i] < T(0)) r = -r;
+        }
+        const double rp = d.Rprev[(size_t)j * n + i];
+        diff += fabs(r - rp);
+        ref += fabs(rp);
+        cur += fabs(r);
+        d.Rprev[(size_t)j * n + i] = r;
+        const T ap = W[(size_t)(n + j) * ld + n + i];
+        const T bp = W[(size_t)(2 * n + j) * ld + n + i];
+        W[(size_t)j * ld + i] = bp;
+        W[(size_t)j * ld + n + i] = -ap;
+        W[(size_t)(n + j) * ld + i] = ap;
+        W[(size_t)(n + j) * ld + n + i] = T(0);
+        W[(size_t)(2 * n + j) * ld + i] = T(0);
+    }
+    diff = block_sum256(diff, sh);
+    ref = block_sum256(ref, sh);
+    cur = block_sum256(cur, sh);
+    if (threadIdx.x == 0) {
+        atomic_max_nonneg(&d.norms[0], diff);
+        atomic_max_nonneg(&d.norms[1], ref);
+        atomic_max_nonneg(&d.norms[2], cur);
+    }
+}
+
+template <typename T>
+void irs_post_batch(const IrsDesc<T>* d, const IrsDesc<T>* h, int count, int /*first*/, hipStream_t s) {
+    int n = 0;
+    for (int i = 0; i < count; ++i)
+        if (h[i].active) n = n > h[i].n ? n : h[i].n;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_irs_post<T>, dim3(n, count), dim3(256), 0, s, d);
+}
+template void irs_post_batch<double>(const IrsDesc<double>*, const IrsDesc<double>*, int, int, hipStream_t);
+template void irs_post_batch<float>(const IrsDesc<float>*, const IrsDesc<float>*, int, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Element-wise n x n operations.
+// ---------------------------------------------------------------------------
+// out[i + j ldo] = alpha * sgn * in[p + q ldi] with (p, q) = trans ? (j, i) : (i, j),
+// then p -> n-1-p if revP and q -> n-1-q if revQ; sgn = sign(sg[p]) if sg.
+// EW_ADD: out = in + in2.  EW_IDENTITY: out = I.  EW_SYM: out = (in + in^T)/2.
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(256) void k_ew(const EwDesc* __restrict__ descs) {
+    const EwDesc d = descs[blockIdx.z];
+    const int n = d.n;
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (!d.active || i >= d.rows || j >= n) return;
+    const Tin* in = static_cast<const Tin*>(d.in);
+    Tout* out = static_cast<Tout*>(d.out);
+    Tout r;
+    switch (d.op) {
+    case EW_PERMUTE: {
+        int p = d.trans ? j : i, q = d.trans ? i : j;
+        if (d.revP) p = (d.trans ? n : d.rows) - 1 - p;
+        if (d.revQ) q = (d.trans ? d.rows : n) - 1 - q;
+        double v = (double)in[(size_t)q * d.ldi + p];
+        if (d.sg && d.sg[p] < 0) v = -v;
+        r = (Tout)(d.alpha * v);
+        break;
+    }
+    case EW_ADD: {
+        const Tin* in2 = static_cast<const Tin*>(d.in2);
+        r = (Tout)((double)in[(size_t)j * d.ldi + i] + (double)in2[(size_t)j * d.ld2 + i]);
+        break;
+    }
+    case EW_IDENTITY:
+        r = (i == j) ? Tout(1) : Tout(0);
+        break;
+    default: {  // EW_SYM
+        r = (Tout)(0.5 * ((double)in[(size_t)j * d.ldi + i] + (double)in[(size_t)i * d.ldi + j]));
+        break;
+    }
+    }
+    out[(size_t)j * d.ldo + i] = r;
+}
+
+template <typename Tin, typename Tout>
+void ew_batch(const EwDesc* d, const EwDesc* h, int count, hipStream_t s) {
+    int n = 0, rows = 0;
+    for (int i = 0; i < count; ++i)
+        if (h[i].active) {
+            n = n > h[i].n ? n : h[i].n;
+            rows = rows > h[i].rows ? rows : h[i].rows;
+        }
+    if (n == 0 || rows == 0) return;
+    hipLaunchKernelGGL((k_ew<Tin, Tout>), dim3((rows + 63) / 64, (n + 3) / 4, count), dim3(256), 0, s, d);
+}
+template void ew_batch<double, double>(const EwDesc*, const EwDesc*, int, hipStream_t);
+template void ew_batch<float, double>(const EwDesc*, const EwDesc*, int, hipStream_t);
+template void ew_batch<float, float>(const EwDesc*, const EwDesc*, int, hipStream_t);
+
+// Fill a device array (used instead of memset so the calls stay capturable).
+template <typename T>
+__global__ void k_fill(T* p, size_t n, T v) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+template <typename T>
+void fill(T* p, size_t n, T v, hipStream_t s) {
+    if (n == 0) return;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+}
+template void fill<double>(double*, size_t, double, hipStream_t);
+template void fill<float>(float*, size_t, float, hipStream_t);
+template void fill<unsigned>(unsigned*, size_t, unsigned, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Norms and the split-point search (Alg. 4 line 5; the prefix-sum plus max
+// reduction of Sec. 4.2).
+// ---------------------------------------------------------------------------
+// out[0] = max_j sum_i |X_ij| (matrix 1-norm), one block per column.
+__global__ __launch_bounds__(256) void k_norm1(const NormDesc* __restrict__ descs) {
+    __shared__ double sh[4];
+    const NormDesc d = descs[blockIdx.y];
+    if (!d.active || (int)blockIdx.x >= d.n) return;
+    const int j = blockIdx.x;
+    double s = 0;
+    for (int i = threadIdx.x; i < d.rows; i += 256) s += fabs(d.X[(size_t)j * d.ld + i]);
+    s = block_sum256(s, sh);
+    if (threadIdx.x == 0) atomic_max_nonneg(d.out, s);
+}
+void norm1_batch(const NormDesc* d, const NormDesc* h, int count, hipStream_t s) {
+    int n = 0;
+    for (int i = 0; i < count; ++i)
+        if (h[i].active) n = n > h[i].n ? n : h[i].n;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_norm1, dim3(n, count), dim3(256), 0, s, d);
+}
+
+// Column suffix sums: S[k + c n] = sum_{i >= k} |X_ic| (one block per column c).
+__global__ __launch_bounds__(256) void k_suffix(const SplitDesc* __restrict__ descs, int which) {
+    __shared__ double part[256];
+    const SplitDesc d = descs[blockIdx.y];
+    const int n = d.n, c = blockIdx.x;
+    if (!d.active || c >= n) return;
+    const double* X = which ? d.Bh : d.Ah;
+    const int ldx = which ? d.ldb : d.lda;
+    if (!X) return;
+    double* S = (which ? d.SB : d.SA) + (size_t)c * n;
+    const int chunk = (n + 255) / 256;
+    const int lo = threadIdx.x * chunk, hi = min(n, lo + chunk);
+    double s = 0;
+    for (int i = lo; i < hi; ++i) s += fabs(X[(size_t)c * ldx + i]);
+    part[threadIdx.x] = s;
+    __syncthreads();
+    // suffix offset of this chunk: sum of later chunks
+    double off = 0;
+    for (int t = threadIdx.x + 1; t < 256; ++t) off += part[t];
+    double run = off;
+    for (int i = hi - 1; i >= lo; --i) {
+        run += fabs(X[(size_t)c * ldx + i]);
+        S[i] = run;
+    }
+}
+
+// e[k] = max_{c<k} SA[k + c n]/normA (+ max_{c<k} SB[k + c n]/normB), k = 1..n-1.
+__global__ __launch_bounds__(256) void k_emax(const SplitDesc* __restrict__ descs) {
+    const SplitDesc d = descs[blockIdx.y];
+    const int n = d.n;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (!d.active || k < 1 || k >= n) return;
+    double ea = 0, eb = 0;
+    for (int c = 0; c < k; ++c) ea = fmax(ea, d.SA[(size_t)c * n + k]);
+    double e = ea / d.norms[0];
+    if (d.Bh) {
+        for (int c = 0; c < k; ++c) eb = fmax(eb, d.SB[(size_t)c * n + k]);
+        e += eb / d.norms[1];
+    }
+    d.e[k] = e;
+}
+
+// argmin over k = 1..n-1 (smallest k on ties); out[0] = k*, out[1] = e(k*).
+__global__ __launch_bounds__(256) void k_argmin(const SplitDesc* __restrict__ descs) {
+    __shared__ double sv[256];
+    __shared__ int sk[256];
+    const SplitDesc d = descs[blockIdx.x];
+    if (!d.active) return;
+    double best = INFINITY;
+    int bk = 0;
+    for (int k = 1 + threadIdx.x; k < d.n; k += 256) {
+        const double v = d.e[k];
+        if (bk == 0 || v < best || best != best) {  // k increases: ties keep the first
+            best = v;
+            bk = k;
+        }
+    }
+    sv[threadIdx.x] = best;
+    sk[threadIdx.x] = bk;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            const double v2 = sv[threadIdx.x + o];
+            const int k2 = sk[threadIdx.x + o];
+            const double v1 = sv[threadIdx.x];
+            const int k1 = sk[threadIdx.x];
+            bool take = false;
+            if (k2 != 0) {
+                if (k1 == 0) take = true;
+                else if (v2 < v1) take = true;
+                else if (v2 == v1 && k2 < k1) take = true;
+                else if (v1 != v1 && v2 == v2) take = true;  // prefer a number over NaN
+            }
+            if (take) { sv[threadIdx.x] = v2; sk[threadIdx.x] = k2; }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        d.out[0] = (double)sk[0];
+        d.out[1] = sv[0];
+    }
+}
+
+void split_search_batch(const SplitDesc* d, const SplitDesc* h, int count, hipStream_t s) {
+    int n = 0, pencil = 0;
+    for (int i = 0; i < count; ++i)
+        if (h[i].active) {
+            n = n > h[i].n ? n : h[i].n;
+            pencil |= h[i].Bh != nullptr;
+        }
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_suffix, dim3(n, count), dim3(256), 0, s, d, 0);
+    if (pencil) hipLaunchKernelGGL(k_suffix, dim3(n, count), dim3(256), 0, s, d, 1);
+    hipLaunchKernelGGL(k_emax, dim3((n + 255) / 256, count), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(k_argmin, dim3(count), dim3(256), 0, s, d);
+}
+
+// ||X^T X - I||_F^2 accumulated into out (X n x n), one block per column of E.
+__global__ __launch_bounds__(256) void k_orth_err(const NormDesc* __restrict__ descs) {
+    __shared__ double sh[4];
+    const NormDesc d = descs[blockIdx.y];
+    if (!d.active || (int)blockIdx.x >= d.n) return;
+    const int j = blockIdx.x;
+    double s = 0;
+    for (int i = threadIdx.x; i < d.n; i += 256) {
+        const double e = d.X[(size_t)j * d.ld + i] - (i == j ? 1.0 : 0.0);
+        s += e * e;
+    }
+    s = block_sum256(s, sh);
+    if (threadIdx.x == 0) atomicAdd(d.out, s);
+}
+void orth_err_batch(const NormDesc* d, const NormDesc* h, int count, hipStream_t s) {
+    int n = 0;
+    for (int i = 0; i < count; ++i)
+        if (h[i].active) n = n > h[i].n ? n : h[i].n;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_orth_err, dim3(n, count), dim3(256), 0, s, d);
+}
+
+// ---------------------------------------------------------------------------
+// Gaussian draw: Philox4x32-10 (Salmon et al., SC'11) + Box-Muller.
+// ---------------------------------------------------------------------------
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gauss(const GaussDesc* __restrict__ descs) {
+    const GaussDesc d = descs[blockIdx.z];
+    const int n = d.n;
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (!d.active || i >= n || j >= n) return;
+    const uint64_t e = (uint64_t)i + (uint64_t)j * (uint64_t)n;
+    uint32_t c[4] = {(uint32_t)e, (uint32_t)(e >> 32), (uint32_t)d.tag, 0u};
+    philox4x32_10(c, (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
+    const uint64_t x1 = (((uint64_t)c[1] << 32) | c[0]) >> 11;
+    const uint64_t x2 = (((uint64_t)c[3] << 32) | c[2]) >> 11;
+    const double u1 = ((double)x1 + 0.5) * 0x1.0p-53;
+    const double u2 = (double)x2 * 0x1.0p-53;
+    d.G[(size_t)j * d.ld + i] = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+}
+void gauss_batch(const GaussDesc* d, const GaussDesc* h, int count, hipStream_t s) {
+    int n = 0;
+    for (int i = 0; i < count; ++i)
+        if (h[i].active) n = n > h[i].n ? n : h[i].n;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_gauss, dim3((n + 63) / 64, (n + 3) / 4, count), dim3(256), 0, s, d);
+}
+
+}  // namespace sdc

@@ -1,0 +1,205 @@
+// C ABI entry points (include/sdc.h): argument checks, handle management,
+// and translation to the engine's jobs.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "engine.hpp"
+#include "sdc.h"
+
+using sdc::Handle;
+using sdc::SplitJob;
+
+struct sdc_handle_s {
+    Handle h;
+};
+
+namespace {
+
+// Largest order the tree QR supports: 2n rows give at most 128 leaves.
+constexpr int kMaxN = 16384;
+
+bool region_ok(const sdc_region_t& r) {
+    if (r.kind == SDC_UNIT_DISK) return true;
+    if (r.kind == SDC_DISK) return std::isfinite(r.center) && std::isfinite(r.radius) && r.radius > 0;
+    if (r.kind == SDC_HALFPLANE) return std::isfinite(r.shift) && std::isfinite(r.scale) && r.scale >= 0;
+    return false;
+}
+
+int use_device(Handle& h) {
+    return hipSetDevice(h.device) == hipSuccess ? SDC_OK : SDC_ERR_DEVICE;
+}
+
+sdc_opts_t resolve(const sdc_opts_t* o) {
+    sdc_opts_t r;
+    if (o) r = *o;
+    else sdc_opts_default(&r);
+    return r;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sdc_opts_default(sdc_opts_t* o) {
+    if (!o) return;
+    o->prec = SDC_FP64;
+    o->tau = 0.0;
+    o->maxit = 60;
+    o->seed = 0;
+    o->max_retries = 2;
+    o->split_tol = 1e-10;
+    o->G = nullptr;
+    o->diagnostics = 0;
+}
+
+const char* sdc_status_string(int s) {
+    switch (s) {
+    case SDC_OK: return "SDC_OK";
+    case SDC_NOT_CONVERGED: return "SDC_NOT_CONVERGED";
+    case SDC_NO_SPLIT: return "SDC_NO_SPLIT";
+    case SDC_RANK_AMBIGUOUS: return "SDC_RANK_AMBIGUOUS";
+    case SDC_ERR_INVALID: return "SDC_ERR_INVALID";
+    case SDC_ERR_NOMEM: return "SDC_ERR_NOMEM";
+    case SDC_ERR_DEVICE: return "SDC_ERR_DEVICE";
+    case SDC_ERR_NONFINITE: return "SDC_ERR_NONFINITE";
+    default: return "SDC_UNKNOWN";
+    }
+}
+
+sdc_status_t sdc_create(sdc_handle_t* handle, int device, size_t budget, void* stream) {
+    if (!handle) return SDC_ERR_INVALID;
+    *handle = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return SDC_ERR_DEVICE;
+    sdc_handle_s* p = new (std::nothrow) sdc_handle_s;
+    if (!p) return SDC_ERR_NOMEM;
+    p->h.device = device;
+    p->h.stream = static_cast<hipStream_t>(stream);
+    p->h.budget = budget;
+    if (use_device(p->h) != SDC_OK) {
+        delete p;
+        return SDC_ERR_DEVICE;
+    }
+    *handle = p;
+    return SDC_OK;
+}
+
+sdc_status_t sdc_destroy(sdc_handle_t handle) {
+    if (!handle) return SDC_OK;
+    Handle& h = handle->h;
+    (void)hipSetDevice(h.device);
+    (void)hipStreamSynchronize(h.stream);
+    if (h.ws) (void)hipFree(h.ws);
+    if (h.desc_d) (void)hipFree(h.desc_d);
+    if (h.desc_h) (void)hipHostFree(h.desc_h);
+    if (h.host) (void)hipHostFree(h.host);
+    delete handle;
+    return SDC_OK;
+}
+
+sdc_status_t sdc_irs(sdc_handle_t hd, int n, const double* A, int lda, const double* B, int ldb, int transpose,
+                     sdc_region_t region, const sdc_opts_t* opts, double* Ap, double* Bp, double* R, int ldo,
+                     int* p, double* rconv) {
+    if (!hd || n < 1 || n > kMaxN || !A || lda < n || (B && ldb < n) || !Ap || !Bp || ldo < n || !p || !rconv ||
+        !region_ok(region))
+        return SDC_ERR_INVALID;
+    Handle& h = hd->h;
+    if (use_device(h) != SDC_OK) return SDC_ERR_DEVICE;
+    const sdc_opts_t o = resolve(opts);
+    return (sdc_status_t)sdc::run_irs_only(h, n, A, lda, B, ldb, transpose ? 1 : 0, region, o, Ap, Bp, R, ldo, p,
+                                           rconv);
+}
+
+sdc_status_t sdc_split_sym(sdc_handle_t hd, int n, const double* A, int lda, sdc_region_t region,
+                           const sdc_opts_t* opts, double* Q, int ldq, double* Ahat, int ldah, sdc_info_t* info) {
+    if (!hd || n < 0 || n > kMaxN || (n > 0 && (!A || !Q || !Ahat)) || lda < n || ldq < n || ldah < n || !region_ok(region))
+        return SDC_ERR_INVALID;
+    sdc_info_t dummy;
+    if (!info) info = &dummy;
+    *info = sdc_info_t{};
+    if (n == 0) return SDC_OK;
+    Handle& h = hd->h;
+    if (use_device(h) != SDC_OK) return SDC_ERR_DEVICE;
+    std::vector<SplitJob> jobs(1);
+    SplitJob& j = jobs[0];
+    j.n = n; j.pencil = false; j.A = A; j.lda = lda; j.region = region; j.opts = resolve(opts);
+    j.Q = Q; j.ldq = ldq; j.Ahat = Ahat; j.ldah = ldah;
+    const int r = sdc::run_split_jobs(h, jobs);
+    if (r < 0) return (sdc_status_t)r;
+    *info = j.info;
+    return (sdc_status_t)j.status;
+}
+
+sdc_status_t sdc_split_pencil(sdc_handle_t hd, int n, const double* A, int lda, const double* B, int ldb,
+                              sdc_region_t region, const sdc_opts_t* opts, double* QL, int ldql, double* QR,
+                              int ldqr, double* Ahat, int ldah, double* Bhat, int ldbh, sdc_info_t* info) {
+    if (!hd || n < 0 || n > kMaxN || (n > 0 && (!A || !B || !QL || !QR || !Ahat || !Bhat)) || lda < n || ldb < n ||
+        ldql < n || ldqr < n || ldah < n || ldbh < n || !region_ok(region))
+        return SDC_ERR_INVALID;
+    sdc_info_t dummy;
+    if (!info) info = &dummy;
+    *info = sdc_info_t{};
+    if (n == 0) return SDC_OK;
+    Handle& h = hd->h;
+    if (use_device(h) != SDC_OK) return SDC_ERR_DEVICE;
+    std::vector<SplitJob> jobs(1);
+    SplitJob& j = jobs[0];
+    j.n = n; j.pencil = true; j.A = A; j.lda = lda; j.B = B; j.ldb = ldb; j.region = region;
+    j.opts = resolve(opts);
+    j.Q = QR; j.ldq = ldqr; j.QL = QL; j.ldql = ldql; j.Ahat = Ahat; j.ldah = ldah; j.Bhat = Bhat; j.ldbh = ldbh;
+    const int r = sdc::run_split_jobs(h, jobs);
+    if (r < 0) return (sdc_status_t)r;
+    *info = j.info;
+    return (sdc_status_t)j.status;
+}
+
+sdc_status_t sdc_split_sym_batched(sdc_handle_t hd, int count, const int* n, const double* const* A,
+                                   const int* lda, const sdc_region_t* regions, const sdc_opts_t* opts,
+                                   double* const* Q, const int* ldq, double* const* Ahat, const int* ldah,
+                                   sdc_info_t* infos, int* statuses) {
+    if (!hd || count < 0) return SDC_ERR_INVALID;
+    if (count == 0) return SDC_OK;
+    if (!n || !A || !lda || !regions || !Q || !ldq || !Ahat || !ldah || !statuses) return SDC_ERR_INVALID;
+    const sdc_opts_t o = resolve(opts);
+    if (o.G) return SDC_ERR_INVALID;
+    std::vector<SplitJob> jobs;
+    std::vector<int> idx;
+    for (int i = 0; i < count; ++i) {
+        if (n[i] < 0 || n[i] > kMaxN || lda[i] < n[i] || ldq[i] < n[i] || ldah[i] < n[i] || !region_ok(regions[i]))
+            return SDC_ERR_INVALID;
+        if (n[i] > 0 && (!A[i] || !Q[i] || !Ahat[i])) return SDC_ERR_INVALID;
+    }
+    for (int i = 0; i < count; ++i) {
+        if (infos) infos[i] = sdc_info_t{};
+        statuses[i] = SDC_OK;
+        if (n[i] == 0) continue;
+        SplitJob j;
+        j.n = n[i]; j.pencil = false; j.A = A[i]; j.lda = lda[i]; j.region = regions[i]; j.opts = o;
+        j.opts.seed = o.seed + (uint64_t)i * 1000003ull;
+        j.Q = Q[i]; j.ldq = ldq[i]; j.Ahat = Ahat[i]; j.ldah = ldah[i];
+        jobs.push_back(j);
+        idx.push_back(i);
+    }
+    Handle& h = hd->h;
+    if (use_device(h) != SDC_OK) return SDC_ERR_DEVICE;
+    const int r = sdc::run_split_jobs(h, jobs);
+    if (r < 0) return (sdc_status_t)r;
+    for (size_t q = 0; q < jobs.size(); ++q) {
+        statuses[idx[q]] = jobs[q].status;
+        if (infos) infos[idx[q]] = jobs[q].info;
+    }
+    return SDC_OK;
+}
+
+sdc_status_t sdc_gaussian(sdc_handle_t hd, int n, uint64_t seed, int tag, double* G, int ldg) {
+    if (!hd || n < 0 || (n > 0 && !G) || ldg < n) return SDC_ERR_INVALID;
+    if (n == 0) return SDC_OK;
+    Handle& h = hd->h;
+    if (use_device(h) != SDC_OK) return SDC_ERR_DEVICE;
+    return (sdc_status_t)sdc::run_gaussian(h, n, seed, tag, G, ldg);
+}
+
+}  // extern "C"

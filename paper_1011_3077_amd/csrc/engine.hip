@@ -1,0 +1,908 @@
+// Host orchestration of the split step (Alg. 3 IRS -> Alg. 2/1 GRURV ->
+// Alg. 4/6 block form and split point) for a batch of independent problems.
+//
+// All problems of a call advance in lockstep: each IRS iteration is one
+// augmented-QR pass plus one epilogue launch for every still-active side, and
+// one 8-byte-per-side device-to-host copy feeds the FP64 stopping test.  The
+// rank-revealing factorization, block form and split search are likewise
+// batched.  Decisions that need the whole problem (rank from the GRURV
+// diagonals, accept/retry) are taken on the host from a few numbers.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+#include "engine.hpp"
+#include "sdc_aux.hpp"
+#include "sdc_internal.hpp"
+
+namespace sdc {
+
+#define HIPCHK(x)                                   \
+    do {                                            \
+        hipError_t e_ = (x);                        \
+        if (e_ != hipSuccess) return SDC_ERR_DEVICE; \
+    } while (0)
+#define CHK(x)                 \
+    do {                       \
+        int r_ = (x);          \
+        if (r_ < 0) return r_; \
+    } while (0)
+
+static constexpr double kRhoOneSide = 1e-3;  // see rank_from_rho
+
+// ---------------------------------------------------------------------------
+// Workspace and staging
+// ---------------------------------------------------------------------------
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(char* b) : base(b) {}
+    template <class T> T* take(size_t n) {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += n * sizeof(T);
+        return p;
+    }
+};
+
+static int ensure_ws(Handle& h, size_t bytes) {
+    if (h.budget && bytes > h.budget) return SDC_ERR_NOMEM;
+    if (bytes <= h.ws_size) return SDC_OK;
+    if (h.ws) {
+        HIPCHK(hipStreamSynchronize(h.stream));
+        HIPCHK(hipFree(h.ws));
+        h.ws = nullptr;
+        h.ws_size = 0;
+    }
+    size_t sz = bytes + bytes / 8 + (1 << 20);
+    if (h.budget && sz > h.budget) sz = bytes;
+    if (hipMalloc(&h.ws, sz) != hipSuccess) {
+        h.ws = nullptr;
+        (void)hipGetLastError();
+        return SDC_ERR_NOMEM;
+    }
+    h.ws_size = sz;
+    return SDC_OK;
+}
+
+static int ensure_desc(Handle& h, size_t bytes) {
+    if (bytes <= h.desc_size) return SDC_OK;
+    if (h.desc_d) {
+        HIPCHK(hipStreamSynchronize(h.stream));
+        HIPCHK(hipFree(h.desc_d));
+        HIPCHK(hipHostFree(h.desc_h));
+        h.desc_d = h.desc_h = nullptr;
+    }
+    if (hipMalloc(&h.desc_d, bytes) != hipSuccess) return SDC_ERR_NOMEM;
+    if (hipHostMalloc(&h.desc_h, bytes, hipHostMallocDefault) != hipSuccess) return SDC_ERR_NOMEM;
+    h.desc_size = bytes;
+    h.desc_off = 0;
+    return SDC_OK;
+}
+
+static int ensure_host(Handle& h, size_t bytes) {
+    if (bytes <= h.host_size) return SDC_OK;
+    if (h.host) {
+        HIPCHK(hipStreamSynchronize(h.stream));
+        HIPCHK(hipHostFree(h.host));
+        h.host = nullptr;
+    }
+    if (hipHostMalloc(&h.host, bytes, hipHostMallocDefault) != hipSuccess) return SDC_ERR_NOMEM;
+    h.host_size = bytes;
+    return SDC_OK;
+}
+
+// Copy a host array of descriptors to the device arena (pinned staging; the
+// arena is rewound only after a stream synchronization).
+template <class T> static const T* upload(Handle& h, const std::vector<T>& v) {
+    const size_t bytes = v.size() * sizeof(T);
+    size_t off = (h.desc_off + 255) & ~size_t(255);
+    if (off + bytes > h.desc_size) return nullptr;
+    std::memcpy(h.desc_h + off, v.data(), bytes);
+    if (hipMemcpyAsync(h.desc_d + off, h.desc_h + off, bytes, hipMemcpyHostToDevice, h.stream) != hipSuccess)
+        return nullptr;
+    h.desc_off = off + bytes;
+    return reinterpret_cast<const T*>(h.desc_d + off);
+}
+#define UPLOAD(ptr, vec)                                   \
+    auto ptr = upload(h, vec);                             \
+    if (!ptr) return SDC_ERR_DEVICE;
+
+// ---------------------------------------------------------------------------
+// Region map (Sec. 3.3): A0 = a1 A + a2 B, B0 = b1 A + b2 B.
+// ---------------------------------------------------------------------------
+static void region_coeffs(const sdc_region_t& r, double& a1, double& a2, double& b1, double& b2) {
+    if (r.kind == SDC_DISK) {
+        a1 = 1; a2 = -r.center; b1 = 0; b2 = r.radius;
+    } else if (r.kind == SDC_HALFPLANE) {
+        const double s = r.scale > 0 ? r.scale : 1.0;
+        a1 = 1; a2 = -(r.shift - s); b1 = 1; b2 = -(r.shift + s);
+    } else {
+        a1 = 1; a2 = 0; b1 = 0; b2 = 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched implicit repeated squaring (Alg. 3)
+// ---------------------------------------------------------------------------
+template <typename T> struct IrsSide {
+    int n = 0;
+    const double* A = nullptr; int lda = 0;
+    const double* B = nullptr; int ldb = 0;
+    int trans = 0;
+    double a1 = 1, a2 = 0, b1 = 0, b2 = 1;
+    double tau = 0;
+    int maxit = 60;
+    T* W = nullptr; double* Rprev = nullptr; T* diag = nullptr; double* norms = nullptr;
+    T* Tm = nullptr; unsigned* counters = nullptr;
+    int p = 0, converged = 0, nonfinite = 0;
+    double rconv = NAN;
+};
+
+template <typename T> static void irs_layout(Carver& c, IrsSide<T>& s) {
+    const size_t n = (size_t)s.n;
+    s.W = c.take<T>(6 * n * n);
+    s.Rprev = c.take<double>(n * n);
+    s.diag = c.take<T>(n);
+    s.Tm = c.take<T>(qr_aux_elems<T>());
+    s.counters = c.take<unsigned>(kMaxInternal);
+}
+
+template <typename T> static QrDesc<T> qr_desc(T* W, int ld, int m, int nf, int ncols, T* aux, T* diag,
+                                               unsigned* counters) {
+    using C = QrCfg<T>;
+    QrDesc<T> d;
+    d.W = W; d.ld = ld; d.m = m; d.nf = nf; d.ncols = ncols;
+    d.Tm = aux;
+    d.Vint = aux + (size_t)(kMaxLeaves + kMaxInternal) * C::NB * C::NB;
+    d.diag = diag; d.counters = counters; d.active = 1;
+    return d;
+}
+
+template <typename T> static int run_irs(Handle& h, std::vector<IrsSide<T>*>& sides, double* norms_all) {
+    const int cnt = (int)sides.size();
+    if (!cnt) return SDC_OK;
+    std::vector<IrsInit<T>> ini(cnt);
+    std::vector<QrDesc<T>> qd(cnt);
+    std::vector<IrsDesc<T>> pd(cnt);
+    for (int i = 0; i < cnt; ++i) {
+        IrsSide<T>& s = *sides[i];
+        s.norms = norms_all + 4 * i;
+        ini[i] = IrsInit<T>{s.W, s.n, s.A, s.lda, s.B, s.ldb, s.a1, s.a2, s.b1, s.b2, s.trans};
+        qd[i] = qr_desc<T>(s.W, 2 * s.n, 2 * s.n, s.n, 3 * s.n, s.Tm, s.diag, s.counters);
+        pd[i] = IrsDesc<T>{s.W, s.n, s.Rprev, s.diag, s.norms, 1};
+        fill<unsigned>(s.counters, kMaxInternal, 0u, h.stream);
+        s.p = 0; s.converged = 0; s.nonfinite = 0; s.rconv = NAN;
+    }
+    UPLOAD(dini, ini);
+    irs_init_batch<T>(dini, ini.data(), cnt, h.stream);
+    CHK(ensure_host(h, sizeof(double) * 4 * cnt));
+    double* hn = reinterpret_cast<double*>(h.host);
+    HIPCHK(hipStreamSynchronize(h.stream));
+    const size_t mark = h.desc_off;
+    for (int it = 0;; ++it) {
+        h.desc_off = mark;
+        UPLOAD(dq, qd);
+        UPLOAD(dp, pd);
+        fill<double>(norms_all, 4 * (size_t)cnt, 0.0, h.stream);
+        qr_aug_batch<T>(dq, qd.data(), cnt, h.stream);
+        irs_post_batch<T>(dp, pd.data(), cnt, it == 0, h.stream);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(hn, norms_all, sizeof(double) * 4 * cnt, hipMemcpyDeviceToHost, h.stream));
+        HIPCHK(hipStreamSynchronize(h.stream));
+        int any = 0;
+        for (int i = 0; i < cnt; ++i) {
+            if (!qd[i].active) continue;
+            IrsSide<T>& s = *sides[i];
+            const double diff = hn[4 * i], ref = hn[4 * i + 1], cur = hn[4 * i + 2];
+            s.p = it + 1;
+            bool stop = false;
+            if (!std::isfinite(cur) || (it > 0 && !std::isfinite(diff))) {
+                s.nonfinite = 1;
+                stop = true;
+            } else if (it > 0) {
+                s.rconv = ref > 0 ? diff / ref : INFINITY;
+                if (diff <= s.tau * ref) {
+                    s.converged = 1;
+                    stop = true;
+                }
+            }
+            if (!stop && it + 1 > s.maxit) stop = true;
+            if (stop) {
+                qd[i].active = 0;
+                pd[i].active = 0;
+            } else {
+                any = 1;
+            }
+        }
+        if (!any) break;
+    }
+    return SDC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Rank read off the GRURV diagonals (same rule as the oracle): every ratio
+// tiny -> all eigenvalues inside; none tiny -> all outside; otherwise the
+// count above the largest gap of the sorted ratios.
+// ---------------------------------------------------------------------------
+enum Side { SIDE_INSIDE = 0, SIDE_OUTSIDE = 1, SIDE_SPLIT = 2 };
+static int rank_from_rho(const std::vector<double>& rho, double& gap, int& side) {
+    const int n = (int)rho.size();
+    double mx = 0, mn = INFINITY;
+    for (double r : rho) {
+        mx = std::max(mx, std::fabs(r));
+        mn = std::min(mn, std::fabs(r));
+    }
+    gap = 1.0;
+    if (!(mx >= kRhoOneSide)) {
+        side = SIDE_INSIDE;
+        return 0;
+    }
+    if (mn > kRhoOneSide) {
+        side = SIDE_OUTSIDE;
+        return n;
+    }
+    std::vector<double> s(n);
+    for (int i = 0; i < n; ++i) s[i] = std::max(std::fabs(rho[i]), 1e-300);
+    std::sort(s.begin(), s.end(), std::greater<double>());
+    int best = 0;
+    double bg = -1;
+    for (int i = 0; i + 1 < n; ++i) {
+        const double r = s[i] / s[i + 1];
+        if (r > bg) {
+            bg = r;
+            best = i;
+        }
+    }
+    side = SIDE_SPLIT;
+    gap = bg;
+    return best + 1;
+}
+
+// ---------------------------------------------------------------------------
+// Per-problem workspace of the FP64 stages.
+// ---------------------------------------------------------------------------
+struct JobWs {
+    SplitJob* job = nullptr;
+    IrsSide<double> sd[2];
+    IrsSide<float> sf[2];
+    bool fp32 = false;
+    const double* Ap[2] = {nullptr, nullptr};
+    const double* Bp[2] = {nullptr, nullptr};
+    int ldp[2] = {0, 0};
+    double* Apd[2] = {nullptr, nullptr};
+    double* Bpd[2] = {nullptr, nullptr};
+    double *X = nullptr, *Vt = nullptr, *T1 = nullptr, *T2 = nullptr;
+    double* qaux = nullptr;
+    double* dg[4] = {nullptr, nullptr, nullptr, nullptr};
+    unsigned* qcnt = nullptr;
+    double *SA = nullptr, *SB = nullptr, *e = nullptr, *out = nullptr, *nrm = nullptr, *orth = nullptr;
+    std::vector<double> rho_r, rho_l;
+    int attempt = 0, done = 0, best_attempt = -1;
+    double best_e = INFINITY;
+    int status = 0;
+    double tau = 0;
+};
+
+static void job_layout(Carver& c, JobWs& w) {
+    const SplitJob& j = *w.job;
+    const size_t n = (size_t)j.n;
+    const int nsides = j.pencil ? 2 : 1;
+    for (int s = 0; s < nsides; ++s) {
+        if (w.fp32) {
+            irs_layout(c, w.sf[s]);
+            w.Apd[s] = c.take<double>(n * n);
+            w.Bpd[s] = c.take<double>(n * n);
+        } else {
+            irs_layout(c, w.sd[s]);
+        }
+    }
+    w.X = c.take<double>(2 * n * n);
+    w.Vt = c.take<double>(n * n);
+    w.T1 = c.take<double>(n * n);
+    w.T2 = c.take<double>(n * n);
+    w.qaux = c.take<double>(qr_aux_elems<double>());
+    for (int k = 0; k < 4; ++k) w.dg[k] = c.take<double>(n);
+    w.qcnt = c.take<unsigned>(kMaxInternal);
+    w.SA = c.take<double>(n * n);
+    w.SB = j.pencil ? c.take<double>(n * n) : nullptr;
+    w.e = c.take<double>(n + 1);
+    w.out = c.take<double>(2);
+    w.nrm = c.take<double>(2);
+    w.orth = c.take<double>(1);
+}
+
+static EwDesc ew_perm(int n, const double* in, int ldi, double* out, int ldo, int trans, int revP, int revQ,
+                      const double* sg) {
+    EwDesc d{};
+    d.op = EW_PERMUTE; d.n = n; d.rows = n; d.in = in; d.ldi = ldi; d.out = out; d.ldo = ldo;
+    d.trans = trans; d.revP = revP; d.revQ = revQ; d.sg = sg; d.alpha = 1.0; d.active = 1;
+    return d;
+}
+static EwDesc ew_ident(int n, double* out, int ldo) {
+    EwDesc d{};
+    d.op = EW_IDENTITY; d.n = n; d.rows = n; d.out = out; d.ldo = ldo; d.alpha = 1.0; d.active = 1;
+    return d;
+}
+static EwDesc ew_add(int n, const double* a, int lda, const double* b, int ldb, double* out, int ldo) {
+    EwDesc d{};
+    d.op = EW_ADD; d.n = n; d.rows = n; d.in = a; d.ldi = lda; d.in2 = b; d.ld2 = ldb; d.out = out; d.ldo = ldo;
+    d.alpha = 1.0; d.active = 1;
+    return d;
+}
+static GemmDesc<double> gemm(int n, const double* A, int lda, int ta, const double* B, int ldb, int tb, double* C,
+                             int ldc) {
+    GemmDesc<double> g{};
+    g.A = A; g.B = B; g.C = C; g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+    g.M = n; g.N = n; g.K = n; g.ta = ta; g.tb = tb; g.alpha = 1.0; g.beta = 0.0; g.active = 1;
+    return g;
+}
+
+static int run_ew(Handle& h, const std::vector<EwDesc>& v) {
+    if (v.empty()) return SDC_OK;
+    UPLOAD(d, v);
+    ew_batch<double, double>(d, v.data(), (int)v.size(), h.stream);
+    return SDC_OK;
+}
+static int run_gemm(Handle& h, const std::vector<GemmDesc<double>>& v) {
+    if (v.empty()) return SDC_OK;
+    UPLOAD(d, v);
+    gemm_batch<double>(d, v.data(), (int)v.size(), h.stream);
+    return SDC_OK;
+}
+static int run_qr(Handle& h, std::vector<JobWs*>& js, int dgi) {
+    std::vector<QrDesc<double>> q;
+    for (JobWs* w : js) {
+        const int n = w->job->n;
+        q.push_back(qr_desc<double>(w->X, n, n, n, 2 * n, w->qaux, w->dg[dgi], w->qcnt));
+    }
+    if (q.empty()) return SDC_OK;
+    UPLOAD(d, q);
+    qr_aug_batch<double>(d, q.data(), (int)q.size(), h.stream);
+    return SDC_OK;
+}
+
+// X[:, 0:n] <- the Gaussian of (attempt, side); X[:, n:2n] <- I.
+static int stage_gaussian(Handle& h, std::vector<JobWs*>& js, int side) {
+    std::vector<EwDesc> copies;
+    std::vector<GaussDesc> draws;
+    std::vector<EwDesc> ids;
+    for (JobWs* w : js) {
+        const SplitJob& j = *w->job;
+        const int n = j.n;
+        if (j.opts.G) {
+            const double* G = j.opts.G + (size_t)(w->attempt * 2 + side) * n * n;
+            copies.push_back(ew_perm(n, G, n, w->X, n, 0, 0, 0, nullptr));
+        } else {
+            GaussDesc g{};
+            g.G = w->X; g.ld = n; g.n = n; g.seed = j.opts.seed + (uint64_t)w->attempt; g.tag = side; g.active = 1;
+            draws.push_back(g);
+        }
+        ids.push_back(ew_ident(n, w->X + (size_t)n * n, n));
+    }
+    CHK(run_ew(h, copies));
+    if (!draws.empty()) {
+        UPLOAD(d, draws);
+        gauss_batch(d, draws.data(), (int)draws.size(), h.stream);
+    }
+    CHK(run_ew(h, ids));
+    return SDC_OK;
+}
+
+// Alg. 2 with k = 2, m = (-1, 1): Q_R = GRURV(2, A_p + B_p, A_p, -1, 1).
+// RURV of A_p (V from QR of the Gaussian, sign-fixed; A_p V^T = U R2), then
+// RQ of U^T (A_p + B_p) = R1 W by the reversal J, Q_R = W^T.  Writes Q_R to
+// job.Q and the diagonals of R2 (dg[1]) and of the reversed R1 (dg[2]).
+static int grurv_right(Handle& h, std::vector<JobWs*>& js) {
+    CHK(stage_gaussian(h, js, 0));
+    CHK(run_qr(h, js, 0));
+    std::vector<EwDesc> e1, e2, e3, e4;
+    std::vector<GemmDesc<double>> g1;
+    for (JobWs* w : js) {
+        const int n = w->job->n;
+        double* Xr = w->X + (size_t)n * n;
+        e1.push_back(ew_perm(n, Xr, n, w->Vt, n, 0, 0, 0, w->dg[0]));              // V^T = diag(s) Q_G^T
+        g1.push_back(gemm(n, w->Ap[0], w->ldp[0], 0, w->Vt, n, 0, w->X, n));        // A_p V^T
+        e2.push_back(ew_add(n, w->Ap[0], w->ldp[0], w->Bp[0], w->ldp[0], Xr, n));   // A_p + B_p
+    }
+    CHK(run_ew(h, e1));
+    CHK(run_gemm(h, g1));
+    CHK(run_ew(h, e2));
+    CHK(run_qr(h, js, 1));  // U^T (A_p + B_p) in the right block, R2 diagonal in dg[1]
+    for (JobWs* w : js) {
+        const int n = w->job->n;
+        double* Xr = w->X + (size_t)n * n;
+        // Y = J (diag(s2) U^T(A_p+B_p))^T J
+        e3.push_back(ew_perm(n, Xr, n, w->X, n, 1, 1, 1, w->dg[1]));
+        e4.push_back(ew_ident(n, Xr, n));
+    }
+    CHK(run_ew(h, e3));
+    CHK(run_ew(h, e4));
+    CHK(run_qr(h, js, 2));
+    std::vector<EwDesc> e5;
+    for (JobWs* w : js) {
+        const int n = w->job->n;
+        // Q_R = J Qt diag(s3) J
+        e5.push_back(ew_perm(n, w->X + (size_t)n * n, n, w->job->Q, w->job->ldq, 1, 1, 1, w->dg[2]));
+    }
+    CHK(run_ew(h, e5));
+    return SDC_OK;
+}
+
+// Alg. 2 with k = 2, m = (1, -1) on the transposed pencil's iterates:
+// Q_L = GRURV(2, A_p'^T, (A_p' + B_p')^T, 1, -1).  RULV of A_p' + B_p'
+// (QL through the column reversal: (A_p'+B_p') V^T J = Qt Rt, U = Qt J),
+// then QR of A_p'^T U.  Writes Q_L to job.QL, the diagonal of the reversed L
+// (dg[1]) and of R1 (dg[2]).
+static int grurv_left(Handle& h, std::vector<JobWs*>& js) {
+    CHK(stage_gaussian(h, js, 1));
+    CHK(run_qr(h, js, 0));
+    std::vector<EwDesc> e1, e2, e3;
+    std::vector<GemmDesc<double>> g1;
+    for (JobWs* w : js) {
+        const int n = w->job->n;
+        double* Xr = w->X + (size_t)n * n;
+        e1.push_back(ew_perm(n, Xr, n, w->Vt, n, 0, 0, 1, w->dg[0]));                  // V^T J
+        e2.push_back(ew_add(n, w->Ap[1], w->ldp[1], w->Bp[1], w->ldp[1], w->T1, n));    // A_p' + B_p'
+        g1.push_back(gemm(n, w->T1, n, 0, w->Vt, n, 0, w->X, n));                       // (A_p'+B_p') V^T J
+        e3.push_back(ew_ident(n, Xr, n));
+    }
+    CHK(run_ew(h, e1));
+    CHK(run_ew(h, e2));
+    CHK(run_gemm(h, g1));
+    CHK(run_ew(h, e3));
+    CHK(run_qr(h, js, 1));
+    std::vector<EwDesc> e4, e5;
+    std::vector<GemmDesc<double>> g2;
+    for (JobWs* w : js) {
+        const int n = w->job->n;
+        double* Xr = w->X + (size_t)n * n;
+        e4.push_back(ew_perm(n, Xr, n, w->Vt, n, 1, 1, 0, w->dg[1]));                   // U = Qt diag(s) J
+        g2.push_back(gemm(n, w->Ap[1], w->ldp[1], 1, w->Vt, n, 0, w->X, n));            // A_p'^T U
+        e5.push_back(ew_ident(n, Xr, n));
+    }
+    CHK(run_ew(h, e4));
+    CHK(run_gemm(h, g2));
+    CHK(run_ew(h, e5));
+    CHK(run_qr(h, js, 2));
+    std::vector<EwDesc> e6;
+    for (JobWs* w : js) {
+        const int n = w->job->n;
+        e6.push_back(ew_perm(n, w->X + (size_t)n * n, n, w->job->QL, w->job->ldql, 1, 0, 0, w->dg[2]));
+    }
+    CHK(run_ew(h, e6));
+    return SDC_OK;
+}
+
+// Block form (Alg. 4 line 5 / Alg. 6 line 3) with the original A, B.
+static int block_form(Handle& h, std::vector<JobWs*>& js) {
+    std::vector<GemmDesc<double>> g1, g2;
+    std::vector<EwDesc> es;
+    for (JobWs* w : js) {
+        SplitJob& j = *w->job;
+        const int n = j.n;
+        g1.push_back(gemm(n, j.A, j.lda, 0, j.Q, j.ldq, 0, w->T1, n));
+        if (j.pencil) {
+            g1.push_back(gemm(n, j.B, j.ldb, 0, j.Q, j.ldq, 0, w->T2, n));
+            g2.push_back(gemm(n, j.QL, j.ldql, 1, w->T1, n, 0, j.Ahat, j.ldah));
+            g2.push_back(gemm(n, j.QL, j.ldql, 1, w->T2, n, 0, j.Bhat, j.ldbh));
+        } else {
+            g2.push_back(gemm(n, j.Q, j.ldq, 1, w->T1, n, 0, w->T2, n));
+            EwDesc d{};
+            d.op = EW_SYM; d.n = n; d.rows = n; d.in = w->T2; d.ldi = n; d.out = j.Ahat; d.ldo = j.ldah;
+            d.alpha = 1.0; d.active = 1;
+            es.push_back(d);
+        }
+    }
+    CHK(run_gemm(h, g1));
+    CHK(run_gemm(h, g2));
+    CHK(run_ew(h, es));
+    return SDC_OK;
+}
+
+static int split_search(Handle& h, std::vector<JobWs*>& js) {
+    std::vector<SplitDesc> sd;
+    for (JobWs* w : js) {
+        SplitJob& j = *w->job;
+        SplitDesc d{};
+        d.Ah = j.Ahat; d.lda = j.ldah;
+        d.Bh = j.pencil ? j.Bhat : nullptr; d.ldb = j.ldbh;
+        d.n = j.n; d.SA = w->SA; d.SB = w->SB; d.norms = w->nrm; d.e = w->e; d.out = w->out; d.active = 1;
+        sd.push_back(d);
+    }
+    if (sd.empty()) return SDC_OK;
+    UPLOAD(d, sd);
+    split_search_batch(d, sd.data(), (int)sd.size(), h.stream);
+    return SDC_OK;
+}
+
+// Read back the diagonals of the GRURV triangular factors and form the rank
+// statistic rho = |diag(R1^{m1} R2^{m2})|.
+static int fetch_rho(Handle& h, std::vector<JobWs*>& js, bool left) {
+    size_t need = 0;
+    for (JobWs* w : js) need += 2 * (size_t)w->job->n;
+    CHK(ensure_host(h, need * sizeof(double) + 64));
+    double* hb = reinterpret_cast<double*>(h.host);
+    size_t off = 0;
+    for (JobWs* w : js) {
+        const int n = w->job->n;
+        HIPCHK(hipMemcpyAsync(hb + off, w->dg[1], sizeof(double) * n, hipMemcpyDeviceToHost, h.stream));
+        HIPCHK(hipMemcpyAsync(hb + off + n, w->dg[2], sizeof(double) * n, hipMemcpyDeviceToHost, h.stream));
+        off += 2 * (size_t)n;
+    }
+    HIPCHK(hipStreamSynchronize(h.stream));
+    off = 0;
+    for (JobWs* w : js) {
+        const int n = w->job->n;
+        const double* d1 = hb + off;
+        const double* d2 = d1 + n;
+        std::vector<double>& rho = left ? w->rho_l : w->rho_r;
+        rho.assign(n, 0.0);
+        for (int i = 0; i < n; ++i) {
+            // right: |R2_ii| / |R1_ii| with R1_ii = Rt_{n-1-i} (RQ by reversal)
+            // left:  |R1_ii| / |L_ii|  with L_ii  = Rt_{n-1-i} (QL by reversal)
+            rho[i] = left ? std::fabs(d2[i]) / std::fabs(d1[n - 1 - i])
+                          : std::fabs(d1[i]) / std::fabs(d2[n - 1 - i]);
+        }
+        off += 2 * (size_t)n;
+    }
+    return SDC_OK;
+}
+
+static int fetch_search(Handle& h, std::vector<JobWs*>& js) {
+    CHK(ensure_host(h, js.size() * 2 * sizeof(double) + 64));
+    double* hb = reinterpret_cast<double*>(h.host);
+    for (size_t q = 0; q < js.size(); ++q)
+        HIPCHK(hipMemcpyAsync(hb + 2 * q, js[q]->out, sizeof(double) * 2, hipMemcpyDeviceToHost, h.stream));
+    HIPCHK(hipStreamSynchronize(h.stream));
+    for (size_t q = 0; q < js.size(); ++q) {
+        js[q]->job->info.k_lead = (int)hb[2 * q];
+        js[q]->job->info.e21_rel = hb[2 * q + 1];
+    }
+    return SDC_OK;
+}
+
+// One GRURV + block form + split search pass for the jobs in js, each at its
+// own w->attempt.
+static int split_pass(Handle& h, std::vector<JobWs*>& js) {
+    if (js.empty()) return SDC_OK;
+    CHK(grurv_right(h, js));
+    CHK(fetch_rho(h, js, false));
+    std::vector<JobWs*> pen;
+    for (JobWs* w : js)
+        if (w->job->pencil) pen.push_back(w);
+    if (!pen.empty()) {
+        CHK(grurv_left(h, pen));
+        CHK(fetch_rho(h, pen, true));
+    }
+    CHK(block_form(h, js));
+    CHK(split_search(h, js));
+    HIPCHK(hipGetLastError());
+    CHK(fetch_search(h, js));
+    return SDC_OK;
+}
+
+static bool sides_converged(const JobWs& w) {
+    const int ns = w.job->pencil ? 2 : 1;
+    for (int s = 0; s < ns; ++s)
+        if (!(w.fp32 ? w.sf[s].converged : w.sd[s].converged)) return false;
+    return true;
+}
+
+// Accept / retry / classify one attempt (the oracle's rule, Alg. 4 line 5:
+// accept when the minimized norm is small, cross-checked with the rank the
+// GRURV diagonals reveal).  Returns true when the job is finished.
+static bool decide(JobWs& w, bool& needs_best) {
+    SplitJob& j = *w.job;
+    const int n = j.n;
+    double gap = 1, gapl = 1;
+    int side = SIDE_SPLIT, sidel = SIDE_SPLIT;
+    const int krho = rank_from_rho(w.rho_r, gap, side);
+    int krhol = krho;
+    if (j.pencil) krhol = rank_from_rho(w.rho_l, gapl, sidel);
+    const bool conv = sides_converged(w);
+    needs_best = false;
+    j.info.k_rho = krho;
+    j.info.rank_gap = j.pencil ? std::min(gap, gapl) : gap;
+    j.info.attempts = w.attempt + 1;
+    if (side != SIDE_SPLIT || (j.pencil && sidel != SIDE_SPLIT)) {
+        const int k = side == SIDE_INSIDE ? 0 : n;
+        if (!j.pencil) w.status = conv ? SDC_NO_SPLIT : SDC_NOT_CONVERGED;
+        else w.status = (conv && side == sidel) ? SDC_NO_SPLIT : (conv ? SDC_RANK_AMBIGUOUS : SDC_NOT_CONVERGED);
+        j.info.k_lead = k;
+        j.info.n_inside = n - k;
+        j.info.e21_rel = 0.0;
+        return true;
+    }
+    const int ks = j.info.k_lead;
+    const double es = j.info.e21_rel;
+    j.info.n_inside = n - ks;
+    if (es < w.best_e) {
+        w.best_e = es;
+        w.best_attempt = w.attempt;
+    }
+    if (ks == krho && (!j.pencil || ks == krhol) && es <= j.opts.split_tol) {
+        w.status = conv ? SDC_OK : SDC_NOT_CONVERGED;
+        return true;
+    }
+    if (w.attempt < j.opts.max_retries) {
+        ++w.attempt;
+        return false;
+    }
+    w.status = conv ? SDC_RANK_AMBIGUOUS : SDC_NOT_CONVERGED;
+    needs_best = w.best_attempt >= 0 && w.best_attempt != w.attempt;
+    return true;
+}
+
+static void fill_defaults(sdc_opts_t& o) {
+    if (o.maxit <= 0) o.maxit = 60;
+    if (o.split_tol <= 0) o.split_tol = 1e-10;
+    if (o.max_retries < 0) o.max_retries = 0;
+}
+
+int run_split_jobs(Handle& h, std::vector<SplitJob>& jobs) {
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<JobWs> ws(jobs.size());
+    int nsides = 0;
+    for (size_t i = 0; i < jobs.size(); ++i) {
+        fill_defaults(jobs[i].opts);
+        ws[i].job = &jobs[i];
+        ws[i].fp32 = jobs[i].opts.prec == SDC_FP32_REFINE;
+        nsides += jobs[i].pencil ? 2 : 1;
+    }
+    // workspace: size pass, then carve
+    auto layout = [&](Carver& c) -> double* {
+        for (JobWs& w : ws) job_layout(c, w);
+        return c.take<double>(4 * (size_t)nsides);
+    };
+    {
+        Carver c0(nullptr);
+        layout(c0);
+        CHK(ensure_ws(h, c0.off + 4096));
+    }
+    Carver c(h.ws);
+    double* norms_all = layout(c);
+    CHK(ensure_desc(h, (size_t)(64 << 10) + jobs.size() * (size_t)(8 << 10)));
+    h.desc_off = 0;
+
+    // IRS on every side, FP64 and FP32 sides in separate lockstep batches
+    std::vector<IrsSide<double>*> sd;
+    std::vector<IrsSide<float>*> sf;
+    for (JobWs& w : ws) {
+        SplitJob& j = *w.job;
+        double a1, a2, b1, b2;
+        region_coeffs(j.region, a1, a2, b1, b2);
+        const int ns = j.pencil ? 2 : 1;
+        for (int s = 0; s < ns; ++s) {
+            auto setup = [&](auto& side, double eps) {
+                side.n = j.n; side.A = j.A; side.lda = j.lda;
+                side.B = j.pencil ? j.B : nullptr; side.ldb = j.ldb;
+                side.trans = s; side.a1 = a1; side.a2 = a2; side.b1 = b1; side.b2 = b2;
+                side.tau = j.opts.tau > 0 ? j.opts.tau : std::sqrt(eps);
+                side.maxit = j.opts.maxit;
+            };
+            if (w.fp32) {
+                setup(w.sf[s], (double)std::numeric_limits<float>::epsilon());
+                sf.push_back(&w.sf[s]);
+            } else {
+                setup(w.sd[s], std::numeric_limits<double>::epsilon());
+                sd.push_back(&w.sd[s]);
+            }
+        }
+    }
+    double* nd = norms_all;
+    double* nf = norms_all + 4 * sd.size();
+    CHK(run_irs<double>(h, sd, nd));
+    h.desc_off = 0;
+    CHK(run_irs<float>(h, sf, nf));
+    h.desc_off = 0;
+
+    // views of (A_p, B_p) in FP64; norms of the inputs
+    std::vector<EwDesc> conv;
+    std::vector<NormDesc> nrm;
+    std::vector<JobWs*> live;
+    for (JobWs& w : ws) {
+        SplitJob& j = *w.job;
+        const int n = j.n;
+        j.info.n = n;
+        const int ns = j.pencil ? 2 : 1;
+        bool bad = false;
+        for (int s = 0; s < ns; ++s) {
+            if (w.fp32) {
+                IrsSide<float>& S = w.sf[s];
+                bad |= S.nonfinite != 0;
+                EwDesc a{}, b{};
+                a.op = b.op = EW_PERMUTE; a.n = b.n = n; a.rows = b.rows = n; a.alpha = b.alpha = 1.0;
+                a.active = b.active = 1;
+                a.in = S.W + (size_t)2 * n * n; a.ldi = 2 * n; a.out = w.Apd[s]; a.ldo = n;
+                b.in = S.W; b.ldi = 2 * n; b.out = w.Bpd[s]; b.ldo = n;
+                conv.push_back(a);
+                conv.push_back(b);
+                w.Ap[s] = w.Apd[s]; w.Bp[s] = w.Bpd[s]; w.ldp[s] = n;
+                if (s == 0) { j.info.iters_right = S.p; j.info.rconv_last = S.rconv; }
+                else j.info.iters_left = S.p;
+            } else {
+                IrsSide<double>& S = w.sd[s];
+                bad |= S.nonfinite != 0;
+                w.Ap[s] = S.W + (size_t)2 * n * n; w.Bp[s] = S.W; w.ldp[s] = 2 * n;
+                if (s == 0) { j.info.iters_right = S.p; j.info.rconv_last = S.rconv; }
+                else j.info.iters_left = S.p;
+            }
+        }
+        if (bad) {
+            w.status = SDC_ERR_NONFINITE;
+            continue;
+        }
+        fill<double>(w.nrm, 2, 0.0, h.stream);
+        fill<double>(w.orth, 1, 0.0, h.stream);
+        fill<unsigned>(w.qcnt, kMaxInternal, 0u, h.stream);
+        nrm.push_back(NormDesc{j.A, j.lda, n, n, w.nrm, 1});
+        if (j.pencil) nrm.push_back(NormDesc{j.B, j.ldb, n, n, w.nrm + 1, 1});
+        live.push_back(&w);
+    }
+    if (!conv.empty()) {
+        UPLOAD(dc, conv);
+        ew_batch<float, double>(dc, conv.data(), (int)conv.size(), h.stream);
+    }
+    if (!nrm.empty()) {
+        UPLOAD(dn, nrm);
+        norm1_batch(dn, nrm.data(), (int)nrm.size(), h.stream);
+    }
+
+    // rank-revealing factorization, block form, split point; retries
+    std::vector<JobWs*> redo;
+    while (!live.empty()) {
+        const size_t mark = h.desc_off;
+        CHK(split_pass(h, live));
+        h.desc_off = mark;
+        std::vector<JobWs*> next;
+        for (JobWs* w : live) {
+            bool needs_best = false;
+            if (!decide(*w, needs_best)) next.push_back(w);
+            else if (needs_best) redo.push_back(w);
+        }
+        live.swap(next);
+    }
+    if (!redo.empty()) {
+        // recompute the attempt with the smallest e(k*) (deterministic draws)
+        std::vector<sdc_info_t> keep;
+        for (JobWs* w : redo) {
+            keep.push_back(w->job->info);
+            w->attempt = w->best_attempt;
+        }
+        CHK(split_pass(h, redo));
+        for (size_t q = 0; q < redo.size(); ++q) {
+            SplitJob& j = *redo[q]->job;
+            const int k = j.info.k_lead;
+            const double e = j.info.e21_rel;
+            j.info = keep[q];
+            j.info.k_lead = k;
+            j.info.e21_rel = e;
+            j.info.n_inside = j.n - k;
+        }
+        h.desc_off = 0;
+    }
+
+    // diagnostics: ||Q^T Q - I||_F
+    std::vector<GemmDesc<double>> go;
+    std::vector<NormDesc> no;
+    std::vector<JobWs*> diag_jobs;
+    for (JobWs& w : ws) {
+        SplitJob& j = *w.job;
+        if (!j.opts.diagnostics || w.status < 0) continue;
+        go.push_back(gemm(j.n, j.Q, j.ldq, 1, j.Q, j.ldq, 0, w.T1, j.n));
+        no.push_back(NormDesc{w.T1, j.n, j.n, j.n, w.orth, 1});
+        diag_jobs.push_back(&w);
+    }
+    if (!go.empty()) {
+        CHK(run_gemm(h, go));
+        UPLOAD(dno, no);
+        orth_err_batch(dno, no.data(), (int)no.size(), h.stream);
+        CHK(ensure_host(h, diag_jobs.size() * sizeof(double) + 64));
+        double* hb = reinterpret_cast<double*>(h.host);
+        for (size_t q = 0; q < diag_jobs.size(); ++q)
+            HIPCHK(hipMemcpyAsync(hb + q, diag_jobs[q]->orth, sizeof(double), hipMemcpyDeviceToHost, h.stream));
+        HIPCHK(hipStreamSynchronize(h.stream));
+        for (size_t q = 0; q < diag_jobs.size(); ++q) diag_jobs[q]->job->info.orth_err = std::sqrt(hb[q]);
+    }
+    HIPCHK(hipStreamSynchronize(h.stream));
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (JobWs& w : ws) {
+        w.job->status = w.status;
+        w.job->info.ms = ms;
+    }
+    return SDC_OK;
+}
+
+int run_irs_only(Handle& h, int n, const double* A, int lda, const double* B, int ldb, int transpose,
+                 const sdc_region_t& region, const sdc_opts_t& opts_in, double* Ap, double* Bp, double* R,
+                 int ldo, int* p, double* rconv) {
+    sdc_opts_t opts = opts_in;
+    fill_defaults(opts);
+    double a1, a2, b1, b2;
+    region_coeffs(region, a1, a2, b1, b2);
+    const bool fp32 = opts.prec == SDC_FP32_REFINE;
+    IrsSide<double> sdd;
+    IrsSide<float> sff;
+    auto setup = [&](auto& side, double eps) {
+        side.n = n; side.A = A; side.lda = lda; side.B = B; side.ldb = ldb; side.trans = transpose;
+        side.a1 = a1; side.a2 = a2; side.b1 = b1; side.b2 = b2;
+        side.tau = opts.tau > 0 ? opts.tau : std::sqrt(eps);
+        side.maxit = opts.maxit;
+    };
+    auto layout = [&](Carver& c) -> double* {
+        if (fp32) irs_layout(c, sff);
+        else irs_layout(c, sdd);
+        return c.take<double>(4);
+    };
+    {
+        Carver c0(nullptr);
+        layout(c0);
+        CHK(ensure_ws(h, c0.off + 4096));
+    }
+    Carver c(h.ws);
+    double* norms = layout(c);
+    CHK(ensure_desc(h, 64 << 10));
+    h.desc_off = 0;
+    int nonfinite, converged;
+    const void* W;
+    if (fp32) {
+        setup(sff, (double)std::numeric_limits<float>::epsilon());
+        std::vector<IrsSide<float>*> v{&sff};
+        CHK(run_irs<float>(h, v, norms));
+        nonfinite = sff.nonfinite; converged = sff.converged; *p = sff.p; *rconv = sff.rconv; W = sff.W;
+    } else {
+        setup(sdd, std::numeric_limits<double>::epsilon());
+        std::vector<IrsSide<double>*> v{&sdd};
+        CHK(run_irs<double>(h, v, norms));
+        nonfinite = sdd.nonfinite; converged = sdd.converged; *p = sdd.p; *rconv = sdd.rconv; W = sdd.W;
+    }
+    h.desc_off = 0;
+    if (nonfinite) return SDC_ERR_NONFINITE;
+    std::vector<EwDesc> cp;
+    auto mk = [&](const void* in, int ldi, double* out) {
+        EwDesc d{};
+        d.op = EW_PERMUTE; d.n = n; d.rows = n; d.in = in; d.ldi = ldi; d.out = out; d.ldo = ldo;
+        d.alpha = 1.0; d.active = 1;
+        cp.push_back(d);
+    };
+    const size_t off_a = (size_t)2 * n * n;
+    if (fp32) {
+        mk(static_cast<const float*>(W) + off_a, 2 * n, Ap);
+        mk(W, 2 * n, Bp);
+    } else {
+        mk(static_cast<const double*>(W) + off_a, 2 * n, Ap);
+        mk(W, 2 * n, Bp);
+    }
+    UPLOAD(dcp, cp);
+    if (fp32) ew_batch<float, double>(dcp, cp.data(), (int)cp.size(), h.stream);
+    else ew_batch<double, double>(dcp, cp.data(), (int)cp.size(), h.stream);
+    if (R) {
+        std::vector<EwDesc> rc;
+        EwDesc d{};
+        d.op = EW_PERMUTE; d.n = n; d.rows = n; d.in = fp32 ? sff.Rprev : sdd.Rprev; d.ldi = n; d.out = R;
+        d.ldo = ldo; d.alpha = 1.0; d.active = 1;
+        rc.push_back(d);
+        UPLOAD(drc, rc);
+        ew_batch<double, double>(drc, rc.data(), 1, h.stream);
+    }
+    HIPCHK(hipStreamSynchronize(h.stream));
+    return converged ? SDC_OK : SDC_NOT_CONVERGED;
+}
+
+int run_gaussian(Handle& h, int n, uint64_t seed, int tag, double* G, int ldg) {
+    CHK(ensure_desc(h, 64 << 10));
+    h.desc_off = 0;
+    std::vector<GaussDesc> v(1);
+    v[0].G = G; v[0].ld = ldg; v[0].n = n; v[0].seed = seed; v[0].tag = tag; v[0].active = 1;
+    UPLOAD(d, v);
+    gauss_batch(d, v.data(), 1, h.stream);
+    HIPCHK(hipStreamSynchronize(h.stream));
+    return SDC_OK;
+}
+
+}  // namespace sdc

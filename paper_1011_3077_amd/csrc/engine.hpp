@@ -1,0 +1,58 @@
+// Host-side engine of the split step: workspace, descriptor staging, and the
+// batched drivers behind the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "sdc.h"
+
+namespace sdc {
+
+struct Handle {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    size_t budget = 0;
+    // device workspace (bump-allocated per call)
+    char* ws = nullptr;
+    size_t ws_size = 0;
+    size_t ws_off = 0;
+    // descriptor staging: pinned host mirror + device arena, same offsets
+    char* desc_h = nullptr;
+    char* desc_d = nullptr;
+    size_t desc_size = 0;
+    size_t desc_off = 0;
+    // pinned host buffer for small device-to-host results
+    char* host = nullptr;
+    size_t host_size = 0;
+};
+
+// One split problem (symmetric or pencil) as the drivers see it.
+struct SplitJob {
+    int n = 0;
+    bool pencil = false;
+    const double* A = nullptr; int lda = 0;
+    const double* B = nullptr; int ldb = 0;
+    sdc_region_t region{};
+    sdc_opts_t opts{};
+    double* Q = nullptr; int ldq = 0;      // Q (symmetric) or Q_R
+    double* QL = nullptr; int ldql = 0;
+    double* Ahat = nullptr; int ldah = 0;
+    double* Bhat = nullptr; int ldbh = 0;
+    sdc_info_t info{};
+    int status = 0;
+};
+
+// Runs every job; returns a negative status on argument/device failure,
+// else SDC_OK (per-job statuses in job.status).
+int run_split_jobs(Handle& h, std::vector<SplitJob>& jobs);
+
+// IRS alone for one side; see sdc_irs.
+int run_irs_only(Handle& h, int n, const double* A, int lda, const double* B, int ldb, int transpose,
+                 const sdc_region_t& region, const sdc_opts_t& opts, double* Ap, double* Bp, double* R,
+                 int ldo, int* p, double* rconv);
+
+int run_gaussian(Handle& h, int n, uint64_t seed, int tag, double* G, int ldg);
+
+}  // namespace sdc

@@ -1,0 +1,448 @@
+// Augmented blocked Householder QR on gfx950.
+//
+// For an m x ncols column-major matrix W, the leading nf columns are reduced
+// to upper-triangular form by Householder reflectors, and the transpose of
+// the accumulated orthogonal factor is applied to ALL ncols columns.  The
+// repeated squaring step (Alg. 3) uses it on W = [B_j A_j 0; -A_j 0 B_j]:
+// the QR of the first block column [B_j; -A_j] leaves R_j in the top rows and
+// turns the bottom halves of the two extra block columns into
+// Q12^T A_j = A_{j+1} and Q22^T B_j = B_{j+1}, so no explicit Q is formed.
+//
+// Panels are NB columns wide.  A panel's QR is a reduction tree of Householder
+// QRs over row blocks (the TSQR panel of communication-avoiding QR, which the
+// paper uses for its QR costs, Sec. 4.2): leaves of about H rows, then nodes
+// stacking up to F child R factors.  One kernel launch factors every node of
+// a panel; the last workgroup to finish among a node's children (counted with
+// an atomic) factors the parent, so no grid-wide barrier is needed.  The
+// trailing update applies the tree level by level: each node's block
+// reflector I - V T V^T is applied to its rows of every trailing column tile
+// on the matrix cores (MFMA), keeping the tile in registers.
+#include "sdc_internal.hpp"
+#include "mfma.hpp"
+
+namespace sdc {
+
+// p[idx] for idx in 0..3 without dynamic register indexing.
+template <typename T, int N>
+__device__ __forceinline__ T get4(const T (&p)[N], int idx) {
+    return idx == 0 ? p[0] : idx == 1 ? p[1] : idx == 2 ? p[2] : p[3];
+}
+template <typename T, int N>
+__device__ __forceinline__ void set4(T (&p)[N], int idx, T v) {
+    if (idx == 0) p[0] = v;
+    else if (idx == 1) p[1] = v;
+    else if (idx == 2) p[2] = v;
+    else p[3] = v;
+}
+
+// Householder QR of one tree node held in registers by a 256-thread
+// workgroup.  Thread (grp = tid/32, c = tid%32) owns column c, rows
+// r = 8*i + grp (i < RPG).  Rows >= mt and columns >= nbk are zero.
+//
+// Column step j (the usual reflector H_j = I - tau v v^T, v_j = 1,
+// beta = -sign(alpha) ||x||, tau = (beta - alpha)/beta, v = x/(alpha - beta)):
+// one reduction gives, for every column c, the dot product of column c with
+// the part of column j below the diagonal; from it each thread gets the
+// norm, the reflector scalars, w_c = v^T P[:, c] and (for c < j) the entries
+// v_c^T v_j needed for the compact-WY factor T.
+//
+// On return the registers hold R (upper part, diagonal = beta) and V
+// (strictly lower part); s_tau/s_beta hold tau and beta, s_T the
+// upper-triangular T (stride NB+1) with H_0 ... H_{nbk-1} = I - V T V^T.
+template <typename T>
+__device__ void node_qr(T (&p)[QrCfg<T>::RPG], int mt, int nbk, T* s_col, T* s_row, T* s_red,
+                        T* s_Sm, T* s_T, T* s_tau, T* s_beta) {
+    constexpr int RPG = QrCfg<T>::RPG, NB = QrCfg<T>::NB;
+    const int tid = threadIdx.x, grp = tid >> 5, c = tid & 31;
+    const int rpge = (mt + 7) >> 3;
+    for (int j = 0; j < nbk; ++j) {
+        T* tcol = s_col + (j & 1) * 8 * RPG;
+        T* trow = s_row + (j & 1) * NB;
+        if (c == j) {
+#pragma unroll
+            for (int i = 0; i < RPG; ++i)
+                if (i < rpge) tcol[grp * RPG + i] = (8 * i + grp > j) ? p[i] : T(0);
+        }
+        if (grp == (j & 7)) trow[c] = get4(p, j >> 3);
+        __syncthreads();
+        T z = 0;
+#pragma unroll
+        for (int i = 0; i < RPG; ++i)
+            if (i < rpge) z += tcol[grp * RPG + i] * p[i];
+        s_red[grp * NB + c] = z;
+        __syncthreads();
+        T zc = 0, xn2 = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            zc += s_red[q * NB + c];
+            xn2 += s_red[q * NB + j];
+        }
+        const T alpha = trow[j];
+        T beta, tau, scale;
+        if (xn2 == T(0)) {
+            beta = alpha;
+            tau = 0;
+            scale = 0;
+        } else {
+            const T nrm = sqrt(alpha * alpha + xn2);
+            beta = alpha >= T(0) ? -nrm : nrm;
+            tau = (beta - alpha) / beta;
+            scale = T(1) / (alpha - beta);
+        }
+        const T w = trow[c] + scale * zc;  // v_j^T P[:, c]  (= v_c^T v_j for c < j)
+        if (c > j) {
+            const T tw = tau * w, tws = tw * scale;
+#pragma unroll
+            for (int i = 0; i < RPG; ++i)
+                if (i < rpge) p[i] -= tws * tcol[grp * RPG + i];
+            if (grp == (j & 7)) set4(p, j >> 3, get4(p, j >> 3) - tw);
+        } else if (c == j) {
+#pragma unroll
+            for (int i = 0; i < RPG; ++i)
+                if (i < rpge && 8 * i + grp > j) p[i] = tcol[grp * RPG + i] * scale;
+            if (grp == (j & 7)) set4(p, j >> 3, beta);
+        } else if (grp == 0) {
+            s_Sm[c * (NB + 1) + j] = w;
+        }
+        if (tid == 0) {
+            s_tau[j] = tau;
+            s_beta[j] = beta;
+        }
+    }
+    __syncthreads();
+    // Compact-WY factor, forward columnwise recurrence:
+    // T[i][j] = -tau_j sum_{l=i}^{j-1} T[i][l] (v_l^T v_j), T[i][i] = tau_i.
+    if (tid < nbk) {
+        const int i = tid;
+        s_T[i * (NB + 1) + i] = s_tau[i];
+        for (int j = i + 1; j < nbk; ++j) {
+            T acc = 0;
+            for (int l = i; l < j; ++l) acc += s_T[i * (NB + 1) + l] * s_Sm[l * (NB + 1) + j];
+            s_T[i * (NB + 1) + j] = -s_tau[j] * acc;
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_panel(const QrDesc<T>* __restrict__ descs, int c0) {
+    using C = QrCfg<T>;
+    constexpr int NB = C::NB, RPG = C::RPG, LDT = C::MT_MAX + 1;
+    __shared__ T s_tile[LDT * NB];
+    __shared__ T s_col[2 * 8 * RPG];
+    __shared__ T s_row[2 * NB];
+    __shared__ T s_tau[NB], s_beta[NB];
+    __shared__ int s_last;
+    T* s_red = s_tile;
+    T* s_Sm = s_tile + 8 * NB;
+    T* s_T = s_Sm + NB * (NB + 1);
+
+    const QrDesc<T> d = descs[blockIdx.y];
+    if (!d.active || c0 >= d.nf) return;
+    const int nbk = min(NB, d.nf - c0);
+    const int mp = d.m - c0;
+    const TreeGeom g = tree_geom<T>(mp);
+    int node = blockIdx.x;
+    if (node >= g.L[0]) return;
+    const int tid = threadIdx.x, grp = tid >> 5, c = tid & 31;
+    const size_t ld = (size_t)d.ld;
+    T* W = d.W;
+    T p[RPG];
+
+    // ---- leaf: rows [row0, row0 + mt) of the panel columns
+    const int row0 = c0 + leaf_lo(node, mp, g.L[0]);
+    int mt = c0 + leaf_lo(node + 1, mp, g.L[0]) - row0;
+    for (int col = 0; col < NB; ++col)
+        for (int r = tid; r < mt; r += 256)
+            s_tile[col * LDT + r] = col < nbk ? W[(size_t)(c0 + col) * ld + row0 + r] : T(0);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RPG; ++i) {
+        const int r = 8 * i + grp;
+        p[i] = r < mt ? s_tile[c * LDT + r] : T(0);
+    }
+    __syncthreads();
+    node_qr<T>(p, mt, nbk, s_col, s_row, s_red, s_Sm, s_T, s_tau, s_beta);
+    {
+        T* Tg = d.Tm + (size_t)node_index(g, 0, node) * NB * NB;
+        for (int e = tid; e < NB * NB; e += 256) {
+            const int i = e % NB, j = e / NB;
+            Tg[e] = (i <= j && j < nbk) ? s_T[i * (NB + 1) + j] : T(0);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RPG; ++i) {
+        const int r = 8 * i + grp;
+        if (r < mt) s_tile[c * LDT + r] = p[i];
+    }
+    __syncthreads();
+    for (int col = 0; col < nbk; ++col)
+        for (int r = tid; r < mt; r += 256) W[(size_t)(c0 + col) * ld + row0 + r] = s_tile[col * LDT + r];
+
+    // ---- climb the tree: the last child to arrive factors the parent
+    for (int level = 1; level < g.levels; ++level) {
+        __threadfence();
+        __syncthreads();
+        const int parent = node / C::F;
+        const int iidx = internal_index(g, level, parent);
+        const int nch = min(C::F, g.L[level - 1] - parent * C::F);
+        if (tid == 0) {
+            const unsigned old = atomicAdd(&d.counters[iidx], 1u);
+            s_last = (old == (unsigned)(nch - 1));
+            if (s_last) d.counters[iidx] = 0u;
+        }
+        __syncthreads();
+        if (!s_last) return;
+        __threadfence();
+        node = parent;
+        mt = nch * NB;
+        // stacked upper-triangular R factors of the children
+        for (int e = tid; e < mt * NB; e += 256) {
+            const int col = e / mt, s = e % mt;
+            const int t = s / NB, r = s % NB;
+            T v = 0;
+            if (col < nbk && r <= col) {
+                const int child = node * C::F + t;
+                const int rb = c0 + leaf_lo(child * g.pow[level - 1], mp, g.L[0]);
+                v = W[(size_t)(c0 + col) * ld + rb + r];
+            }
+            s_tile[col * LDT + s] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < RPG; ++i) {
+            const int r = 8 * i + grp;
+            p[i] = r < mt ? s_tile[c * LDT + r] : T(0);
+        }
+        __syncthreads();
+        node_qr<T>(p, mt, nbk, s_col, s_row, s_red, s_Sm, s_T, s_tau, s_beta);
+        {
+            T* Tg = d.Tm + (size_t)node_index(g, level, node) * NB * NB;
+            for (int e = tid; e < NB * NB; e += 256) {
+                const int i = e % NB, j = e / NB;
+                Tg[e] = (i <= j && j < nbk) ? s_T[i * (NB + 1) + j] : T(0);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < RPG; ++i) {
+            const int r = 8 * i + grp;
+            if (r < mt) s_tile[c * LDT + r] = p[i];
+        }
+        __syncthreads();
+        // explicit reflectors of this node, and its R into the top rows
+        T* Vi = d.Vint + (size_t)iidx * C::MT_MAX * NB;
+        const int rbase = c0 + leaf_lo(node * g.pow[level], mp, g.L[0]);
+        for (int e = tid; e < C::MT_MAX * NB; e += 256) {
+            const int col = e / C::MT_MAX, s = e % C::MT_MAX;
+            T v = 0;
+            if (s < mt && col < nbk) v = s > col ? s_tile[col * LDT + s] : (s == col ? T(1) : T(0));
+            Vi[e] = v;
+        }
+        for (int e = tid; e < nbk * nbk; e += 256) {
+            const int col = e / nbk, s = e % nbk;
+            if (s <= col) W[(size_t)(c0 + col) * ld + rbase + s] = s_tile[col * LDT + s];
+        }
+    }
+    if (tid < nbk) d.diag[c0 + tid] = s_beta[tid];
+}
+
+// Apply the transpose of one tree level's block reflectors to a 64-column
+// tile of the trailing matrix: C <- C - V (T^T (V^T C)) for the node's rows.
+// Each wave owns 16 columns; the tile stays in MFMA accumulator layout in
+// registers (row block rb, lane (gq, ln) holds rows 16 rb + 4 gq + v, column
+// ln).  Both contractions over rows use the k-slices {16 rb + 4 gq + v : gq}
+// so that the accumulator registers are directly the B operand.
+template <typename T, int RB>
+__global__ __launch_bounds__(256) void k_update(const QrDesc<T>* __restrict__ descs, int c0, int level) {
+    using C = QrCfg<T>;
+    using M = Mfma<T>;
+    typedef typename M::v4 v4;
+    constexpr int NB = C::NB, VS = 36;
+    __shared__ T s_V[RB * 16 * VS];
+    __shared__ T s_T[NB * (NB + 1)];
+    __shared__ int s_rb[32];
+
+    const QrDesc<T> d = descs[blockIdx.z];
+    if (!d.active || c0 >= d.nf) return;
+    const int nbk = min(NB, d.nf - c0);
+    const int col0 = c0 + nbk + blockIdx.y * 64;
+    if (col0 >= d.ncols) return;
+    const int mp = d.m - c0;
+    const TreeGeom g = tree_geom<T>(mp);
+    if (level >= g.levels) return;
+    const int node = blockIdx.x;
+    if (node >= g.L[level]) return;
+    const int tid = threadIdx.x;
+    const size_t ld = (size_t)d.ld;
+    T* W = d.W;
+
+    int mt, lo = 0;
+    if (level == 0) {
+        lo = c0 + leaf_lo(node, mp, g.L[0]);
+        mt = c0 + leaf_lo(node + 1, mp, g.L[0]) - lo;
+    } else {
+        const int nch = min(C::F, g.L[level - 1] - node * C::F);
+        mt = nch * NB;
+        if (tid < nch) s_rb[tid] = c0 + leaf_lo((node * C::F + tid) * g.pow[level - 1], mp, g.L[0]);
+    }
+    const int rows_pad = ((mt + 15) >> 4) << 4;
+    if (level == 0) {
+        for (int e = tid; e < rows_pad * NB; e += 256) {
+            const int col = e / rows_pad, s = e % rows_pad;
+            T v = 0;
+            if (s < mt && col < nbk) v = s > col ? W[(size_t)(c0 + col) * ld + lo + s] : (s == col ? T(1) : T(0));
+            s_V[s * VS + col] = v;
+        }
+    } else {
+        const T* Vi = d.Vint + (size_t)internal_index(g, level, node) * C::MT_MAX * NB;
+        for (int e = tid; e < rows_pad * NB; e += 256) {
+            const int col = e / rows_pad, s = e % rows_pad;
+            s_V[s * VS + col] = (s < mt && col < nbk) ? Vi[(size_t)col * C::MT_MAX + s] : T(0);
+        }
+    }
+    {
+        const T* Tg = d.Tm + (size_t)node_index(g, level, node) * NB * NB;
+        for (int e = tid; e < NB * NB; e += 256) s_T[(e % NB) * (NB + 1) + e / NB] = Tg[e];
+    }
+    __syncthreads();
+
+    const int wave = tid >> 6, lane = tid & 63, gq = lane >> 4, ln = lane & 15;
+    const int col = col0 + wave * 16 + ln;
+    const bool colok = col < d.ncols;
+    const int rbe = rows_pad >> 4;
+    T* Wc = W + (size_t)col * ld;
+
+    v4 cr[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+        cr[rb] = v4{0, 0, 0, 0};
+        if (rb < rbe && colok) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int s = rb * 16 + gq * 4 + v;
+                if (s < mt) {
+                    int wr;
+                    if (level == 0) wr = lo + s;
+                    else wr = ((s & (NB - 1)) < nbk) ? s_rb[s / NB] + (s & (NB - 1)) : -1;
+                    if (wr >= 0) cr[rb][v] = Wc[wr];
+                }
+            }
+        }
+    }
+    // Wt = V^T C  (NB x 16): two 16x16 blocks
+    v4 w0 = v4{0, 0, 0, 0}, w1 = v4{0, 0, 0, 0};
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+        if (rb < rbe) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const T* vr = s_V + (rb * 16 + gq * 4 + v) * VS;
+                w0 = M::mma(vr[ln], cr[rb][v], w0);
+                w1 = M::mma(vr[16 + ln], cr[rb][v], w1);
+            }
+        }
+    }
+    // Y = T^T Wt
+    v4 y0 = v4{0, 0, 0, 0}, y1 = v4{0, 0, 0, 0};
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const T b = kb ? w1[j] : w0[j];
+            const int k = kb * 16 + gq * 4 + j;
+            y0 = M::mma(s_T[k * (NB + 1) + ln], b, y0);
+            y1 = M::mma(s_T[k * (NB + 1) + 16 + ln], b, y1);
+        }
+    }
+    // C -= V Y
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+        if (rb < rbe) {
+            const T* vr = s_V + (rb * 16 + ln) * VS;
+#pragma unroll
+            for (int pb = 0; pb < 2; ++pb) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const T b = pb ? y1[j] : y0[j];
+                    cr[rb] = M::mma(-vr[pb * 16 + gq * 4 + j], b, cr[rb]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+        if (rb < rbe && colok) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int s = rb * 16 + gq * 4 + v;
+                if (s < mt) {
+                    int wr;
+                    if (level == 0) wr = lo + s;
+                    else wr = ((s & (NB - 1)) < nbk) ? s_rb[s / NB] + (s & (NB - 1)) : -1;
+                    if (wr >= 0) Wc[wr] = cr[rb][v];
+                }
+            }
+        }
+    }
+}
+
+// Register-tile height (in 16-row blocks) is chosen per launch; only
+// instantiations whose LDS tile fits (MT_MAX rows) exist.
+template <typename T>
+static void launch_update(int rows, dim3 grid, hipStream_t s, const QrDesc<T>* d, int c0, int lev);
+template <>
+void launch_update<double>(int rows, dim3 grid, hipStream_t s, const QrDesc<double>* d, int c0, int lev) {
+    if (rows <= 256)
+        hipLaunchKernelGGL((k_update<double, 16>), grid, dim3(256), 0, s, d, c0, lev);
+    else
+        hipLaunchKernelGGL((k_update<double, 32>), grid, dim3(256), 0, s, d, c0, lev);
+}
+template <>
+void launch_update<float>(int rows, dim3 grid, hipStream_t s, const QrDesc<float>* d, int c0, int lev) {
+    if (rows <= 256)
+        hipLaunchKernelGGL((k_update<float, 16>), grid, dim3(256), 0, s, d, c0, lev);
+    else if (rows <= 512)
+        hipLaunchKernelGGL((k_update<float, 32>), grid, dim3(256), 0, s, d, c0, lev);
+    else
+        hipLaunchKernelGGL((k_update<float, 64>), grid, dim3(256), 0, s, d, c0, lev);
+}
+
+template <typename T>
+void qr_aug_batch(const QrDesc<T>* d_descs, const QrDesc<T>* h, int count, hipStream_t s) {
+    using C = QrCfg<T>;
+    int max_nf = 0;
+    for (int i = 0; i < count; ++i)
+        if (h[i].active) max_nf = max_nf > h[i].nf ? max_nf : h[i].nf;
+    for (int c0 = 0; c0 < max_nf; c0 += C::NB) {
+        int maxL[kMaxLevels] = {0, 0, 0, 0};
+        int maxlev = 0, maxleaf = 0, maxtrail = 0;
+        for (int i = 0; i < count; ++i) {
+            if (!h[i].active || c0 >= h[i].nf) continue;
+            const int mp = h[i].m - c0;
+            const TreeGeom g = tree_geom<T>(mp);
+            for (int l = 0; l < g.levels; ++l) maxL[l] = maxL[l] > g.L[l] ? maxL[l] : g.L[l];
+            maxlev = maxlev > g.levels ? maxlev : g.levels;
+            const int leaf = g.L[0] == 1 ? mp : (mp + g.L[0] - 1) / g.L[0];
+            maxleaf = maxleaf > leaf ? maxleaf : leaf;
+            const int nbk = h[i].nf - c0 < C::NB ? h[i].nf - c0 : C::NB;
+            const int trail = h[i].ncols - c0 - nbk;
+            maxtrail = maxtrail > trail ? maxtrail : trail;
+        }
+        if (maxL[0] == 0) continue;
+        hipLaunchKernelGGL(k_panel<T>, dim3(maxL[0], count), dim3(256), 0, s, d_descs, c0);
+        if (maxtrail <= 0) continue;
+        const int tiles = (maxtrail + 63) / 64;
+        for (int lev = 0; lev < maxlev; ++lev) {
+            const int rows = lev == 0 ? maxleaf : C::MT_MAX;
+            const dim3 grid(maxL[lev], tiles, count);
+            launch_update<T>(rows, grid, s, d_descs, c0, lev);
+        }
+    }
+}
+
+template void qr_aug_batch<double>(const QrDesc<double>*, const QrDesc<double>*, int, hipStream_t);
+template void qr_aug_batch<float>(const QrDesc<float>*, const QrDesc<float>*, int, hipStream_t);
+
+}  // namespace sdc

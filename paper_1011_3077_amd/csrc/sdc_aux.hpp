@@ -1,0 +1,55 @@
+// Descriptors and launchers of the supporting kernels (aux_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace sdc {
+
+enum EwOp { EW_PERMUTE = 0, EW_ADD = 1, EW_IDENTITY = 2, EW_SYM = 3 };
+
+// Element-wise op on a rows x n output (rows = n for square operands).
+struct EwDesc {
+    int op, n, rows;
+    const void* in; int ldi;
+    const void* in2; int ld2;
+    void* out; int ldo;
+    int trans, revP, revQ;
+    const double* sg;  // optional sign source, indexed by the source row
+    double alpha;
+    int active;
+};
+
+struct NormDesc {
+    const double* X; int ld, n, rows;
+    double* out;
+    int active;
+};
+
+struct SplitDesc {
+    const double* Ah; int lda;
+    const double* Bh; int ldb;  // null for the symmetric case
+    int n;
+    double* SA; double* SB;     // n x n suffix-sum scratch
+    const double* norms;        // [0] ||A||_1, [1] ||B||_1
+    double* e;                  // n
+    double* out;                // [0] k*, [1] e(k*)
+    int active;
+};
+
+struct GaussDesc {
+    double* G; int ld, n;
+    uint64_t seed;
+    int tag;
+    int active;
+};
+
+template <typename Tin, typename Tout>
+void ew_batch(const EwDesc* d, const EwDesc* h, int count, hipStream_t s);
+template <typename T>
+void fill(T* p, size_t n, T v, hipStream_t s);
+void norm1_batch(const NormDesc* d, const NormDesc* h, int count, hipStream_t s);
+void split_search_batch(const SplitDesc* d, const SplitDesc* h, int count, hipStream_t s);
+void orth_err_batch(const NormDesc* d, const NormDesc* h, int count, hipStream_t s);
+void gauss_batch(const GaussDesc* d, const GaussDesc* h, int count, hipStream_t s);
+
+}  // namespace sdc
