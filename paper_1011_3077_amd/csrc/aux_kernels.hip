@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc<T>* __restrict__ de
             const int n = n0 + wn * 32 + j * 16 + ln;
             if (n >= d.N) continue;
             for (int v = 0; v < 4; ++v) {
-                const int m = m0 + wm * 32 + i * 16 + gq * 4 + v;
+                const int m = m0 + wm * 32 + i * 16 + M::row(gq, v);
                 if (m >= d.M) continue;
                 T* cp = d.C + (size_t)n * d.ldc + m;
                 T r = d.alpha * acc[i][j][v];

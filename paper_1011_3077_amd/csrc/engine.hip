@@ -37,14 +37,20 @@ static constexpr double kRhoOneSide = 1e-3;  // see rank_from_rho
 // ---------------------------------------------------------------------------
 // Workspace and staging
 // ---------------------------------------------------------------------------
+// Bump allocator over the handle's workspace.  A sizing pass (base null)
+// measures; the carving pass must stay within cap, else `overflow` is set and
+// the caller refuses to launch anything.
 struct Carver {
     char* base;
+    size_t cap;
     size_t off = 0;
-    explicit Carver(char* b) : base(b) {}
+    bool overflow = false;
+    explicit Carver(char* b, size_t c = 0) : base(b), cap(c) {}
     template <class T> T* take(size_t n) {
         off = (off + 255) & ~size_t(255);
         T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
         off += n * sizeof(T);
+        if (base && off > cap) overflow = true;
         return p;
     }
 };
@@ -143,6 +149,7 @@ template <typename T> struct IrsSide {
     double rconv = NAN;
 };
 
+// Buffers of one IRS side; s.n must be set before the call.
 template <typename T> static void irs_layout(Carver& c, IrsSide<T>& s) {
     const size_t n = (size_t)s.n;
     s.W = c.take<T>(6 * n * n);
@@ -293,6 +300,8 @@ static void job_layout(Carver& c, JobWs& w) {
     const size_t n = (size_t)j.n;
     const int nsides = j.pencil ? 2 : 1;
     for (int s = 0; s < nsides; ++s) {
+        w.sf[s].n = j.n;
+        w.sd[s].n = j.n;
         if (w.fp32) {
             irs_layout(c, w.sf[s]);
             w.Apd[s] = c.take<double>(n * n);
@@ -664,8 +673,9 @@ int run_split_jobs(Handle& h, std::vector<SplitJob>& jobs) {
         layout(c0);
         CHK(ensure_ws(h, c0.off + 4096));
     }
-    Carver c(h.ws);
+    Carver c(h.ws, h.ws_size);
     double* norms_all = layout(c);
+    if (c.overflow) return SDC_ERR_NOMEM;
     CHK(ensure_desc(h, (size_t)(64 << 10) + jobs.size() * (size_t)(8 << 10)));
     h.desc_off = 0;
 
@@ -834,6 +844,8 @@ int run_irs_only(Handle& h, int n, const double* A, int lda, const double* B, in
         side.tau = opts.tau > 0 ? opts.tau : std::sqrt(eps);
         side.maxit = opts.maxit;
     };
+    sdd.n = n;
+    sff.n = n;
     auto layout = [&](Carver& c) -> double* {
         if (fp32) irs_layout(c, sff);
         else irs_layout(c, sdd);
@@ -844,8 +856,9 @@ int run_irs_only(Handle& h, int n, const double* A, int lda, const double* B, in
         layout(c0);
         CHK(ensure_ws(h, c0.off + 4096));
     }
-    Carver c(h.ws);
+    Carver c(h.ws, h.ws_size);
     double* norms = layout(c);
+    if (c.overflow) return SDC_ERR_NOMEM;
     CHK(ensure_desc(h, 64 << 10));
     h.desc_off = 0;
     int nonfinite, converged;

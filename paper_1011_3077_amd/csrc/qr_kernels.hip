@@ -251,9 +251,10 @@ __global__ __launch_bounds__(256) void k_panel(const QrDesc<T>* __restrict__ des
 // Apply the transpose of one tree level's block reflectors to a 64-column
 // tile of the trailing matrix: C <- C - V (T^T (V^T C)) for the node's rows.
 // Each wave owns 16 columns; the tile stays in MFMA accumulator layout in
-// registers (row block rb, lane (gq, ln) holds rows 16 rb + 4 gq + v, column
-// ln).  Both contractions over rows use the k-slices {16 rb + 4 gq + v : gq}
-// so that the accumulator registers are directly the B operand.
+// registers (row block rb, lane (gq, ln) holds rows 16 rb + row(gq, v),
+// column ln).  Both contractions over rows use the k-slices
+// {16 rb + row(gq, v) : gq} so that the accumulator registers are directly
+// the B operand.
 template <typename T, int RB>
 __global__ __launch_bounds__(256) void k_update(const QrDesc<T>* __restrict__ descs, int c0, int level) {
     using C = QrCfg<T>;
@@ -321,7 +322,7 @@ __global__ __launch_bounds__(256) void k_update(const QrDesc<T>* __restrict__ de
         if (rb < rbe && colok) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int s = rb * 16 + gq * 4 + v;
+                const int s = rb * 16 + M::row(gq, v);
                 if (s < mt) {
                     int wr;
                     if (level == 0) wr = lo + s;
@@ -338,7 +339,7 @@ __global__ __launch_bounds__(256) void k_update(const QrDesc<T>* __restrict__ de
         if (rb < rbe) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const T* vr = s_V + (rb * 16 + gq * 4 + v) * VS;
+                const T* vr = s_V + (rb * 16 + M::row(gq, v)) * VS;
                 w0 = M::mma(vr[ln], cr[rb][v], w0);
                 w1 = M::mma(vr[16 + ln], cr[rb][v], w1);
             }
@@ -351,7 +352,7 @@ __global__ __launch_bounds__(256) void k_update(const QrDesc<T>* __restrict__ de
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const T b = kb ? w1[j] : w0[j];
-            const int k = kb * 16 + gq * 4 + j;
+            const int k = kb * 16 + M::row(gq, j);
             y0 = M::mma(s_T[k * (NB + 1) + ln], b, y0);
             y1 = M::mma(s_T[k * (NB + 1) + 16 + ln], b, y1);
         }
@@ -366,7 +367,7 @@ __global__ __launch_bounds__(256) void k_update(const QrDesc<T>* __restrict__ de
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const T b = pb ? y1[j] : y0[j];
-                    cr[rb] = M::mma(-vr[pb * 16 + gq * 4 + j], b, cr[rb]);
+                    cr[rb] = M::mma(-vr[pb * 16 + M::row(gq, j)], b, cr[rb]);
                 }
             }
         }
@@ -376,7 +377,7 @@ __global__ __launch_bounds__(256) void k_update(const QrDesc<T>* __restrict__ de
         if (rb < rbe && colok) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int s = rb * 16 + gq * 4 + v;
+                const int s = rb * 16 + M::row(gq, v);
                 if (s < mt) {
                     int wr;
                     if (level == 0) wr = lo + s;
