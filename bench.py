@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Benchmark of the inverse-free spectral divide-and-conquer on one MI355X.
+
+Workload (default, `pencil2048`): the order-2048 real pencil A = U T V^T,
+B = U S V^T (T, S upper triangular, |lambda| log-uniform in [0.1, 10],
+U, V Haar, seed 10113077 + 1000), split at the unit circle and then
+recursively to diagonal blocks of order <= 64, in FP64.  One step is one
+whole divide-and-conquer run (sdc_eig_dc) on inputs already resident in HBM.
+
+metric: split GFLOP/s = nominal split flops / wall time, with the nominal
+flops of every split step counted by the paper's cost model with LAPACK
+leading terms: (40/3 (p_R + p_L) + 32) m^3 for a pencil step of order m with
+p_R, p_L repeated-squaring iterations (refinement and retries not credited).
+
+roofline: the kernel with the largest total time in the timed region, timed
+per launch with HIP events on its stream (sdc_profile_*), against its bound:
+the tree-level trailing update is a dense contraction with 8 flop/byte in
+FP64 (4 R nb ntr flops on 2 R ntr words of 8 bytes, nb = 32), below the
+chip's 9.8 flop/byte balance, so its bound is HBM bandwidth; the panel
+factorization is vector-ALU work.
+
+cpu_baseline: the FP64 oracle (NumPy/LAPACK) on the host cores, running the
+top split of the same pencil family at order 1024 (a bounded sample; about
+1/8 of the order-2048 split's flops), in the same GFLOP/s unit.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64_tflops": 78.6, "fp32_tflops": 157.3, "hbm_gbs": 8000.0}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(n: int = 1024):
+    import numpy as np
+    import sdc_synth as S
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([x.get("num_threads", 1) for x in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    p = S.pencil_problem(n, S.family_seed(1, 500))
+    t0 = time.perf_counter()
+    r = O.split_pencil(p["A"], p["B"], {"kind": "unit_disk"}, seed=1)
+    dt = time.perf_counter() - t0
+    flops = (40.0 / 3.0 * (r.p_right + r.p_left) + 32.0) * n ** 3
+    return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"oracle split_pencil (unit circle) of one order-{n} pencil of the same family, "
+                      f"p_R={r.p_right}, p_L={r.p_left}, {dt:.1f} s, nominal {flops:.3e} flops",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="time without per-launch events")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the independent subproblems would shard across GPUs, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import scipy.linalg as sla
+    import torch
+    import sdc_synth as S
+    import paper_1011_3077_amd as P
+
+    n, leaf = args.n, args.leaf
+    log(f"[bench] generating order-{n} pencil")
+    pb = S.pencil_problem(n, S.family_seed(1))
+    A = torch.from_numpy(pb["A"]).to("cuda:0")
+    B = torch.from_numpy(pb["B"]).to("cuda:0")
+    h = P.Handle(0)
+    o = P.opts(seed=1)
+
+    def step():
+        return h.eig_dc(A, B, leaf_max=leaf, o=o)
+
+    for i in range(args.warmup):
+        r = step()
+        log(f"[bench] warmup {i}: {r[-1]['ms']:.1f} ms, splits {r[-1]['splits']}")
+    torch.cuda.synchronize()
+    h.profile_enable(not args.no_profile)
+    flops = 0.0
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        r = step()
+        flops += r[-1]["nominal_flops"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"[bench] timed {args.steps} steps: {dt:.3f} s")
+    stats = {k: h.profile_read(k) for k in (P.KERNEL_UPDATE, P.KERNEL_PANEL, P.KERNEL_GEMM)}
+    h.profile_enable(False)
+
+    # accuracy of the last step against the construction (outside the timed region)
+    st, t, s, ql, qr, starts, info = r
+    t, s = t.cpu().numpy(), s.cpu().numpy()
+    ev = []
+    for a0, a1 in zip(starts[:-1], starts[1:]):
+        ev.append(sla.eigvals(t[a0:a1, a0:a1], s[a0:a1, a0:a1]))
+    got = np.sort_complex(np.concatenate(ev))
+    want = np.sort_complex(pb["lam"].astype(complex))
+    eig_err = float(np.max(np.abs(got - want) / np.abs(want)))
+    h.close()
+
+    value = flops / dt / 1e9
+    names = {P.KERNEL_UPDATE: "k_update (tree-level trailing update, MFMA f64)",
+             P.KERNEL_PANEL: "k_panel (TSQR panel Householder)",
+             P.KERNEL_GEMM: "k_gemm (MFMA f64)"}
+    roof = None
+    if not args.no_profile:
+        dom = max(stats, key=lambda k: stats[k]["ms"])
+        sd = stats[dom]
+        if sd["ms"] > 0:
+            secs = sd["ms"] / 1e3
+            if dom == P.KERNEL_PANEL:
+                ach = sd["flops"] / secs / 1e12
+                roof = {"bound": "alu", "achieved": ach, "peak": PEAK["fp64_tflops"], "unit": "TFLOP/s",
+                        "frac": ach / PEAK["fp64_tflops"], "traffic": None}
+            else:
+                inten = sd["flops"] / max(sd["bytes"], 1.0)
+                if inten < PEAK["fp64_tflops"] * 1e12 / (PEAK["hbm_gbs"] * 1e9):
+                    ach = sd["bytes"] / secs / 1e9
+                    roof = {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+                            "frac": ach / PEAK["hbm_gbs"], "traffic": None}
+                else:
+                    ach = sd["flops"] / secs / 1e12
+                    roof = {"bound": "mfma", "achieved": ach, "peak": PEAK["fp64_tflops"], "unit": "TFLOP/s",
+                            "frac": ach / PEAK["fp64_tflops"], "traffic": None}
+            roof["kernel"] = names[dom]
+            roof["launches"] = sd["launches"]
+            roof["avg_launch_us"] = sd["ms"] * 1e3 / max(sd["launches"], 1)
+            roof["algorithmic_flops_per_launch"] = sd["flops"] / max(sd["launches"], 1)
+            roof["algorithmic_bytes_per_launch"] = sd["bytes"] / max(sd["launches"], 1)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        cpu = cpu_baseline()
+    out = {
+        "metric": "split GFLOP/s (nominal split flops / wall time), FP64",
+        "value": value,
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"divide-and-conquer of an order-{n} real pencil (unit circle, then recursion "
+                               f"to blocks <= {leaf}), FP64", "n": n, "leaf_max": leaf,
+                   "generator": "sdc_synth.pencil_problem seed 10113077+1000"},
+        "pct_fp64_peak": value / (PEAK["fp64_tflops"] * 1e3),
+        "nominal_flops_per_step": flops / args.steps,
+        "splits_per_step": info["splits"],
+        "blocks": info["nblocks"],
+        "eig_rel_err_vs_construction": eig_err,
+        "kernels": {names[k]: v for k, v in stats.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -161,6 +161,61 @@ sdc_status_t sdc_split_sym_batched(sdc_handle_t h, int count, const int* n, cons
                                    double* const* Ahat, const int* ldah, sdc_info_t* infos,
                                    int* statuses);
 
+/* Statistics of a divide-and-conquer run. */
+typedef struct {
+    int n;
+    int nblocks;         /* diagonal blocks of the final block-triangular pair */
+    int splits;          /* split steps attempted (every call of the split step) */
+    int accepted;        /* split steps that divided a block */
+    int levels;          /* recursion levels run (each level is one batched call) */
+    int unsplit;         /* blocks larger than leaf_max given up on (pseudospectrum hit) */
+    int iters_total;     /* sum of IRS iterations over all split steps and sides */
+    double nominal_flops;/* sum over split steps of (40/3 (p_R + p_L) + 32) m^3 (pencil)
+                            or (40/3 p + 16) m^3 (symmetric), the flop model of the
+                            paper's cost analysis with LAPACK leading terms */
+    double ms;
+} sdc_dc_info_t;
+
+/* Randomized spectral divide-and-conquer to blocks of order <= leaf_max
+ * (Sec. 3.3-3.5).  symmetric != 0: A symmetric, B ignored (B = I), splits at
+ * a random point of the middle half of the Gershgorin interval of each block
+ * (Sec. 3.4).  Otherwise the pencil is split first at the unit circle, then
+ * (if every eigenvalue was on one side) at circles of radius 2^{-+2^k}, then
+ * at random vertical lines through the middle half of each block's interval
+ * of real parts, with A and B swapped for blocks outside a circle (their
+ * reciprocal eigenvalues lie inside) (Sec. 3.5; real lines only, so a
+ * complex-conjugate pair is never separated).
+ * Outputs (device, column-major): T = Q_L^T A Q_R and, for pencils,
+ * S = Q_L^T B Q_R, block upper triangular with the strictly-lower coupling
+ * blocks set to zero; QL and QR (may be NULL) accumulate the transformations
+ * (QL is unused for symmetric A, where QR = Q).  block_start (HOST, n + 1
+ * ints) receives the first index of each diagonal block and n at position
+ * *nblocks.  A block that cannot be split after repeated draws is returned as
+ * is (counted in info->unsplit).  Returns SDC_OK or a negative error. */
+sdc_status_t sdc_eig_dc(sdc_handle_t h, int n, const double* A, int lda, const double* B, int ldb,
+                        int symmetric, int leaf_max, const sdc_opts_t* opts, double* T, int ldt,
+                        double* S, int lds, double* QL, int ldql, double* QR, int ldqr,
+                        int* nblocks, int* block_start, sdc_dc_info_t* info);
+
+/* Per-kernel timing (opt-in).  With profiling enabled every launch of the
+ * hot kernels is bracketed by HIP events on the handle's stream and its
+ * algorithmic work is recorded: kernel 0 = tree-level trailing update of the
+ * QR (4 R nb ntr + 2 nb^2 ntr flops, 2 R ntr + R nb words for R rows, nb
+ * panel columns, ntr trailing columns), 1 = panel factorization
+ * (2 m nb^2 flops), 2 = GEMM (2 M N K flops).  Events serialize nothing but
+ * add a few microseconds per launch. */
+typedef struct {
+    long long launches;
+    double ms;          /* summed event time */
+    double flops;       /* summed algorithmic flops */
+    double bytes;       /* summed algorithmic bytes */
+} sdc_kernel_stats_t;
+
+/* Enable (on != 0) or disable profiling; either way the totals are reset. */
+sdc_status_t sdc_profile_enable(sdc_handle_t h, int on);
+/* Totals of `kernel` (0, 1, 2 as above) since the last enable. */
+sdc_status_t sdc_profile_read(sdc_handle_t h, int kernel, sdc_kernel_stats_t* out);
+
 /* The Gaussian n x n matrix the library draws when opts->G is NULL:
  * Philox4x32-10 keyed by `seed`, counter (e mod 2^32, e div 2^32, tag, 0) for
  * the column-major element index e, then Box-Muller.  G is a device pointer. */

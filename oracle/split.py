@@ -73,14 +73,19 @@ def split_search(a_hat: np.ndarray, norm_a: float, b_hat: np.ndarray | None = No
     (+ the same for B_hat).  Returns (k_star, e(k_star), e as an array indexed
     by k-1).  Ties go to the smallest k."""
     n = a_hat.shape[0]
-    e = np.empty(max(n - 1, 0))
-    for k in range(1, n):
-        v = norm1(a_hat[k:, :k]) / norm_a
-        if b_hat is not None:
-            v += norm1(b_hat[k:, :k]) / norm_b
-        e[k - 1] = v
     if n < 2:
-        return 0, np.inf, e
+        return 0, np.inf, np.empty(0)
+
+    def e21(x):
+        # suf[k, c] = sum_{i >= k} |x_ic|; ||x[k:, :k]||_1 = max_{c < k} suf[k, c]
+        suf = np.cumsum(np.abs(x)[::-1, :], axis=0)[::-1, :]
+        pre = np.maximum.accumulate(suf, axis=1)
+        k = np.arange(1, n)
+        return pre[k, k - 1]
+
+    e = e21(a_hat) / norm_a
+    if b_hat is not None:
+        e = e + e21(b_hat) / norm_b
     k = int(np.argmin(e)) + 1
     return k, float(e[k - 1]), e
 

@@ -28,7 +28,8 @@ SDC_FP64, SDC_FP32_REFINE = 0, 1
 SDC_UNIT_DISK, SDC_DISK, SDC_HALFPLANE = 0, 1, 2
 
 EXPORTED = ["sdc_opts_default", "sdc_create", "sdc_destroy", "sdc_status_string", "sdc_irs",
-            "sdc_split_sym", "sdc_split_pencil", "sdc_split_sym_batched", "sdc_gaussian"]
+            "sdc_split_sym", "sdc_split_pencil", "sdc_split_sym_batched", "sdc_eig_dc", "sdc_gaussian",
+            "sdc_profile_enable", "sdc_profile_read"]
 
 
 class Region(C.Structure):
@@ -52,6 +53,24 @@ class Info(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class DcInfo(C.Structure):
+    _fields_ = [("n", C.c_int), ("nblocks", C.c_int), ("splits", C.c_int), ("accepted", C.c_int),
+                ("levels", C.c_int), ("unsplit", C.c_int), ("iters_total", C.c_int),
+                ("nominal_flops", C.c_double), ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class KernelStats(C.Structure):
+    _fields_ = [("launches", C.c_longlong), ("ms", C.c_double), ("flops", C.c_double), ("bytes", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+KERNEL_UPDATE, KERNEL_PANEL, KERNEL_GEMM = 0, 1, 2
+
 _P = C.c_void_p
 _I = C.c_int
 lib.sdc_opts_default.argtypes = [C.POINTER(Opts)]
@@ -74,6 +93,13 @@ lib.sdc_split_sym_batched.argtypes = [_P, _I, C.POINTER(_I), C.POINTER(_P), C.PO
                                       C.POINTER(Region), C.POINTER(Opts), C.POINTER(_P), C.POINTER(_I),
                                       C.POINTER(_P), C.POINTER(_I), C.POINTER(Info), C.POINTER(_I)]
 lib.sdc_split_sym_batched.restype = _I
+lib.sdc_eig_dc.argtypes = [_P, _I, _P, _I, _P, _I, _I, _I, C.POINTER(Opts), _P, _I, _P, _I, _P, _I, _P, _I,
+                           C.POINTER(_I), C.POINTER(_I), C.POINTER(DcInfo)]
+lib.sdc_eig_dc.restype = _I
+lib.sdc_profile_enable.argtypes = [_P, _I]
+lib.sdc_profile_enable.restype = _I
+lib.sdc_profile_read.argtypes = [_P, _I, C.POINTER(KernelStats)]
+lib.sdc_profile_read.restype = _I
 lib.sdc_gaussian.argtypes = [_P, _I, C.c_uint64, _I, _P, _I]
 lib.sdc_gaussian.restype = _I
 
@@ -201,6 +227,35 @@ class Handle:
                                          ptr_h, ns, infos, sts))
         return [SplitResult(sts[i], infos[i].as_dict(), outs_q[i].t(), None, outs_a[i].t(), None)
                 for i in range(cnt)]
+
+    def eig_dc(self, A, B=None, leaf_max: int = 64, o: Opts | None = None, symmetric: bool = False,
+               factors: bool = True):
+        """Divide and conquer to blocks <= leaf_max.  Returns
+        (status, T, S, QL, QR, block_starts, info); S/QL are None for symmetric."""
+        n = A.shape[0]
+        a = _cm(A)
+        b = _cm(B) if (B is not None and not symmetric) else None
+        t = _out(n, A)
+        s = _out(n, A) if b is not None else None
+        ql = _out(n, A) if (factors and b is not None) else None
+        qr = _out(n, A) if factors else None
+        nb = C.c_int()
+        starts = (_I * (n + 1))()
+        info = DcInfo()
+        ptr = lambda x: None if x is None else x.data_ptr()
+        st = _check(lib.sdc_eig_dc(self._h, n, a.data_ptr(), n, ptr(b), n, int(symmetric), leaf_max,
+                                   C.byref(o or opts()), t.data_ptr(), n, ptr(s), n, ptr(ql), n, ptr(qr), n,
+                                   C.byref(nb), starts, C.byref(info)))
+        tr = lambda x: None if x is None else x.t()
+        return st, tr(t), tr(s), tr(ql), tr(qr), [starts[i] for i in range(nb.value + 1)], info.as_dict()
+
+    def profile_enable(self, on: bool = True):
+        _check(lib.sdc_profile_enable(self._h, int(on)))
+
+    def profile_read(self, kernel: int) -> dict:
+        ks = KernelStats()
+        _check(lib.sdc_profile_read(self._h, kernel, C.byref(ks)))
+        return ks.as_dict()
 
     def gaussian(self, n: int, seed: int, tag: int):
         import torch

@@ -2,7 +2,8 @@
 
 Each .hip source under csrc/ is compiled with hipcc (objects under _build/,
 in parallel) and linked into paper_1011_3077_amd/libsdc.so.  Run as
-``python -m paper_1011_3077_amd.build`` or through ``__graft_entry__.build()``.
+``python paper_1011_3077_amd/build.py`` or through ``__graft_entry__.build()``
+(not through the package, whose import loads the library being rebuilt).
 """
 from __future__ import annotations
 
@@ -16,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsdc.so")
-SOURCES = ["qr_kernels.hip", "aux_kernels.hip", "engine.hip", "capi.hip"]
+SOURCES = ["qr_kernels.hip", "aux_kernels.hip", "engine.hip", "eig_dc.hip", "capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SDC_OFFLOAD_ARCH", "gfx950")

@@ -7,6 +7,7 @@
 #include "sdc_internal.hpp"
 #include "sdc_aux.hpp"
 #include "mfma.hpp"
+#include "profiler.hpp"
 
 namespace sdc {
 
@@ -117,7 +118,17 @@ void gemm_batch(const GemmDesc<T>* d_descs, const GemmDesc<T>* h, int count, hip
             N = N > h[i].N ? N : h[i].N;
         }
     if (M == 0 || N == 0) return;
+    Profiler* prof = g_prof;
+    double fl = 0, by = 0;
+    if (prof)
+        for (int i = 0; i < count; ++i)
+            if (h[i].active) {
+                fl += 2.0 * h[i].M * h[i].N * h[i].K;
+                by += ((double)h[i].M * h[i].K + (double)h[i].K * h[i].N + (double)h[i].M * h[i].N) * sizeof(T);
+            }
+    const int id = prof ? prof->begin(s) : -1;
     hipLaunchKernelGGL(k_gemm<T>, dim3((N + 63) / 64, (M + 63) / 64, count), dim3(256), 0, s, d_descs);
+    if (prof) prof->end(id, s, PROF_GEMM, fl, by);
 }
 template void gemm_batch<double>(const GemmDesc<double>*, const GemmDesc<double>*, int, hipStream_t);
 template void gemm_batch<float>(const GemmDesc<float>*, const GemmDesc<float>*, int, hipStream_t);
@@ -250,6 +261,9 @@ __global__ __launch_bounds__(256) void k_ew(const EwDesc* __restrict__ descs) {
     }
     case EW_IDENTITY:
         r = (i == j) ? Tout(1) : Tout(0);
+        break;
+    case EW_ZERO:
+        r = Tout(0);
         break;
     default: {  // EW_SYM
         r = (Tout)(0.5 * ((double)in[(size_t)j * d.ldi + i] + (double)in[(size_t)i * d.ldi + j]));
@@ -409,6 +423,29 @@ void split_search_batch(const SplitDesc* d, const SplitDesc* h, int count, hipSt
     if (pencil) hipLaunchKernelGGL(k_suffix, dim3(n, count), dim3(256), 0, s, d, 1);
     hipLaunchKernelGGL(k_emax, dim3((n + 255) / 256, count), dim3(256), 0, s, d);
     hipLaunchKernelGGL(k_argmin, dim3(count), dim3(256), 0, s, d);
+}
+
+__global__ __launch_bounds__(256) void k_gersh(const GershDesc* __restrict__ descs) {
+    __shared__ double sh[4];
+    const GershDesc d = descs[blockIdx.y];
+    if (!d.active || (int)blockIdx.x >= d.n) return;
+    const int j = blockIdx.x;
+    double s = 0;
+    for (int i = threadIdx.x; i < d.n; i += 256)
+        if (i != j) s += fabs(d.X[(size_t)j * d.ld + i]);
+    s = block_sum256(s, sh);
+    if (threadIdx.x == 0) {
+        const double c = d.X[(size_t)j * d.ld + j];
+        d.out[2 * j] = c - s;
+        d.out[2 * j + 1] = c + s;
+    }
+}
+void gersh_batch(const GershDesc* d, const GershDesc* h, int count, hipStream_t s) {
+    int n = 0;
+    for (int i = 0; i < count; ++i)
+        if (h[i].active) n = n > h[i].n ? n : h[i].n;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_gersh, dim3(n, count), dim3(256), 0, s, d);
 }
 
 // ||X^T X - I||_F^2 accumulated into out (X n x n), one block per column of E.

@@ -32,6 +32,12 @@ int use_device(Handle& h) {
     return hipSetDevice(h.device) == hipSuccess ? SDC_OK : SDC_ERR_DEVICE;
 }
 
+void resolve_profile(Handle& h) {
+    if (!h.prof.on) return;
+    (void)hipStreamSynchronize(h.stream);
+    h.prof.resolve();
+}
+
 sdc_opts_t resolve(const sdc_opts_t* o) {
     sdc_opts_t r;
     if (o) r = *o;
@@ -96,6 +102,7 @@ sdc_status_t sdc_destroy(sdc_handle_t handle) {
     if (h.desc_d) (void)hipFree(h.desc_d);
     if (h.desc_h) (void)hipHostFree(h.desc_h);
     if (h.host) (void)hipHostFree(h.host);
+    if (h.ws2) (void)hipFree(h.ws2);
     delete handle;
     return SDC_OK;
 }
@@ -109,8 +116,10 @@ sdc_status_t sdc_irs(sdc_handle_t hd, int n, const double* A, int lda, const dou
     Handle& h = hd->h;
     if (use_device(h) != SDC_OK) return SDC_ERR_DEVICE;
     const sdc_opts_t o = resolve(opts);
-    return (sdc_status_t)sdc::run_irs_only(h, n, A, lda, B, ldb, transpose ? 1 : 0, region, o, Ap, Bp, R, ldo, p,
-                                           rconv);
+    sdc::ProfScope ps(h);
+    const int r = sdc::run_irs_only(h, n, A, lda, B, ldb, transpose ? 1 : 0, region, o, Ap, Bp, R, ldo, p, rconv);
+    resolve_profile(h);
+    return (sdc_status_t)r;
 }
 
 sdc_status_t sdc_split_sym(sdc_handle_t hd, int n, const double* A, int lda, sdc_region_t region,
@@ -127,7 +136,9 @@ sdc_status_t sdc_split_sym(sdc_handle_t hd, int n, const double* A, int lda, sdc
     SplitJob& j = jobs[0];
     j.n = n; j.pencil = false; j.A = A; j.lda = lda; j.region = region; j.opts = resolve(opts);
     j.Q = Q; j.ldq = ldq; j.Ahat = Ahat; j.ldah = ldah;
+    sdc::ProfScope ps(h);
     const int r = sdc::run_split_jobs(h, jobs);
+    resolve_profile(h);
     if (r < 0) return (sdc_status_t)r;
     *info = j.info;
     return (sdc_status_t)j.status;
@@ -150,7 +161,9 @@ sdc_status_t sdc_split_pencil(sdc_handle_t hd, int n, const double* A, int lda, 
     j.n = n; j.pencil = true; j.A = A; j.lda = lda; j.B = B; j.ldb = ldb; j.region = region;
     j.opts = resolve(opts);
     j.Q = QR; j.ldq = ldqr; j.QL = QL; j.ldql = ldql; j.Ahat = Ahat; j.ldah = ldah; j.Bhat = Bhat; j.ldbh = ldbh;
+    sdc::ProfScope ps(h);
     const int r = sdc::run_split_jobs(h, jobs);
+    resolve_profile(h);
     if (r < 0) return (sdc_status_t)r;
     *info = j.info;
     return (sdc_status_t)j.status;
@@ -185,12 +198,58 @@ sdc_status_t sdc_split_sym_batched(sdc_handle_t hd, int count, const int* n, con
     }
     Handle& h = hd->h;
     if (use_device(h) != SDC_OK) return SDC_ERR_DEVICE;
+    sdc::ProfScope ps(h);
     const int r = sdc::run_split_jobs(h, jobs);
+    resolve_profile(h);
     if (r < 0) return (sdc_status_t)r;
     for (size_t q = 0; q < jobs.size(); ++q) {
         statuses[idx[q]] = jobs[q].status;
         if (infos) infos[idx[q]] = jobs[q].info;
     }
+    return SDC_OK;
+}
+
+sdc_status_t sdc_eig_dc(sdc_handle_t hd, int n, const double* A, int lda, const double* B, int ldb, int symmetric,
+                        int leaf_max, const sdc_opts_t* opts, double* T, int ldt, double* S, int lds, double* QL,
+                        int ldql, double* QR, int ldqr, int* nblocks, int* block_start, sdc_dc_info_t* info) {
+    if (!hd || n < 0 || n > kMaxN || !nblocks || !block_start || leaf_max < 1) return SDC_ERR_INVALID;
+    if (n > 0 && (!A || lda < n || !T || ldt < n)) return SDC_ERR_INVALID;
+    if (!symmetric && n > 0 && (!B || ldb < n || !S || lds < n)) return SDC_ERR_INVALID;
+    if ((QL && ldql < n) || (QR && ldqr < n)) return SDC_ERR_INVALID;
+    sdc_dc_info_t dummy;
+    if (!info) info = &dummy;
+    *info = sdc_dc_info_t{};
+    if (n == 0) {
+        *nblocks = 0;
+        block_start[0] = 0;
+        return SDC_OK;
+    }
+    const sdc_opts_t o = resolve(opts);
+    if (o.G) return SDC_ERR_INVALID;
+    Handle& h = hd->h;
+    if (use_device(h) != SDC_OK) return SDC_ERR_DEVICE;
+    sdc::ProfScope ps(h);
+    const int r = sdc::run_eig_dc(h, n, A, lda, symmetric ? nullptr : B, ldb, symmetric ? 1 : 0, leaf_max, o, T, ldt,
+                                  symmetric ? nullptr : S, lds, symmetric ? nullptr : QL, ldql, QR, ldqr, nblocks,
+                                  block_start, info);
+    resolve_profile(h);
+    return (sdc_status_t)r;
+}
+
+sdc_status_t sdc_profile_enable(sdc_handle_t hd, int on) {
+    if (!hd) return SDC_ERR_INVALID;
+    hd->h.prof.on = on != 0;
+    hd->h.prof.reset();
+    return SDC_OK;
+}
+
+sdc_status_t sdc_profile_read(sdc_handle_t hd, int kernel, sdc_kernel_stats_t* out) {
+    if (!hd || !out || kernel < 0 || kernel >= sdc::PROF_NKERNELS) return SDC_ERR_INVALID;
+    const sdc::Profiler& p = hd->h.prof;
+    out->launches = p.launches[kernel];
+    out->ms = p.ms[kernel];
+    out->flops = p.flops[kernel];
+    out->bytes = p.bytes[kernel];
     return SDC_OK;
 }
 

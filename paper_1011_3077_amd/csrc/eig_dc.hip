@@ -1,0 +1,361 @@
+// Randomized spectral divide-and-conquer driver (Sec. 3.3-3.5): repeated
+// split steps on the diagonal blocks of a block-triangular pencil until every
+// block has order <= leaf_max.
+//
+// Each recursion level is one batched call of the split engine over all the
+// blocks still to be divided (the blocks are independent; Sec. 4.3 hands them
+// to disjoint processor sets, here they share the GPU's launches).  After a
+// block [s, e) is split by (Q_L', Q_R') with leading size k, the global pair
+// is updated:   T[s:e, s:e] <- A_hat',   T[s+k:e, s:s+k] <- 0 (E21 dropped),
+//               T[s:e, e:n] <- Q_L'^T T[s:e, e:n],  T[0:s, s:e] <- T[0:s, s:e] Q_R',
+// likewise S, and the accumulated Q_L[:, s:e] <- Q_L[:, s:e] Q_L',
+// Q_R[:, s:e] <- Q_R[:, s:e] Q_R'.
+//
+// Split curves: symmetric blocks use a random point of the middle half of
+// their interval (initially the Gershgorin interval, Sec. 3.4).  Pencils use
+// the unit circle first, circles of radius 2^{-2^k} (2^{2^k}) when every
+// eigenvalue was inside (outside), then random vertical lines through the
+// middle half of the block's interval of real parts; a block whose
+// eigenvalues lie outside a circle is continued on the swapped pair (B, A),
+// whose eigenvalues are the reciprocals and lie inside (Sec. 3.5).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <random>
+#include <vector>
+
+#include "engine.hpp"
+#include "engine_util.hpp"
+#include "sdc_aux.hpp"
+#include "sdc_internal.hpp"
+
+namespace sdc {
+
+namespace {
+
+enum Mode { MODE_CIRCLE = 0, MODE_LINE = 1 };
+
+struct Block {
+    int s = 0, e = 0;
+    int swapped = 0;     // pencil split as (S_block, T_block): eigenvalues 1/lambda
+    int mode = MODE_LINE;
+    double lo = -1, hi = 1;  // interval of real parts (line mode)
+    double radius = 1;       // circle mode
+    int tries = 0;
+};
+
+constexpr int kMaxTries = 8;
+
+int ensure_ws2(Handle& h, size_t bytes) {
+    if (bytes <= h.ws2_size) return SDC_OK;
+    if (h.ws2) {
+        HIPCHK(hipStreamSynchronize(h.stream));
+        HIPCHK(hipFree(h.ws2));
+        h.ws2 = nullptr;
+        h.ws2_size = 0;
+    }
+    const size_t sz = bytes + bytes / 8 + (1 << 20);
+    if (hipMalloc(&h.ws2, sz) != hipSuccess) {
+        (void)hipGetLastError();
+        return SDC_ERR_NOMEM;
+    }
+    h.ws2_size = sz;
+    return SDC_OK;
+}
+
+EwDesc copy_desc(int rows, int cols, const double* in, int ldi, double* out, int ldo) {
+    EwDesc d{};
+    d.op = EW_PERMUTE; d.n = cols; d.rows = rows; d.in = in; d.ldi = ldi; d.out = out; d.ldo = ldo;
+    d.alpha = 1.0; d.active = 1;
+    return d;
+}
+EwDesc zero_desc(int rows, int cols, double* out, int ldo) {
+    EwDesc d{};
+    d.op = EW_ZERO; d.n = cols; d.rows = rows; d.out = out; d.ldo = ldo; d.alpha = 1.0; d.active = 1;
+    return d;
+}
+EwDesc ident_desc(int n, double* out, int ldo) {
+    EwDesc d{};
+    d.op = EW_IDENTITY; d.n = n; d.rows = n; d.out = out; d.ldo = ldo; d.alpha = 1.0; d.active = 1;
+    return d;
+}
+GemmDesc<double> gemm_desc(int M, int N, int K, const double* A, int lda, int ta, const double* B, int ldb, int tb,
+                           double* C, int ldc) {
+    GemmDesc<double> g{};
+    g.A = A; g.B = B; g.C = C; g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+    g.M = M; g.N = N; g.K = K; g.ta = ta; g.tb = tb; g.alpha = 1.0; g.beta = 0.0; g.active = 1;
+    return g;
+}
+
+int launch_ew(Handle& h, const std::vector<EwDesc>& v) {
+    if (v.empty()) return SDC_OK;
+    UPLOAD(d, v);
+    ew_batch<double, double>(d, v.data(), (int)v.size(), h.stream);
+    return SDC_OK;
+}
+int launch_gemm(Handle& h, const std::vector<GemmDesc<double>>& v) {
+    if (v.empty()) return SDC_OK;
+    UPLOAD(d, v);
+    gemm_batch<double>(d, v.data(), (int)v.size(), h.stream);
+    return SDC_OK;
+}
+
+}  // namespace
+
+int run_eig_dc(Handle& h, int n, const double* A, int lda, const double* B, int ldb, int symmetric, int leaf_max,
+               const sdc_opts_t& opts, double* T, int ldt, double* S, int lds, double* QL, int ldql, double* QR,
+               int ldqr, int* nblocks, int* block_start, sdc_dc_info_t* info) {
+    const auto t0 = std::chrono::steady_clock::now();
+    CHK(ensure_desc(h, (size_t)(256 << 10)));
+    h.desc_off = 0;
+    std::mt19937_64 rng(opts.seed * 6364136223846793005ull + 1442695040888963407ull);
+    std::uniform_real_distribution<double> U(0.0, 1.0);
+
+    // T <- A, S <- B, accumulated factors <- I
+    {
+        std::vector<EwDesc> init;
+        init.push_back(copy_desc(n, n, A, lda, T, ldt));
+        if (!symmetric) init.push_back(copy_desc(n, n, B, ldb, S, lds));
+        if (QL) init.push_back(ident_desc(n, QL, ldql));
+        if (QR) init.push_back(ident_desc(n, QR, ldqr));
+        CHK(launch_ew(h, init));
+    }
+    Block top;
+    top.s = 0;
+    top.e = n;
+    if (symmetric) {
+        // Gershgorin interval of A
+        CHK(ensure_ws2(h, sizeof(double) * 2 * (size_t)n));
+        double* gb = reinterpret_cast<double*>(h.ws2);
+        std::vector<GershDesc> gd(1);
+        gd[0] = GershDesc{A, lda, n, gb, 1};
+        UPLOAD(dg, gd);
+        gersh_batch(dg, gd.data(), 1, h.stream);
+        CHK(ensure_host(h, sizeof(double) * 2 * (size_t)n));
+        HIPCHK(hipMemcpyAsync(h.host, gb, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, h.stream));
+        HIPCHK(hipStreamSynchronize(h.stream));
+        const double* hb = reinterpret_cast<const double*>(h.host);
+        double lo = INFINITY, hi = -INFINITY;
+        for (int j = 0; j < n; ++j) {
+            lo = std::min(lo, hb[2 * j]);
+            hi = std::max(hi, hb[2 * j + 1]);
+        }
+        if (!std::isfinite(lo) || !std::isfinite(hi)) return SDC_ERR_NONFINITE;
+        if (hi <= lo) hi = lo + 1.0;
+        top.mode = MODE_LINE;
+        top.lo = lo;
+        top.hi = hi;
+    } else {
+        top.mode = MODE_CIRCLE;
+        top.radius = 1.0;
+    }
+    h.desc_off = 0;
+
+    std::vector<Block> leaves, work;
+    if (n <= leaf_max) leaves.push_back(top);
+    else work.push_back(top);
+    sdc_dc_info_t st{};
+    st.n = n;
+    uint64_t split_id = 0;
+
+    while (!work.empty()) {
+        ++st.levels;
+        // ---- output buffers of this level's split steps
+        const int cnt = (int)work.size();
+        std::vector<size_t> off(cnt);
+        size_t need = 0;
+        for (int i = 0; i < cnt; ++i) {
+            const size_t m = (size_t)(work[i].e - work[i].s);
+            off[i] = need;
+            // QR', QL', Ahat', Bhat', row temp (2 x m x (n-e)), col temp (2 x s x m), factor temp (2 x n x m)
+            need += 4 * m * m + 2 * m * (size_t)(n - work[i].e) + 2 * (size_t)work[i].s * m + 2 * (size_t)n * m;
+            need = (need + 31) & ~size_t(31);
+        }
+        CHK(ensure_ws2(h, need * sizeof(double) + 4096));
+        double* base = reinterpret_cast<double*>(h.ws2);
+
+        std::vector<SplitJob> jobs(cnt);
+        std::vector<sdc_region_t> regs(cnt);
+        for (int i = 0; i < cnt; ++i) {
+            Block& b = work[i];
+            const int m = b.e - b.s;
+            double* o = base + off[i];
+            SplitJob& j = jobs[i];
+            j.n = m;
+            j.pencil = !symmetric;
+            double* Tb = T + b.s + (size_t)b.s * ldt;
+            double* Sb = symmetric ? nullptr : S + b.s + (size_t)b.s * lds;
+            j.A = b.swapped ? Sb : Tb;
+            j.lda = b.swapped ? lds : ldt;
+            j.B = b.swapped ? Tb : Sb;
+            j.ldb = b.swapped ? ldt : lds;
+            sdc_region_t r{};
+            if (b.mode == MODE_CIRCLE) {
+                r.kind = SDC_DISK;
+                r.center = 0.0;
+                r.radius = b.radius;
+            } else {
+                const double c = 0.5 * (b.lo + b.hi), R = 0.5 * (b.hi - b.lo);
+                r.kind = SDC_HALFPLANE;
+                r.shift = c + (U(rng) - 0.5) * R;
+                r.scale = R > 0 ? R : 1.0;
+            }
+            regs[i] = r;
+            j.region = r;
+            j.opts = opts;
+            j.opts.seed = opts.seed + 7919ull * (++split_id);
+            j.Q = o; j.ldq = m;
+            j.QL = o + (size_t)m * m; j.ldql = m;
+            j.Ahat = o + 2 * (size_t)m * m; j.ldah = m;
+            j.Bhat = o + 3 * (size_t)m * m; j.ldbh = m;
+            if (symmetric) j.QL = nullptr;
+        }
+        CHK(run_split_jobs(h, jobs));
+        h.desc_off = 0;
+
+        // ---- classify, and collect the global updates of accepted splits
+        std::vector<EwDesc> put, zero, back1, back2;
+        std::vector<GemmDesc<double>> rows, cols, facs;
+        std::vector<Block> next;
+        for (int i = 0; i < cnt; ++i) {
+            Block& b = work[i];
+            SplitJob& j = jobs[i];
+            const int m = b.e - b.s;
+            ++st.splits;
+            const double m3 = (double)m * m * m;
+            st.iters_total += j.info.iters_right + (symmetric ? 0 : j.info.iters_left);
+            st.nominal_flops += symmetric ? (40.0 / 3.0 * j.info.iters_right + 16.0) * m3
+                                          : (40.0 / 3.0 * (j.info.iters_right + j.info.iters_left) + 32.0) * m3;
+            if (j.status < 0 && j.status != SDC_ERR_NONFINITE) return j.status;
+            const int k = j.info.k_lead;
+            const bool ok = j.status == SDC_OK && k > 0 && k < m;
+            if (!ok) {
+                Block nb = b;
+                ++nb.tries;
+                if (j.status == SDC_NO_SPLIT) {
+                    const bool all_inside = j.info.n_inside == m;
+                    if (b.mode == MODE_CIRCLE) {
+                        // radii 2^{-2^k} when everything is inside, 2^{2^k} when outside
+                        if (all_inside) nb.radius = b.radius >= 1.0 ? 0.5 : b.radius * b.radius;
+                        else nb.radius = b.radius <= 1.0 ? 2.0 : b.radius * b.radius;
+                        if (nb.tries >= 6) {
+                            // give up on circles: continue with lines inside the last circle
+                            nb.mode = MODE_LINE;
+                            if (all_inside) {
+                                nb.lo = -b.radius; nb.hi = b.radius;
+                            } else {
+                                nb.swapped ^= 1; nb.lo = -1.0 / b.radius; nb.hi = 1.0 / b.radius;
+                            }
+                            nb.tries = 0;
+                        }
+                    } else {
+                        // the line missed the spectrum: the interval shrinks (progress, Sec. 3.4)
+                        if (all_inside) nb.hi = regs[i].shift;
+                        else nb.lo = regs[i].shift;
+                        nb.tries = 0;
+                        if (!(nb.hi > nb.lo)) nb.tries = kMaxTries;
+                    }
+                }
+                if (nb.tries >= kMaxTries) {
+                    ++st.unsplit;
+                    leaves.push_back(b);
+                } else {
+                    next.push_back(nb);
+                }
+                continue;
+            }
+            ++st.accepted;
+            double* o = base + off[i];
+            const double* Qr = j.Q;
+            const double* Ql = symmetric ? j.Q : j.QL;
+            const double* Ah = b.swapped ? j.Bhat : j.Ahat;
+            const double* Bh = b.swapped ? j.Ahat : j.Bhat;
+            double* rowt = o + 4 * (size_t)m * m;
+            double* colt = rowt + 2 * (size_t)m * (n - b.e);
+            double* fact = colt + 2 * (size_t)b.s * m;
+            put.push_back(copy_desc(m, m, Ah, m, T + b.s + (size_t)b.s * ldt, ldt));
+            zero.push_back(zero_desc(m - k, k, T + (b.s + k) + (size_t)b.s * ldt, ldt));
+            if (!symmetric) {
+                put.push_back(copy_desc(m, m, Bh, m, S + b.s + (size_t)b.s * lds, lds));
+                zero.push_back(zero_desc(m - k, k, S + (b.s + k) + (size_t)b.s * lds, lds));
+            } else {
+                // symmetric: the dropped coupling block is E21 and E21^T
+                zero.push_back(zero_desc(k, m - k, T + b.s + (size_t)(b.s + k) * ldt, ldt));
+            }
+            // For symmetric A both coupling blocks are dropped at every split,
+            // so T stays block diagonal and the row/column updates would
+            // multiply zero blocks: only the factor is accumulated.
+            const int nr = symmetric ? 0 : n - b.e;
+            if (nr > 0) {
+                rows.push_back(gemm_desc(m, nr, m, Ql, m, 1, T + b.s + (size_t)b.e * ldt, ldt, 0, rowt, m));
+                back1.push_back(copy_desc(m, nr, rowt, m, T + b.s + (size_t)b.e * ldt, ldt));
+                if (!symmetric) {
+                    rows.push_back(gemm_desc(m, nr, m, Ql, m, 1, S + b.s + (size_t)b.e * lds, lds, 0,
+                                             rowt + (size_t)m * nr, m));
+                    back1.push_back(copy_desc(m, nr, rowt + (size_t)m * nr, m, S + b.s + (size_t)b.e * lds, lds));
+                }
+            }
+            if (b.s > 0 && !symmetric) {
+                cols.push_back(gemm_desc(b.s, m, m, T + (size_t)b.s * ldt, ldt, 0, Qr, m, 0, colt, b.s));
+                back2.push_back(copy_desc(b.s, m, colt, b.s, T + (size_t)b.s * ldt, ldt));
+                if (!symmetric) {
+                    cols.push_back(gemm_desc(b.s, m, m, S + (size_t)b.s * lds, lds, 0, Qr, m, 0,
+                                             colt + (size_t)b.s * m, b.s));
+                    back2.push_back(copy_desc(b.s, m, colt + (size_t)b.s * m, b.s, S + (size_t)b.s * lds, lds));
+                }
+            }
+            if (QR) {
+                facs.push_back(gemm_desc(n, m, m, QR + (size_t)b.s * ldqr, ldqr, 0, Qr, m, 0, fact, n));
+                back2.push_back(copy_desc(n, m, fact, n, QR + (size_t)b.s * ldqr, ldqr));
+            }
+            if (QL) {
+                facs.push_back(gemm_desc(n, m, m, QL + (size_t)b.s * ldql, ldql, 0, Ql, m, 0,
+                                         fact + (size_t)n * m, n));
+                back2.push_back(copy_desc(n, m, fact + (size_t)n * m, n, QL + (size_t)b.s * ldql, ldql));
+            }
+            // children: leading block = eigenvalues outside the curve
+            Block c1 = b, c2 = b;
+            c1.e = b.s + k;
+            c2.s = b.s + k;
+            c1.tries = c2.tries = 0;
+            if (b.mode == MODE_CIRCLE) {
+                const double r = b.radius;
+                c1.mode = c2.mode = MODE_LINE;
+                c1.swapped = b.swapped ^ 1;
+                c1.lo = -1.0 / r; c1.hi = 1.0 / r;
+                c2.lo = -r; c2.hi = r;
+            } else {
+                c1.lo = regs[i].shift;
+                c2.hi = regs[i].shift;
+            }
+            for (const Block& c : {c1, c2}) {
+                if (c.e - c.s <= leaf_max) leaves.push_back(c);
+                else next.push_back(c);
+            }
+        }
+        // order matters only between the phases: row updates, then column
+        // updates and factor accumulation (disjoint within a phase)
+        CHK(launch_ew(h, put));
+        CHK(launch_ew(h, zero));
+        CHK(launch_gemm(h, rows));
+        CHK(launch_ew(h, back1));
+        CHK(launch_gemm(h, cols));
+        CHK(launch_gemm(h, facs));
+        CHK(launch_ew(h, back2));
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(h.stream));
+        h.desc_off = 0;
+        work.swap(next);
+    }
+    std::sort(leaves.begin(), leaves.end(), [](const Block& a, const Block& b) { return a.s < b.s; });
+    int nb = 0;
+    for (const Block& b : leaves) block_start[nb++] = b.s;
+    block_start[nb] = n;
+    *nblocks = nb;
+    st.nblocks = nb;
+    st.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *info = st;
+    return SDC_OK;
+}
+
+}  // namespace sdc

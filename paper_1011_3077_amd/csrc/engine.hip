@@ -16,107 +16,11 @@
 #include <vector>
 
 #include "engine.hpp"
+#include "engine_util.hpp"
 #include "sdc_aux.hpp"
 #include "sdc_internal.hpp"
 
 namespace sdc {
-
-#define HIPCHK(x)                                   \
-    do {                                            \
-        hipError_t e_ = (x);                        \
-        if (e_ != hipSuccess) return SDC_ERR_DEVICE; \
-    } while (0)
-#define CHK(x)                 \
-    do {                       \
-        int r_ = (x);          \
-        if (r_ < 0) return r_; \
-    } while (0)
-
-static constexpr double kRhoOneSide = 1e-3;  // see rank_from_rho
-
-// ---------------------------------------------------------------------------
-// Workspace and staging
-// ---------------------------------------------------------------------------
-// Bump allocator over the handle's workspace.  A sizing pass (base null)
-// measures; the carving pass must stay within cap, else `overflow` is set and
-// the caller refuses to launch anything.
-struct Carver {
-    char* base;
-    size_t cap;
-    size_t off = 0;
-    bool overflow = false;
-    explicit Carver(char* b, size_t c = 0) : base(b), cap(c) {}
-    template <class T> T* take(size_t n) {
-        off = (off + 255) & ~size_t(255);
-        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
-        off += n * sizeof(T);
-        if (base && off > cap) overflow = true;
-        return p;
-    }
-};
-
-static int ensure_ws(Handle& h, size_t bytes) {
-    if (h.budget && bytes > h.budget) return SDC_ERR_NOMEM;
-    if (bytes <= h.ws_size) return SDC_OK;
-    if (h.ws) {
-        HIPCHK(hipStreamSynchronize(h.stream));
-        HIPCHK(hipFree(h.ws));
-        h.ws = nullptr;
-        h.ws_size = 0;
-    }
-    size_t sz = bytes + bytes / 8 + (1 << 20);
-    if (h.budget && sz > h.budget) sz = bytes;
-    if (hipMalloc(&h.ws, sz) != hipSuccess) {
-        h.ws = nullptr;
-        (void)hipGetLastError();
-        return SDC_ERR_NOMEM;
-    }
-    h.ws_size = sz;
-    return SDC_OK;
-}
-
-static int ensure_desc(Handle& h, size_t bytes) {
-    if (bytes <= h.desc_size) return SDC_OK;
-    if (h.desc_d) {
-        HIPCHK(hipStreamSynchronize(h.stream));
-        HIPCHK(hipFree(h.desc_d));
-        HIPCHK(hipHostFree(h.desc_h));
-        h.desc_d = h.desc_h = nullptr;
-    }
-    if (hipMalloc(&h.desc_d, bytes) != hipSuccess) return SDC_ERR_NOMEM;
-    if (hipHostMalloc(&h.desc_h, bytes, hipHostMallocDefault) != hipSuccess) return SDC_ERR_NOMEM;
-    h.desc_size = bytes;
-    h.desc_off = 0;
-    return SDC_OK;
-}
-
-static int ensure_host(Handle& h, size_t bytes) {
-    if (bytes <= h.host_size) return SDC_OK;
-    if (h.host) {
-        HIPCHK(hipStreamSynchronize(h.stream));
-        HIPCHK(hipHostFree(h.host));
-        h.host = nullptr;
-    }
-    if (hipHostMalloc(&h.host, bytes, hipHostMallocDefault) != hipSuccess) return SDC_ERR_NOMEM;
-    h.host_size = bytes;
-    return SDC_OK;
-}
-
-// Copy a host array of descriptors to the device arena (pinned staging; the
-// arena is rewound only after a stream synchronization).
-template <class T> static const T* upload(Handle& h, const std::vector<T>& v) {
-    const size_t bytes = v.size() * sizeof(T);
-    size_t off = (h.desc_off + 255) & ~size_t(255);
-    if (off + bytes > h.desc_size) return nullptr;
-    std::memcpy(h.desc_h + off, v.data(), bytes);
-    if (hipMemcpyAsync(h.desc_d + off, h.desc_h + off, bytes, hipMemcpyHostToDevice, h.stream) != hipSuccess)
-        return nullptr;
-    h.desc_off = off + bytes;
-    return reinterpret_cast<const T*>(h.desc_d + off);
-}
-#define UPLOAD(ptr, vec)                                   \
-    auto ptr = upload(h, vec);                             \
-    if (!ptr) return SDC_ERR_DEVICE;
 
 // ---------------------------------------------------------------------------
 // Region map (Sec. 3.3): A0 = a1 A + a2 B, B0 = b1 A + b2 B.

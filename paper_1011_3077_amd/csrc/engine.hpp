@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "sdc.h"
+#include "profiler.hpp"
 
 namespace sdc {
 
@@ -26,6 +27,18 @@ struct Handle {
     // pinned host buffer for small device-to-host results
     char* host = nullptr;
     size_t host_size = 0;
+    // second device workspace, owned by the divide-and-conquer driver
+    char* ws2 = nullptr;
+    size_t ws2_size = 0;
+    // opt-in kernel timing
+    Profiler prof;
+};
+
+// Installs the handle's profiler (if enabled) for the lifetime of a call.
+struct ProfScope {
+    Profiler* prev;
+    explicit ProfScope(Handle& h) : prev(g_prof) { g_prof = h.prof.on ? &h.prof : nullptr; }
+    ~ProfScope() { g_prof = prev; }
 };
 
 // One split problem (symmetric or pencil) as the drivers see it.
@@ -54,5 +67,10 @@ int run_irs_only(Handle& h, int n, const double* A, int lda, const double* B, in
                  int ldo, int* p, double* rconv);
 
 int run_gaussian(Handle& h, int n, uint64_t seed, int tag, double* G, int ldg);
+
+// Randomized divide-and-conquer; see sdc_eig_dc.
+int run_eig_dc(Handle& h, int n, const double* A, int lda, const double* B, int ldb, int symmetric, int leaf_max,
+               const sdc_opts_t& opts, double* T, int ldt, double* S, int lds, double* QL, int ldql, double* QR,
+               int ldqr, int* nblocks, int* block_start, sdc_dc_info_t* info);
 
 }  // namespace sdc

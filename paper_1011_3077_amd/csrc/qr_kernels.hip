@@ -19,6 +19,7 @@
 // on the matrix cores (MFMA), keeping the tile in registers.
 #include "sdc_internal.hpp"
 #include "mfma.hpp"
+#include "profiler.hpp"
 
 namespace sdc {
 
@@ -37,7 +38,9 @@ __device__ __forceinline__ void set4(T (&p)[N], int idx, T v) {
 
 // Householder QR of one tree node held in registers by a 256-thread
 // workgroup.  Thread (grp = tid/32, c = tid%32) owns column c, rows
-// r = 8*i + grp (i < RPG).  Rows >= mt and columns >= nbk are zero.
+// r = 8*i + grp (i < NR, NR a compile-time tile height).  Rows beyond the
+// node and columns >= nbk are zero and stay zero, so every loop runs over all
+// NR registers without guards (no divergent control flow in the hot loop).
 //
 // Column step j (the usual reflector H_j = I - tau v v^T, v_j = 1,
 // beta = -sign(alpha) ||x||, tau = (beta - alpha)/beta, v = x/(alpha - beta)):
@@ -49,26 +52,25 @@ __device__ __forceinline__ void set4(T (&p)[N], int idx, T v) {
 // On return the registers hold R (upper part, diagonal = beta) and V
 // (strictly lower part); s_tau/s_beta hold tau and beta, s_T the
 // upper-triangular T (stride NB+1) with H_0 ... H_{nbk-1} = I - V T V^T.
-template <typename T>
-__device__ void node_qr(T (&p)[QrCfg<T>::RPG], int mt, int nbk, T* s_col, T* s_row, T* s_red,
-                        T* s_Sm, T* s_T, T* s_tau, T* s_beta) {
-    constexpr int RPG = QrCfg<T>::RPG, NB = QrCfg<T>::NB;
+// Always inlined: a call would pass the register tile by reference and so
+// force it into scratch memory.
+template <typename T, int NR>
+__device__ __forceinline__ void node_qr(T (&p)[NR], int nbk, T* s_col, T* s_row, T* s_red, T* s_Sm, T* s_T,
+                                        T* s_tau, T* s_beta) {
+    constexpr int NB = QrCfg<T>::NB;
     const int tid = threadIdx.x, grp = tid >> 5, c = tid & 31;
-    const int rpge = (mt + 7) >> 3;
     for (int j = 0; j < nbk; ++j) {
-        T* tcol = s_col + (j & 1) * 8 * RPG;
+        T* tcol = s_col + (j & 1) * 8 * NR;
         T* trow = s_row + (j & 1) * NB;
         if (c == j) {
 #pragma unroll
-            for (int i = 0; i < RPG; ++i)
-                if (i < rpge) tcol[grp * RPG + i] = (8 * i + grp > j) ? p[i] : T(0);
+            for (int i = 0; i < NR; ++i) tcol[grp * NR + i] = (8 * i + grp > j) ? p[i] : T(0);
         }
         if (grp == (j & 7)) trow[c] = get4(p, j >> 3);
         __syncthreads();
         T z = 0;
 #pragma unroll
-        for (int i = 0; i < RPG; ++i)
-            if (i < rpge) z += tcol[grp * RPG + i] * p[i];
+        for (int i = 0; i < NR; ++i) z += tcol[grp * NR + i] * p[i];
         s_red[grp * NB + c] = z;
         __syncthreads();
         T zc = 0, xn2 = 0;
@@ -90,20 +92,21 @@ __device__ void node_qr(T (&p)[QrCfg<T>::RPG], int mt, int nbk, T* s_col, T* s_r
             scale = T(1) / (alpha - beta);
         }
         const T w = trow[c] + scale * zc;  // v_j^T P[:, c]  (= v_c^T v_j for c < j)
-        if (c > j) {
-            const T tw = tau * w, tws = tw * scale;
+        // c > j: p -= tau w v;  c == j: p <- v below the diagonal;  c < j: unchanged
+        const T tw = c > j ? tau * w : T(0);
+        const T coef = tw * scale;
+        const bool isj = c == j;
 #pragma unroll
-            for (int i = 0; i < RPG; ++i)
-                if (i < rpge) p[i] -= tws * tcol[grp * RPG + i];
-            if (grp == (j & 7)) set4(p, j >> 3, get4(p, j >> 3) - tw);
-        } else if (c == j) {
-#pragma unroll
-            for (int i = 0; i < RPG; ++i)
-                if (i < rpge && 8 * i + grp > j) p[i] = tcol[grp * RPG + i] * scale;
-            if (grp == (j & 7)) set4(p, j >> 3, beta);
-        } else if (grp == 0) {
-            s_Sm[c * (NB + 1) + j] = w;
+        for (int i = 0; i < NR; ++i) {
+            const T x = tcol[grp * NR + i];  // zero at rows <= j
+            const T upd = p[i] - coef * x;
+            p[i] = (isj && 8 * i + grp > j) ? x * scale : upd;
         }
+        if (grp == (j & 7)) {
+            const T pj = get4(p, j >> 3);
+            set4(p, j >> 3, isj ? beta : pj - tw);
+        }
+        if (c < j && grp == 0) s_Sm[c * (NB + 1) + j] = w;
         if (tid == 0) {
             s_tau[j] = tau;
             s_beta[j] = beta;
@@ -124,6 +127,44 @@ __device__ void node_qr(T (&p)[QrCfg<T>::RPG], int mt, int nbk, T* s_col, T* s_r
     __syncthreads();
 }
 
+// Factor the mt x nbk node staged column-major in s_tile (stride LDT) with an
+// NR-row register tile: load, QR, write T (NB x NB, column-major) to Tg, and
+// put R/V back into s_tile.  s_red/s_Sm/s_T alias the start of s_tile.
+template <typename T, int NR>
+__device__ __forceinline__ void factor_tile(T* s_tile, int mt, int nbk, T* s_col, T* s_row, T* s_tau, T* s_beta,
+                                            T* Tg) {
+    constexpr int NB = QrCfg<T>::NB, LDT = QrCfg<T>::MT_MAX + 1;
+    const int tid = threadIdx.x, grp = tid >> 5, c = tid & 31;
+    T* s_red = s_tile;
+    T* s_Sm = s_tile + 8 * NB;
+    T* s_T = s_Sm + NB * (NB + 1);
+    T p[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const int r = 8 * i + grp;
+        p[i] = r < mt ? s_tile[c * LDT + r] : T(0);
+    }
+    __syncthreads();
+    node_qr<T, NR>(p, nbk, s_col, s_row, s_red, s_Sm, s_T, s_tau, s_beta);
+    for (int e = tid; e < NB * NB; e += 256) {
+        const int i = e % NB, j = e / NB;
+        Tg[e] = (i <= j && j < nbk) ? s_T[i * (NB + 1) + j] : T(0);
+    }
+    __syncthreads();
+    // rows >= mt hold zeros; the tile has LDT >= 8 NR rows, so store them all
+#pragma unroll
+    for (int i = 0; i < NR; ++i) s_tile[c * LDT + 8 * i + grp] = p[i];
+    __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ void factor_node(T* s_tile, int mt, int nbk, T* s_col, T* s_row, T* s_tau, T* s_beta,
+                                            T* Tg) {
+    constexpr int NRL = QrCfg<T>::RPG, NRS = QrCfg<T>::RPG / 2;
+    if (mt <= 8 * NRS) factor_tile<T, NRS>(s_tile, mt, nbk, s_col, s_row, s_tau, s_beta, Tg);
+    else factor_tile<T, NRL>(s_tile, mt, nbk, s_col, s_row, s_tau, s_beta, Tg);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_panel(const QrDesc<T>* __restrict__ descs, int c0) {
     using C = QrCfg<T>;
@@ -133,9 +174,6 @@ __global__ __launch_bounds__(256) void k_panel(const QrDesc<T>* __restrict__ des
     __shared__ T s_row[2 * NB];
     __shared__ T s_tau[NB], s_beta[NB];
     __shared__ int s_last;
-    T* s_red = s_tile;
-    T* s_Sm = s_tile + 8 * NB;
-    T* s_T = s_Sm + NB * (NB + 1);
 
     const QrDesc<T> d = descs[blockIdx.y];
     if (!d.active || c0 >= d.nf) return;
@@ -144,10 +182,9 @@ __global__ __launch_bounds__(256) void k_panel(const QrDesc<T>* __restrict__ des
     const TreeGeom g = tree_geom<T>(mp);
     int node = blockIdx.x;
     if (node >= g.L[0]) return;
-    const int tid = threadIdx.x, grp = tid >> 5, c = tid & 31;
+    const int tid = threadIdx.x;
     const size_t ld = (size_t)d.ld;
     T* W = d.W;
-    T p[RPG];
 
     // ---- leaf: rows [row0, row0 + mt) of the panel columns
     const int row0 = c0 + leaf_lo(node, mp, g.L[0]);
@@ -156,27 +193,7 @@ __global__ __launch_bounds__(256) void k_panel(const QrDesc<T>* __restrict__ des
         for (int r = tid; r < mt; r += 256)
             s_tile[col * LDT + r] = col < nbk ? W[(size_t)(c0 + col) * ld + row0 + r] : T(0);
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < RPG; ++i) {
-        const int r = 8 * i + grp;
-        p[i] = r < mt ? s_tile[c * LDT + r] : T(0);
-    }
-    __syncthreads();
-    node_qr<T>(p, mt, nbk, s_col, s_row, s_red, s_Sm, s_T, s_tau, s_beta);
-    {
-        T* Tg = d.Tm + (size_t)node_index(g, 0, node) * NB * NB;
-        for (int e = tid; e < NB * NB; e += 256) {
-            const int i = e % NB, j = e / NB;
-            Tg[e] = (i <= j && j < nbk) ? s_T[i * (NB + 1) + j] : T(0);
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < RPG; ++i) {
-        const int r = 8 * i + grp;
-        if (r < mt) s_tile[c * LDT + r] = p[i];
-    }
-    __syncthreads();
+    factor_node<T>(s_tile, mt, nbk, s_col, s_row, s_tau, s_beta, d.Tm + (size_t)node_index(g, 0, node) * NB * NB);
     for (int col = 0; col < nbk; ++col)
         for (int r = tid; r < mt; r += 256) W[(size_t)(c0 + col) * ld + row0 + r] = s_tile[col * LDT + r];
 
@@ -210,27 +227,8 @@ __global__ __launch_bounds__(256) void k_panel(const QrDesc<T>* __restrict__ des
             s_tile[col * LDT + s] = v;
         }
         __syncthreads();
-#pragma unroll
-        for (int i = 0; i < RPG; ++i) {
-            const int r = 8 * i + grp;
-            p[i] = r < mt ? s_tile[c * LDT + r] : T(0);
-        }
-        __syncthreads();
-        node_qr<T>(p, mt, nbk, s_col, s_row, s_red, s_Sm, s_T, s_tau, s_beta);
-        {
-            T* Tg = d.Tm + (size_t)node_index(g, level, node) * NB * NB;
-            for (int e = tid; e < NB * NB; e += 256) {
-                const int i = e % NB, j = e / NB;
-                Tg[e] = (i <= j && j < nbk) ? s_T[i * (NB + 1) + j] : T(0);
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < RPG; ++i) {
-            const int r = 8 * i + grp;
-            if (r < mt) s_tile[c * LDT + r] = p[i];
-        }
-        __syncthreads();
+        factor_node<T>(s_tile, mt, nbk, s_col, s_row, s_tau, s_beta,
+                       d.Tm + (size_t)node_index(g, level, node) * NB * NB);
         // explicit reflectors of this node, and its R into the top rows
         T* Vi = d.Vint + (size_t)iidx * C::MT_MAX * NB;
         const int rbase = c0 + leaf_lo(node * g.pow[level], mp, g.L[0]);
@@ -432,16 +430,44 @@ void qr_aug_batch(const QrDesc<T>* d_descs, const QrDesc<T>* h, int count, hipSt
             maxtrail = maxtrail > trail ? maxtrail : trail;
         }
         if (maxL[0] == 0) continue;
+        // algorithmic work of this panel, per tree level: the update of level
+        // l touches R_l rows (all panel rows at the leaves, nbk per child
+        // above): 4 R nbk ntr + 2 nbk^2 ntr L_l flops, and reads + writes the
+        // R x ntr trailing slice and reads the R x nbk reflectors once
+        double pf = 0, pb = 0, uf[kMaxLevels] = {0, 0, 0, 0}, ub[kMaxLevels] = {0, 0, 0, 0};
+        Profiler* prof = g_prof;
+        if (prof) {
+            for (int i = 0; i < count; ++i) {
+                if (!h[i].active || c0 >= h[i].nf) continue;
+                const int mp = h[i].m - c0;
+                const TreeGeom g = tree_geom<T>(mp);
+                const double nbk = h[i].nf - c0 < C::NB ? h[i].nf - c0 : C::NB;
+                const double ntr = h[i].ncols - c0 - nbk;
+                pf += 2.0 * mp * nbk * nbk;               // Householder QR of the panel
+                pb += 2.0 * mp * nbk * sizeof(T);
+                for (int l = 0; l < g.levels; ++l) {
+                    const double rows = l == 0 ? (double)mp : (double)g.L[l - 1] * nbk;
+                    uf[l] += 4.0 * rows * nbk * ntr + 2.0 * nbk * nbk * ntr * g.L[l];
+                    ub[l] += (2.0 * rows * ntr + rows * nbk) * sizeof(T);
+                }
+            }
+        }
+        int pid = prof ? prof->begin(s) : -1;
         hipLaunchKernelGGL(k_panel<T>, dim3(maxL[0], count), dim3(256), 0, s, d_descs, c0);
+        if (prof) prof->end(pid, s, PROF_PANEL, pf, pb);
         if (maxtrail <= 0) continue;
         const int tiles = (maxtrail + 63) / 64;
         for (int lev = 0; lev < maxlev; ++lev) {
             const int rows = lev == 0 ? maxleaf : C::MT_MAX;
             const dim3 grid(maxL[lev], tiles, count);
+            const int uid = prof ? prof->begin(s) : -1;
             launch_update<T>(rows, grid, s, d_descs, c0, lev);
+            if (prof) prof->end(uid, s, PROF_UPDATE, uf[lev], ub[lev]);
         }
     }
 }
+
+thread_local Profiler* g_prof = nullptr;
 
 template void qr_aug_batch<double>(const QrDesc<double>*, const QrDesc<double>*, int, hipStream_t);
 template void qr_aug_batch<float>(const QrDesc<float>*, const QrDesc<float>*, int, hipStream_t);

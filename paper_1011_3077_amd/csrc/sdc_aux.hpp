@@ -5,7 +5,7 @@
 
 namespace sdc {
 
-enum EwOp { EW_PERMUTE = 0, EW_ADD = 1, EW_IDENTITY = 2, EW_SYM = 3 };
+enum EwOp { EW_PERMUTE = 0, EW_ADD = 1, EW_IDENTITY = 2, EW_SYM = 3, EW_ZERO = 4 };
 
 // Element-wise op on a rows x n output (rows = n for square operands).
 struct EwDesc {
@@ -42,6 +42,15 @@ struct GaussDesc {
     int tag;
     int active;
 };
+
+// Gershgorin bounds of a symmetric n x n matrix: out[2j] = A_jj - r_j,
+// out[2j+1] = A_jj + r_j with r_j = sum_{i != j} |A_ij| (column sums).
+struct GershDesc {
+    const double* X; int ld, n;
+    double* out;
+    int active;
+};
+void gersh_batch(const GershDesc* d, const GershDesc* h, int count, hipStream_t s);
 
 template <typename Tin, typename Tout>
 void ew_batch(const EwDesc* d, const EwDesc* h, int count, hipStream_t s);

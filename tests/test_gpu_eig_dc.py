@@ -1,0 +1,109 @@
+"""Divide-and-conquer (sdc_eig_dc) on the GPU against the oracle and the
+construction.
+
+The split points are random, so the two sides' block structures differ; what
+is unique is compared: the union of the block spectra (= the spectrum by
+construction), and properties every correct result has: blocks of order
+<= leaf_max, an exactly block-upper-triangular pair, orthogonal factors and
+Q_L^T A Q_R = T up to the dropped coupling blocks (backward error).  The
+full-size case is the benchmark workload: the order-2048 pencil, unit circle
+first, then recursion to blocks of order <= 64.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import sdc_synth as S
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sdc():
+    import paper_1011_3077_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def handle(sdc):
+    h = sdc.Handle(0)
+    yield h
+    h.close()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def block_spectrum(t, s, starts):
+    ev = []
+    for a0, a1 in zip(starts[:-1], starts[1:]):
+        if s is None:
+            blk = t[a0:a1, a0:a1]
+            ev.append(np.linalg.eigvalsh(0.5 * (blk + blk.T)))
+        else:
+            ev.append(sla.eigvals(t[a0:a1, a0:a1], s[a0:a1, a0:a1]))
+    return np.concatenate(ev)
+
+
+def check_pencil(res, a, b, lam, leaf, rel_tol):
+    st, t, s, ql, qr, starts, info = res
+    t, s, ql, qr = (x.cpu().numpy() for x in (t, s, ql, qr))
+    n = a.shape[0]
+    assert st == 0 and info["unsplit"] == 0
+    assert starts[0] == 0 and starts[-1] == n
+    assert all(e - s0 <= leaf for s0, e in zip(starts[:-1], starts[1:]))
+    for a0, a1 in zip(starts[:-1], starts[1:]):
+        assert np.all(t[a1:, a0:a1] == 0) and np.all(s[a1:, a0:a1] == 0)
+    eye = np.eye(n)
+    assert np.abs(ql.T @ ql - eye).max() <= 1e-12 * np.sqrt(n) * 10
+    assert np.abs(qr.T @ qr - eye).max() <= 1e-12 * np.sqrt(n) * 10
+    assert np.linalg.norm(ql.T @ a @ qr - t, 2) <= 1e-10 * np.linalg.norm(a, 2)
+    assert np.linalg.norm(ql.T @ b @ qr - s, 2) <= 1e-10 * np.linalg.norm(b, 2)
+    got = np.sort_complex(block_spectrum(t, s, starts))
+    want = np.sort_complex(lam.astype(complex))
+    err = np.max(np.abs(got - want) / np.abs(want))
+    assert err <= rel_tol, err
+    return got
+
+
+def test_eig_dc_pencil_matches_oracle(handle, sdc):
+    from oracle.eig_dc import eig_dc
+    n, leaf = 256, 32
+    print("CASE eig_dc pencil", n, flush=True)
+    p = S.pencil_problem(n, S.family_seed(1, 7))
+    res = handle.eig_dc(dev(p["A"]), dev(p["B"]), leaf_max=leaf, o=sdc.opts(seed=3))
+    got = check_pencil(res, p["A"], p["B"], p["lam"], leaf, 1e-10)
+    ref = eig_dc(p["A"], p["B"], leaf_max=leaf, seed=3)
+    ref_ev = []
+    for a0, a1 in ref["blocks"]:
+        ref_ev.append(sla.eigvals(ref["T"][a0:a1, a0:a1], ref["S"][a0:a1, a0:a1]))
+    ref_ev = np.sort_complex(np.concatenate(ref_ev))
+    assert np.max(np.abs(got - ref_ev) / np.abs(ref_ev)) <= 1e-10
+
+
+def test_eig_dc_symmetric(handle, sdc):
+    n, leaf = 300, 40
+    print("CASE eig_dc symmetric", n, flush=True)
+    a, d, q = S.sym_problem(n, S.family_seed(0, 9))
+    st, t, s, ql, qr, starts, info = handle.eig_dc(dev(a), None, leaf_max=leaf, symmetric=True,
+                                                    o=sdc.opts(seed=4))
+    assert st == 0 and s is None and ql is None and info["unsplit"] == 0
+    t, qr = t.cpu().numpy(), qr.cpu().numpy()
+    assert all(e - s0 <= leaf for s0, e in zip(starts[:-1], starts[1:]))
+    ev = np.sort(block_spectrum(t, None, starts))
+    assert np.abs(ev - np.sort(d)).max() <= 1e-12
+    assert np.abs(qr.T @ qr - np.eye(n)).max() <= 1e-12
+    assert np.linalg.norm(qr.T @ a @ qr - t, 2) <= 1e-11
+
+
+def test_eig_dc_benchmark_workload_full_size(handle, sdc):
+    """Order-2048 pencil of the benchmark: unit circle, then blocks <= 64."""
+    n, leaf = 2048, 64
+    print("CASE eig_dc full size", n, flush=True)
+    p = S.pencil_problem(n, S.family_seed(1))
+    res = handle.eig_dc(dev(p["A"]), dev(p["B"]), leaf_max=leaf, o=sdc.opts(seed=1))
+    check_pencil(res, p["A"], p["B"], p["lam"], leaf, 1e-9)
+    info = res[-1]
+    print("full-size info", info, flush=True)
