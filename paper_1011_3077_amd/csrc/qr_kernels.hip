@@ -36,18 +36,38 @@ __device__ __forceinline__ void set4(T (&p)[N], int idx, T v) {
     else p[3] = v;
 }
 
-// Householder QR of one tree node held in registers by a 256-thread
-// workgroup.  Thread (grp = tid/32, c = tid%32) owns column c, rows
-// r = 8*i + grp (i < NR, NR a compile-time tile height).  Rows beyond the
-// node and columns >= nbk are zero and stay zero, so every loop runs over all
-// NR registers without guards (no divergent control flow in the hot loop).
+// Sum over the 16 lanes of a DPP row, result in every lane of the row
+// (rotations by 8, 4, 2, 1 within the row).
+template <int CTRL> __device__ __forceinline__ double dpp_mov(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL> __device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <typename T> __device__ __forceinline__ T row16_sum(T v) {
+    v += dpp_mov<0x128>(v);  // row_ror:8
+    v += dpp_mov<0x124>(v);  // row_ror:4
+    v += dpp_mov<0x122>(v);  // row_ror:2
+    v += dpp_mov<0x121>(v);  // row_ror:1
+    return v;
+}
+
+// Householder QR of one tree node held in registers by a PT-thread
+// workgroup (PT/32 = G row groups).  Thread (grp = tid/32, c = tid%32) owns
+// column c, rows r = G*i + grp (i < NR, NR a compile-time tile height).  Rows
+// beyond the node and columns >= nbk are zero and stay zero, so every loop
+// runs over all NR registers without guards.
 //
 // Column step j (the usual reflector H_j = I - tau v v^T, v_j = 1,
 // beta = -sign(alpha) ||x||, tau = (beta - alpha)/beta, v = x/(alpha - beta)):
 // one reduction gives, for every column c, the dot product of column c with
 // the part of column j below the diagonal; from it each thread gets the
 // norm, the reflector scalars, w_c = v^T P[:, c] and (for c < j) the entries
-// v_c^T v_j needed for the compact-WY factor T.
+// v_c^T v_j needed for the compact-WY factor T.  The broadcast column is read
+// from LDS once into registers and serves both the reduction and the update;
+// the broadcast buffers alternate between steps.
 //
 // On return the registers hold R (upper part, diagonal = beta) and V
 // (strictly lower part); s_tau/s_beta hold tau and beta, s_T the
@@ -57,25 +77,35 @@ __device__ __forceinline__ void set4(T (&p)[N], int idx, T v) {
 template <typename T, int NR>
 __device__ __forceinline__ void node_qr(T (&p)[NR], int nbk, T* s_col, T* s_row, T* s_red, T* s_Sm, T* s_T,
                                         T* s_tau, T* s_beta) {
-    constexpr int NB = QrCfg<T>::NB;
+    constexpr int NB = QrCfg<T>::NB, G = QrCfg<T>::PT / 32;
     const int tid = threadIdx.x, grp = tid >> 5, c = tid & 31;
+    // row j of the node is register (j / G) of group (j % G): j < NB <= 2 G
+    static_assert(NB <= 2 * G, "row j must sit in register 0 or 1");
     for (int j = 0; j < nbk; ++j) {
-        T* tcol = s_col + (j & 1) * 8 * NR;
+        T* tcol = s_col + (j & 1) * G * NR;
         T* trow = s_row + (j & 1) * NB;
         if (c == j) {
 #pragma unroll
-            for (int i = 0; i < NR; ++i) tcol[grp * NR + i] = (8 * i + grp > j) ? p[i] : T(0);
+            for (int i = 0; i < NR; ++i) tcol[grp * NR + i] = (G * i + grp > j) ? p[i] : T(0);
         }
-        if (grp == (j & 7)) trow[c] = get4(p, j >> 3);
+        if (grp == j % G) trow[c] = j < G ? p[0] : p[1];
         __syncthreads();
-        T z = 0;
+        T x[NR];
 #pragma unroll
-        for (int i = 0; i < NR; ++i) z += tcol[grp * NR + i] * p[i];
-        s_red[grp * NB + c] = z;
+        for (int i = 0; i < NR; ++i) x[i] = tcol[grp * NR + i];  // zero at rows <= j
+        T z0 = 0, z1 = 0, z2 = 0, z3 = 0;
+#pragma unroll
+        for (int i = 0; i < NR; i += 4) {
+            z0 += x[i] * p[i];
+            if (i + 1 < NR) z1 += x[i + 1] * p[i + 1];
+            if (i + 2 < NR) z2 += x[i + 2] * p[i + 2];
+            if (i + 3 < NR) z3 += x[i + 3] * p[i + 3];
+        }
+        s_red[grp * NB + c] = (z0 + z1) + (z2 + z3);
         __syncthreads();
         T zc = 0, xn2 = 0;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < G; ++q) {
             zc += s_red[q * NB + c];
             xn2 += s_red[q * NB + j];
         }
@@ -98,13 +128,12 @@ __device__ __forceinline__ void node_qr(T (&p)[NR], int nbk, T* s_col, T* s_row,
         const bool isj = c == j;
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
-            const T x = tcol[grp * NR + i];  // zero at rows <= j
-            const T upd = p[i] - coef * x;
-            p[i] = (isj && 8 * i + grp > j) ? x * scale : upd;
+            const T upd = p[i] - coef * x[i];
+            p[i] = (isj && G * i + grp > j) ? x[i] * scale : upd;
         }
-        if (grp == (j & 7)) {
-            const T pj = get4(p, j >> 3);
-            set4(p, j >> 3, isj ? beta : pj - tw);
+        if (grp == j % G) {
+            if (j < G) p[0] = isj ? beta : p[0] - tw;
+            else p[1] = isj ? beta : p[1] - tw;
         }
         if (c < j && grp == 0) s_Sm[c * (NB + 1) + j] = w;
         if (tid == 0) {
@@ -113,15 +142,32 @@ __device__ __forceinline__ void node_qr(T (&p)[NR], int nbk, T* s_col, T* s_row,
         }
     }
     __syncthreads();
-    // Compact-WY factor, forward columnwise recurrence:
-    // T[i][j] = -tau_j sum_{l=i}^{j-1} T[i][l] (v_l^T v_j), T[i][i] = tau_i.
-    if (tid < nbk) {
-        const int i = tid;
-        s_T[i * (NB + 1) + i] = s_tau[i];
-        for (int j = i + 1; j < nbk; ++j) {
-            T acc = 0;
-            for (int l = i; l < j; ++l) acc += s_T[i * (NB + 1) + l] * s_Sm[l * (NB + 1) + j];
-            s_T[i * (NB + 1) + j] = -s_tau[j] * acc;
+    // Compact-WY factor, forward columnwise recurrence
+    //   T[i][j] = -tau_j sum_{l=i}^{j-1} T[i][l] (v_l^T v_j),  T[i][i] = tau_i,
+    // row i on one 16-lane DPP row: lane sub keeps T[i][sub] and T[i][sub + 16]
+    // and the sum over l is split by l mod 16 and reduced within the row.
+    static_assert(QrCfg<T>::PT >= 16 * NB, "T recurrence needs 16 lanes per row");
+    {
+        const int ti = tid >> 4, sub = tid & 15;
+        T t0 = 0, t1 = 0;
+        if (ti < nbk) {
+            if (sub == ti) t0 = s_tau[ti];
+            if (sub + 16 == ti) t1 = s_tau[ti];
+        }
+        for (int j = 1; j < nbk; ++j) {
+            T part = 0;
+            if (sub >= ti && sub < j) part += t0 * s_Sm[sub * (NB + 1) + j];
+            if (sub + 16 >= ti && sub + 16 < j) part += t1 * s_Sm[(sub + 16) * (NB + 1) + j];
+            part = row16_sum(part);
+            if (ti < j) {
+                const T tij = -s_tau[j] * part;
+                if (sub == j) t0 = tij;
+                if (sub + 16 == j) t1 = tij;
+            }
+        }
+        if (ti < NB) {
+            s_T[ti * (NB + 1) + sub] = t0;
+            s_T[ti * (NB + 1) + sub + 16] = t1;
         }
     }
     __syncthreads();
@@ -133,44 +179,44 @@ __device__ __forceinline__ void node_qr(T (&p)[NR], int nbk, T* s_col, T* s_row,
 template <typename T, int NR>
 __device__ __forceinline__ void factor_tile(T* s_tile, int mt, int nbk, T* s_col, T* s_row, T* s_tau, T* s_beta,
                                             T* Tg) {
-    constexpr int NB = QrCfg<T>::NB, LDT = QrCfg<T>::MT_MAX + 1;
+    constexpr int NB = QrCfg<T>::NB, LDT = QrCfg<T>::MT_MAX + 1, G = QrCfg<T>::PT / 32, PT = QrCfg<T>::PT;
     const int tid = threadIdx.x, grp = tid >> 5, c = tid & 31;
     T* s_red = s_tile;
-    T* s_Sm = s_tile + 8 * NB;
+    T* s_Sm = s_tile + G * NB;
     T* s_T = s_Sm + NB * (NB + 1);
     T p[NR];
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
-        const int r = 8 * i + grp;
+        const int r = G * i + grp;
         p[i] = r < mt ? s_tile[c * LDT + r] : T(0);
     }
     __syncthreads();
     node_qr<T, NR>(p, nbk, s_col, s_row, s_red, s_Sm, s_T, s_tau, s_beta);
-    for (int e = tid; e < NB * NB; e += 256) {
+    for (int e = tid; e < NB * NB; e += PT) {
         const int i = e % NB, j = e / NB;
         Tg[e] = (i <= j && j < nbk) ? s_T[i * (NB + 1) + j] : T(0);
     }
     __syncthreads();
-    // rows >= mt hold zeros; the tile has LDT >= 8 NR rows, so store them all
+    // rows >= mt hold zeros; the tile has LDT >= G NR rows, so store them all
 #pragma unroll
-    for (int i = 0; i < NR; ++i) s_tile[c * LDT + 8 * i + grp] = p[i];
+    for (int i = 0; i < NR; ++i) s_tile[c * LDT + G * i + grp] = p[i];
     __syncthreads();
 }
 
 template <typename T>
 __device__ __forceinline__ void factor_node(T* s_tile, int mt, int nbk, T* s_col, T* s_row, T* s_tau, T* s_beta,
                                             T* Tg) {
-    constexpr int NRL = QrCfg<T>::RPG, NRS = QrCfg<T>::RPG / 2;
-    if (mt <= 8 * NRS) factor_tile<T, NRS>(s_tile, mt, nbk, s_col, s_row, s_tau, s_beta, Tg);
+    constexpr int NRL = QrCfg<T>::RPG, NRS = QrCfg<T>::RPG / 2, G = QrCfg<T>::PT / 32;
+    if (mt <= G * NRS) factor_tile<T, NRS>(s_tile, mt, nbk, s_col, s_row, s_tau, s_beta, Tg);
     else factor_tile<T, NRL>(s_tile, mt, nbk, s_col, s_row, s_tau, s_beta, Tg);
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_panel(const QrDesc<T>* __restrict__ descs, int c0) {
+__global__ __launch_bounds__(QrCfg<T>::PT) void k_panel(const QrDesc<T>* __restrict__ descs, int c0) {
     using C = QrCfg<T>;
-    constexpr int NB = C::NB, RPG = C::RPG, LDT = C::MT_MAX + 1;
+    constexpr int NB = C::NB, RPG = C::RPG, LDT = C::MT_MAX + 1, PT = C::PT, G = PT / 32;
     __shared__ T s_tile[LDT * NB];
-    __shared__ T s_col[2 * 8 * RPG];
+    __shared__ T s_col[2 * G * RPG];
     __shared__ T s_row[2 * NB];
     __shared__ T s_tau[NB], s_beta[NB];
     __shared__ int s_last;
@@ -187,15 +233,25 @@ __global__ __launch_bounds__(256) void k_panel(const QrDesc<T>* __restrict__ des
     T* W = d.W;
 
     // ---- leaf: rows [row0, row0 + mt) of the panel columns
+    // Each thread moves whole rows (all NB columns), so its global accesses
+    // are independent and in flight together; across threads every column
+    // access is a contiguous run of rows.
     const int row0 = c0 + leaf_lo(node, mp, g.L[0]);
     int mt = c0 + leaf_lo(node + 1, mp, g.L[0]) - row0;
-    for (int col = 0; col < NB; ++col)
-        for (int r = tid; r < mt; r += 256)
-            s_tile[col * LDT + r] = col < nbk ? W[(size_t)(c0 + col) * ld + row0 + r] : T(0);
+    for (int r = tid; r < mt; r += PT) {
+        T v[NB];
+#pragma unroll
+        for (int col = 0; col < NB; ++col) v[col] = col < nbk ? W[(size_t)(c0 + col) * ld + row0 + r] : T(0);
+#pragma unroll
+        for (int col = 0; col < NB; ++col) s_tile[col * LDT + r] = v[col];
+    }
     __syncthreads();
     factor_node<T>(s_tile, mt, nbk, s_col, s_row, s_tau, s_beta, d.Tm + (size_t)node_index(g, 0, node) * NB * NB);
-    for (int col = 0; col < nbk; ++col)
-        for (int r = tid; r < mt; r += 256) W[(size_t)(c0 + col) * ld + row0 + r] = s_tile[col * LDT + r];
+    for (int r = tid; r < mt; r += PT) {
+#pragma unroll
+        for (int col = 0; col < NB; ++col)
+            if (col < nbk) W[(size_t)(c0 + col) * ld + row0 + r] = s_tile[col * LDT + r];
+    }
 
     // ---- climb the tree: the last child to arrive factors the parent
     for (int level = 1; level < g.levels; ++level) {
@@ -214,17 +270,17 @@ __global__ __launch_bounds__(256) void k_panel(const QrDesc<T>* __restrict__ des
         __threadfence();
         node = parent;
         mt = nch * NB;
-        // stacked upper-triangular R factors of the children
-        for (int e = tid; e < mt * NB; e += 256) {
-            const int col = e / mt, s = e % mt;
+        // stacked upper-triangular R factors of the children (row s of the
+        // stack is row s % NB of child s / NB)
+        for (int s = tid; s < mt; s += PT) {
             const int t = s / NB, r = s % NB;
-            T v = 0;
-            if (col < nbk && r <= col) {
-                const int child = node * C::F + t;
-                const int rb = c0 + leaf_lo(child * g.pow[level - 1], mp, g.L[0]);
-                v = W[(size_t)(c0 + col) * ld + rb + r];
-            }
-            s_tile[col * LDT + s] = v;
+            const int rb = c0 + leaf_lo((node * C::F + t) * g.pow[level - 1], mp, g.L[0]);
+            T v[NB];
+#pragma unroll
+            for (int col = 0; col < NB; ++col)
+                v[col] = (col < nbk && r <= col) ? W[(size_t)(c0 + col) * ld + rb + r] : T(0);
+#pragma unroll
+            for (int col = 0; col < NB; ++col) s_tile[col * LDT + s] = v[col];
         }
         __syncthreads();
         factor_node<T>(s_tile, mt, nbk, s_col, s_row, s_tau, s_beta,
@@ -232,13 +288,15 @@ __global__ __launch_bounds__(256) void k_panel(const QrDesc<T>* __restrict__ des
         // explicit reflectors of this node, and its R into the top rows
         T* Vi = d.Vint + (size_t)iidx * C::MT_MAX * NB;
         const int rbase = c0 + leaf_lo(node * g.pow[level], mp, g.L[0]);
-        for (int e = tid; e < C::MT_MAX * NB; e += 256) {
-            const int col = e / C::MT_MAX, s = e % C::MT_MAX;
-            T v = 0;
-            if (s < mt && col < nbk) v = s > col ? s_tile[col * LDT + s] : (s == col ? T(1) : T(0));
-            Vi[e] = v;
+        for (int s = tid; s < C::MT_MAX; s += PT) {
+#pragma unroll
+            for (int col = 0; col < NB; ++col) {
+                T v = 0;
+                if (s < mt && col < nbk) v = s > col ? s_tile[col * LDT + s] : (s == col ? T(1) : T(0));
+                Vi[(size_t)col * C::MT_MAX + s] = v;
+            }
         }
-        for (int e = tid; e < nbk * nbk; e += 256) {
+        for (int e = tid; e < nbk * nbk; e += PT) {
             const int col = e / nbk, s = e % nbk;
             if (s <= col) W[(size_t)(c0 + col) * ld + rbase + s] = s_tile[col * LDT + s];
         }
@@ -287,18 +345,25 @@ __global__ __launch_bounds__(256) void k_update(const QrDesc<T>* __restrict__ de
         if (tid < nch) s_rb[tid] = c0 + leaf_lo((node * C::F + tid) * g.pow[level - 1], mp, g.L[0]);
     }
     const int rows_pad = ((mt + 15) >> 4) << 4;
+    // reflectors: each thread moves whole rows (independent loads in flight)
     if (level == 0) {
-        for (int e = tid; e < rows_pad * NB; e += 256) {
-            const int col = e / rows_pad, s = e % rows_pad;
-            T v = 0;
-            if (s < mt && col < nbk) v = s > col ? W[(size_t)(c0 + col) * ld + lo + s] : (s == col ? T(1) : T(0));
-            s_V[s * VS + col] = v;
+        for (int s = tid; s < rows_pad; s += 256) {
+            T v[NB];
+#pragma unroll
+            for (int col = 0; col < NB; ++col)
+                v[col] = (s < mt && col < nbk) ? (s > col ? W[(size_t)(c0 + col) * ld + lo + s] : (s == col ? T(1) : T(0)))
+                                               : T(0);
+#pragma unroll
+            for (int col = 0; col < NB; ++col) s_V[s * VS + col] = v[col];
         }
     } else {
         const T* Vi = d.Vint + (size_t)internal_index(g, level, node) * C::MT_MAX * NB;
-        for (int e = tid; e < rows_pad * NB; e += 256) {
-            const int col = e / rows_pad, s = e % rows_pad;
-            s_V[s * VS + col] = (s < mt && col < nbk) ? Vi[(size_t)col * C::MT_MAX + s] : T(0);
+        for (int s = tid; s < rows_pad; s += 256) {
+            T v[NB];
+#pragma unroll
+            for (int col = 0; col < NB; ++col) v[col] = (s < mt && col < nbk) ? Vi[(size_t)col * C::MT_MAX + s] : T(0);
+#pragma unroll
+            for (int col = 0; col < NB; ++col) s_V[s * VS + col] = v[col];
         }
     }
     {
@@ -330,19 +395,27 @@ __global__ __launch_bounds__(256) void k_update(const QrDesc<T>* __restrict__ de
             }
         }
     }
-    // Wt = V^T C  (NB x 16): two 16x16 blocks
-    v4 w0 = v4{0, 0, 0, 0}, w1 = v4{0, 0, 0, 0};
+    // Wt = V^T C  (NB x 16): two 16x16 blocks, each summed over two
+    // interleaved accumulator chains (even / odd row blocks) for MFMA ILP
+    v4 w0 = v4{0, 0, 0, 0}, w1 = v4{0, 0, 0, 0}, w2 = v4{0, 0, 0, 0}, w3 = v4{0, 0, 0, 0};
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-        if (rb < rbe) {
+    for (int rb = 0; rb < RB; rb += 2) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
+        for (int v = 0; v < 4; ++v) {
+            if (rb < rbe) {
                 const T* vr = s_V + (rb * 16 + M::row(gq, v)) * VS;
                 w0 = M::mma(vr[ln], cr[rb][v], w0);
                 w1 = M::mma(vr[16 + ln], cr[rb][v], w1);
             }
+            if (rb + 1 < rbe) {
+                const T* vr = s_V + ((rb + 1) * 16 + M::row(gq, v)) * VS;
+                w2 = M::mma(vr[ln], cr[rb + 1][v], w2);
+                w3 = M::mma(vr[16 + ln], cr[rb + 1][v], w3);
+            }
         }
     }
+    w0 += w2;
+    w1 += w3;
     // Y = T^T Wt
     v4 y0 = v4{0, 0, 0, 0}, y1 = v4{0, 0, 0, 0};
 #pragma unroll
@@ -355,19 +428,16 @@ __global__ __launch_bounds__(256) void k_update(const QrDesc<T>* __restrict__ de
             y1 = M::mma(s_T[k * (NB + 1) + 16 + ln], b, y1);
         }
     }
-    // C -= V Y
+    // C -= V Y: k-steps outer, row blocks inner (RB independent accumulators)
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-        if (rb < rbe) {
-            const T* vr = s_V + (rb * 16 + ln) * VS;
+    for (int pb = 0; pb < 2; ++pb) {
 #pragma unroll
-            for (int pb = 0; pb < 2; ++pb) {
+        for (int j = 0; j < 4; ++j) {
+            const T b = pb ? y1[j] : y0[j];
+            const int kcol = pb * 16 + M::row(gq, j);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const T b = pb ? y1[j] : y0[j];
-                    cr[rb] = M::mma(-vr[pb * 16 + M::row(gq, j)], b, cr[rb]);
-                }
-            }
+            for (int rb = 0; rb < RB; ++rb)
+                if (rb < rbe) cr[rb] = M::mma(-s_V[(rb * 16 + ln) * VS + kcol], b, cr[rb]);
         }
     }
 #pragma unroll
@@ -453,7 +523,7 @@ void qr_aug_batch(const QrDesc<T>* d_descs, const QrDesc<T>* h, int count, hipSt
             }
         }
         int pid = prof ? prof->begin(s) : -1;
-        hipLaunchKernelGGL(k_panel<T>, dim3(maxL[0], count), dim3(256), 0, s, d_descs, c0);
+        hipLaunchKernelGGL(k_panel<T>, dim3(maxL[0], count), dim3(C::PT), 0, s, d_descs, c0);
         if (prof) prof->end(pid, s, PROF_PANEL, pf, pb);
         if (maxtrail <= 0) continue;
         const int tiles = (maxtrail + 63) / 64;

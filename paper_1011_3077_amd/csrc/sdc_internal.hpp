@@ -19,11 +19,13 @@ namespace sdc {
 // columns and lives in one workgroup's registers.
 // ---------------------------------------------------------------------------
 template <typename T> struct QrCfg;
+// Panel workgroups have PT threads = (PT/32) row groups x 32 columns; RPG is
+// the register rows per thread for a full MT_MAX-row node.
 template <> struct QrCfg<double> {
-    static constexpr int NB = 32, MT_MAX = 512, H = 256, F = 16, RPG = 64;
+    static constexpr int NB = 32, MT_MAX = 512, H = 256, F = 16, PT = 512, RPG = MT_MAX / (PT / 32);
 };
 template <> struct QrCfg<float> {
-    static constexpr int NB = 32, MT_MAX = 1024, H = 512, F = 32, RPG = 128;
+    static constexpr int NB = 32, MT_MAX = 1024, H = 512, F = 32, PT = 512, RPG = MT_MAX / (PT / 32);
 };
 
 constexpr int kMaxLevels = 4;
