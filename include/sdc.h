@@ -21,9 +21,16 @@
  *   - Matrix pointers are DEVICE pointers (memory from hipMalloc or a torch
  *     CUDA/HIP tensor) on the handle's device.  Inputs are never modified;
  *     outputs are caller-allocated and written in full.
- *   - Inputs and outputs are always FP64.  SDC_FP32_REFINE only changes the
- *     internal arithmetic of the repeated squaring (FP32 with FP32
- *     accumulation) and adds an FP64 refinement of the basis.
+ *   - Inputs and outputs are always FP64.  SDC_FP32_REFINE (symmetric
+ *     problems only; pencils return SDC_ERR_INVALID) runs the repeated
+ *     squaring in FP32 with FP32 accumulation, keeps the convergence test,
+ *     the rank decision, the block form and the split search in FP64, and
+ *     adds an FP64 Newton refinement of the basis (not in the paper): X
+ *     solving X A11 - A22 X = E21 by conjugate gradients, Q <- Q [I -X^T; X I]
+ *     re-orthonormalized, up to 3 rounds, until ||E21||_1/||A||_1 <=
+ *     split_tol.  The refinement needs the two eigenvalue groups separated by
+ *     a point (a half-plane split); otherwise the split is reported as
+ *     RANK_AMBIGUOUS.
  *   - Eigenvalues of the pencil A - lambda B are the roots of
  *     det(A - lambda B) = 0.  The region's boundary is mapped to the unit
  *     circle (Sec. 3.3): a half plane Re z < shift with scale s becomes the

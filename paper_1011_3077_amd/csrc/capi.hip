@@ -44,6 +44,10 @@ sdc_opts_t resolve(const sdc_opts_t* o) {
     else sdc_opts_default(&r);
     return r;
 }
+bool prec_ok(const sdc_opts_t& o, bool pencil) {
+    if (o.prec == SDC_FP64) return true;
+    return o.prec == SDC_FP32_REFINE && !pencil;
+}
 
 }  // namespace
 
@@ -116,6 +120,7 @@ sdc_status_t sdc_irs(sdc_handle_t hd, int n, const double* A, int lda, const dou
     Handle& h = hd->h;
     if (use_device(h) != SDC_OK) return SDC_ERR_DEVICE;
     const sdc_opts_t o = resolve(opts);
+    if (o.prec != SDC_FP64 && o.prec != SDC_FP32_REFINE) return SDC_ERR_INVALID;
     sdc::ProfScope ps(h);
     const int r = sdc::run_irs_only(h, n, A, lda, B, ldb, transpose ? 1 : 0, region, o, Ap, Bp, R, ldo, p, rconv);
     resolve_profile(h);
@@ -135,6 +140,7 @@ sdc_status_t sdc_split_sym(sdc_handle_t hd, int n, const double* A, int lda, sdc
     std::vector<SplitJob> jobs(1);
     SplitJob& j = jobs[0];
     j.n = n; j.pencil = false; j.A = A; j.lda = lda; j.region = region; j.opts = resolve(opts);
+    if (!prec_ok(j.opts, false)) return SDC_ERR_INVALID;
     j.Q = Q; j.ldq = ldq; j.Ahat = Ahat; j.ldah = ldah;
     sdc::ProfScope ps(h);
     const int r = sdc::run_split_jobs(h, jobs);
@@ -160,6 +166,7 @@ sdc_status_t sdc_split_pencil(sdc_handle_t hd, int n, const double* A, int lda, 
     SplitJob& j = jobs[0];
     j.n = n; j.pencil = true; j.A = A; j.lda = lda; j.B = B; j.ldb = ldb; j.region = region;
     j.opts = resolve(opts);
+    if (!prec_ok(j.opts, true)) return SDC_ERR_INVALID;
     j.Q = QR; j.ldq = ldqr; j.QL = QL; j.ldql = ldql; j.Ahat = Ahat; j.ldah = ldah; j.Bhat = Bhat; j.ldbh = ldbh;
     sdc::ProfScope ps(h);
     const int r = sdc::run_split_jobs(h, jobs);
@@ -177,7 +184,7 @@ sdc_status_t sdc_split_sym_batched(sdc_handle_t hd, int count, const int* n, con
     if (count == 0) return SDC_OK;
     if (!n || !A || !lda || !regions || !Q || !ldq || !Ahat || !ldah || !statuses) return SDC_ERR_INVALID;
     const sdc_opts_t o = resolve(opts);
-    if (o.G) return SDC_ERR_INVALID;
+    if (o.G || !prec_ok(o, false)) return SDC_ERR_INVALID;
     std::vector<SplitJob> jobs;
     std::vector<int> idx;
     for (int i = 0; i < count; ++i) {
@@ -225,7 +232,7 @@ sdc_status_t sdc_eig_dc(sdc_handle_t hd, int n, const double* A, int lda, const 
         return SDC_OK;
     }
     const sdc_opts_t o = resolve(opts);
-    if (o.G) return SDC_ERR_INVALID;
+    if (o.G || !prec_ok(o, !symmetric)) return SDC_ERR_INVALID;
     Handle& h = hd->h;
     if (use_device(h) != SDC_OK) return SDC_ERR_DEVICE;
     sdc::ProfScope ps(h);

@@ -192,6 +192,7 @@ struct JobWs {
     double* dg[4] = {nullptr, nullptr, nullptr, nullptr};
     unsigned* qcnt = nullptr;
     double *SA = nullptr, *SB = nullptr, *e = nullptr, *out = nullptr, *nrm = nullptr, *orth = nullptr;
+    double* cg = nullptr;  // CG partial sums of the FP64 refinement (5 x kCgMaxBlocks)
     std::vector<double> rho_r, rho_l;
     int attempt = 0, done = 0, best_attempt = -1;
     double best_e = INFINITY;
@@ -227,6 +228,7 @@ static void job_layout(Carver& c, JobWs& w) {
     w.out = c.take<double>(2);
     w.nrm = c.take<double>(2);
     w.orth = c.take<double>(1);
+    if (w.fp32 && !j.pencil) w.cg = c.take<double>(5 * (size_t)kCgMaxBlocks);
 }
 
 static EwDesc ew_perm(int n, const double* in, int ldi, double* out, int ldo, int trans, int revP, int revQ,
@@ -253,6 +255,20 @@ static GemmDesc<double> gemm(int n, const double* A, int lda, int ta, const doub
     g.A = A; g.B = B; g.C = C; g.lda = lda; g.ldb = ldb; g.ldc = ldc;
     g.M = n; g.N = n; g.K = n; g.ta = ta; g.tb = tb; g.alpha = 1.0; g.beta = 0.0; g.active = 1;
     return g;
+}
+
+static GemmDesc<double> gemm_g(int M, int N, int K, const double* A, int lda, int ta, const double* B, int ldb,
+                               int tb, double* C, int ldc, double alpha, double beta) {
+    GemmDesc<double> g{};
+    g.A = A; g.B = B; g.C = C; g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+    g.M = M; g.N = N; g.K = K; g.ta = ta; g.tb = tb; g.alpha = alpha; g.beta = beta; g.active = 1;
+    return g;
+}
+static EwDesc ew_copy(int rows, int cols, const double* in, int ldi, double* out, int ldo) {
+    EwDesc d{};
+    d.op = EW_PERMUTE; d.n = cols; d.rows = rows; d.in = in; d.ldi = ldi; d.out = out; d.ldo = ldo;
+    d.alpha = 1.0; d.active = 1;
+    return d;
 }
 
 static int run_ew(Handle& h, const std::vector<EwDesc>& v) {
@@ -506,6 +522,209 @@ static bool sides_converged(const JobWs& w) {
     return true;
 }
 
+// ---------------------------------------------------------------------------
+// FP64 refinement of a symmetric split whose repeated squaring ran in FP32
+// (an addition to the paper, which has no mixed precision).
+//
+// With A_hat = Q^T A Q = [A11 E^T; E A22] (E = A_hat[k:, :k]) and
+// U = [I -X^T; X I], the (2,1) block of U^T A_hat U is, to first order in X,
+// E + A22 X - X A11; it vanishes when X solves the Sylvester equation
+// X A11 - A22 X = E, which CG solves on the device (positive definite when
+// A11's eigenvalues lie above A22's, as for a half-plane split).  Since
+// U^T U = diag(I + X^T X, I + X X^T), Q U (I + ...)^{-1/2} stays orthogonal;
+// the inverse square roots are applied to first order, I - X^T X / 2 and
+// I - X X^T / 2 (error O(|X|^4)), followed by one Newton-Schulz step toward
+// the polar factor.  Each Newton round squares E's size; the block form and
+// split search are then recomputed in FP64.
+// ---------------------------------------------------------------------------
+constexpr int kRefineRounds = 3;
+constexpr int kCgMaxIt = 240;
+constexpr int kCgCheck = 8;       // iterations between host convergence checks
+constexpr double kCgTol = 1e-6;   // relative residual of each Newton correction
+constexpr double kRefineMaxE = 1e-2;
+
+static bool wants_refine(JobWs& w) {
+    SplitJob& j = *w.job;
+    if (!w.fp32 || j.pencil || !w.cg) return false;
+    double gap = 1;
+    int side = SIDE_SPLIT;
+    const int krho = rank_from_rho(w.rho_r, gap, side);
+    const int k = j.info.k_lead;
+    const double e = j.info.e21_rel;
+    return side == SIDE_SPLIT && k == krho && k > 0 && k < j.n && !(e <= j.opts.split_tol) && e < kRefineMaxE;
+}
+
+static int cg_solve(Handle& h, std::vector<JobWs*>& js) {
+    const int count = (int)js.size();
+    std::vector<CgDesc> cg;
+    std::vector<GemmDesc<double>> g1, g2;
+    for (JobWs* w : js) {
+        SplitJob& j = *w->job;
+        const int n = j.n, k = j.info.k_lead, m = n - k;
+        const size_t mk = (size_t)m * k;
+        CgDesc d{};
+        d.m = m; d.k = k; d.E = j.Ahat + k; d.lde = j.ldah;
+        d.X = w->X; d.R = w->X + mk; d.P = w->X + 2 * mk; d.Z = w->X + 3 * mk;
+        d.rr = w->cg; d.rr0 = w->cg + 3 * kCgMaxBlocks; d.pz = w->cg + 4 * kCgMaxBlocks;
+        d.tol2 = kCgTol * kCgTol; d.nblk = cg_blocks(m, k); d.active = 1;
+        cg.push_back(d);
+        // Z = P A11 - A22 P
+        g1.push_back(gemm_g(m, k, k, d.P, m, 0, j.Ahat, j.ldah, 0, d.Z, m, 1.0, 0.0));
+        g2.push_back(gemm_g(m, k, m, j.Ahat + k + (size_t)k * j.ldah, j.ldah, 0, d.P, m, 0, d.Z, m, -1.0, 1.0));
+    }
+    UPLOAD(dcg, cg);
+    UPLOAD(dg1, g1);
+    UPLOAD(dg2, g2);
+    size_t need = 0;
+    for (const CgDesc& d : cg) need += 2 * (size_t)d.nblk;
+    CHK(ensure_host(h, need * sizeof(double) + 64));
+    cg_init_batch(dcg, cg.data(), count, h.stream);
+    for (int it = 0; it < kCgMaxIt; ++it) {
+        gemm_batch<double>(dg1, g1.data(), count, h.stream);
+        gemm_batch<double>(dg2, g2.data(), count, h.stream);
+        for (int ph = 0; ph < 3; ++ph) cg_iter_vec(dcg, cg.data(), count, it, ph, h.stream);
+        if ((it + 1) % kCgCheck != 0) continue;
+        HIPCHK(hipGetLastError());
+        // stop launching once every problem is frozen (the device decides;
+        // this only saves launches)
+        double* hb = reinterpret_cast<double*>(h.host);
+        size_t off = 0;
+        for (const CgDesc& d : cg) {
+            HIPCHK(hipMemcpyAsync(hb + off, d.rr + ((it + 1) % 3) * kCgMaxBlocks, sizeof(double) * d.nblk,
+                                  hipMemcpyDeviceToHost, h.stream));
+            HIPCHK(hipMemcpyAsync(hb + off + d.nblk, d.rr0, sizeof(double) * d.nblk, hipMemcpyDeviceToHost,
+                                  h.stream));
+            off += 2 * (size_t)d.nblk;
+        }
+        HIPCHK(hipStreamSynchronize(h.stream));
+        bool all = true;
+        off = 0;
+        for (const CgDesc& d : cg) {
+            double rr = 0, r0 = 0;
+            for (int b = 0; b < d.nblk; ++b) {
+                rr += hb[off + b];
+                r0 += hb[off + d.nblk + b];
+            }
+            // slack: the device sums in another order
+            if (!(rr <= d.tol2 * r0 * (1 + 1e-9))) all = false;
+            off += 2 * (size_t)d.nblk;
+        }
+        if (all) break;
+    }
+    HIPCHK(hipGetLastError());
+    return SDC_OK;
+}
+
+// Q <- Q U with the first-order orthonormalization (see above).
+static int apply_correction(Handle& h, std::vector<JobWs*>& js) {
+    std::vector<EwDesc> c1, c2;
+    std::vector<GemmDesc<double>> u1, u2;
+    for (JobWs* w : js) {
+        SplitJob& j = *w->job;
+        const int n = j.n, k = j.info.k_lead, m = n - k;
+        const double* X = w->X;
+        double* T1 = w->T1;
+        double* S1 = w->T2;
+        double* S2 = w->T2 + (size_t)k * k;
+        c1.push_back(ew_copy(n, n, j.Q, j.ldq, T1, n));
+        u1.push_back(gemm_g(n, k, m, j.Q + (size_t)k * j.ldq, j.ldq, 0, X, m, 0, T1, n, 1.0, 1.0));   // Q1 + Q2 X
+        u1.push_back(gemm_g(n, m, k, j.Q, j.ldq, 0, X, m, 1, T1 + (size_t)k * n, n, -1.0, 1.0));      // Q2 - Q1 X^T
+        u1.push_back(gemm_g(k, k, m, X, m, 1, X, m, 0, S1, k, 1.0, 0.0));                            // X^T X
+        u1.push_back(gemm_g(m, m, k, X, m, 0, X, m, 1, S2, m, 1.0, 0.0));                            // X X^T
+        c2.push_back(ew_copy(n, n, T1, n, j.Q, j.ldq));
+        u2.push_back(gemm_g(n, k, k, T1, n, 0, S1, k, 0, j.Q, j.ldq, -0.5, 1.0));
+        u2.push_back(gemm_g(n, m, m, T1 + (size_t)k * n, n, 0, S2, m, 0, j.Q + (size_t)k * j.ldq, j.ldq, -0.5, 1.0));
+    }
+    CHK(run_ew(h, c1));
+    CHK(run_gemm(h, u1));
+    CHK(run_ew(h, c2));
+    CHK(run_gemm(h, u2));
+    // one Newton-Schulz step toward the polar factor, Q <- Q (I - (Q^T Q - I)/2):
+    // removes the O(|X|^4) loss of orthogonality left by the first-order
+    // inverse square roots (and any rounding drift), to O(|X|^8)
+    std::vector<EwDesc> e1, e2;
+    std::vector<GemmDesc<double>> g1, g2;
+    for (JobWs* w : js) {
+        SplitJob& j = *w->job;
+        const int n = j.n;
+        e1.push_back(ew_ident(n, w->T1, n));
+        g1.push_back(gemm_g(n, n, n, j.Q, j.ldq, 1, j.Q, j.ldq, 0, w->T1, n, 1.0, -1.0));
+        e2.push_back(ew_copy(n, n, j.Q, j.ldq, w->T2, n));
+        g2.push_back(gemm_g(n, n, n, w->T2, n, 0, w->T1, n, 0, j.Q, j.ldq, -0.5, 1.0));
+    }
+    CHK(run_ew(h, e1));
+    CHK(run_gemm(h, g1));
+    CHK(run_ew(h, e2));
+    CHK(run_gemm(h, g2));
+    return SDC_OK;
+}
+
+// FP32 iterates leave ||E21|| at the rank-revealed split of order
+// eps32 |A| / gap.  At large n that can exceed e(k) of the trivial splits next
+// to k = 1 or k = n - 1 (one border row or column has a small 1-norm), so the
+// refinement starts from the rank the GRURV diagonals reveal: for jobs whose
+// split-search minimum k* differs from that rank, e(k_rho) is read back and
+// taken as the candidate.
+static int pin_to_rank(Handle& h, std::vector<JobWs*>& js) {
+    std::vector<JobWs*> alt;
+    std::vector<int> ks;
+    for (JobWs* w : js) {
+        if (!w->fp32 || w->job->pencil || !w->cg) continue;
+        double gap = 1;
+        int side = SIDE_SPLIT;
+        const int krho = rank_from_rho(w->rho_r, gap, side);
+        if (side != SIDE_SPLIT || krho == w->job->info.k_lead || krho < 1 || krho >= w->job->n) continue;
+        alt.push_back(w);
+        ks.push_back(krho);
+    }
+    if (alt.empty()) return SDC_OK;
+    CHK(ensure_host(h, alt.size() * sizeof(double) + 64));
+    double* hb = reinterpret_cast<double*>(h.host);
+    for (size_t q = 0; q < alt.size(); ++q)
+        HIPCHK(hipMemcpyAsync(hb + q, alt[q]->e + ks[q], sizeof(double), hipMemcpyDeviceToHost, h.stream));
+    HIPCHK(hipStreamSynchronize(h.stream));
+    for (size_t q = 0; q < alt.size(); ++q) {
+        alt[q]->job->info.k_lead = ks[q];
+        alt[q]->job->info.e21_rel = hb[q];
+    }
+    return SDC_OK;
+}
+
+static int refine(Handle& h, std::vector<JobWs*> js) {
+    for (int round = 0; round < kRefineRounds && !js.empty(); ++round) {
+        const size_t mark = h.desc_off;
+        CHK(cg_solve(h, js));
+        CHK(apply_correction(h, js));
+        CHK(block_form(h, js));
+        CHK(split_search(h, js));
+        HIPCHK(hipGetLastError());
+        CHK(fetch_search(h, js));
+        CHK(pin_to_rank(h, js));
+        h.desc_off = mark;
+        std::vector<JobWs*> next;
+        for (JobWs* w : js) {
+            w->job->info.refine_rounds = round + 1;
+            if (wants_refine(*w)) next.push_back(w);
+        }
+        js.swap(next);
+    }
+    return SDC_OK;
+}
+
+// GRURV, block form and split search, then the FP64 refinement where the
+// repeated squaring ran in FP32.
+static int split_pass_refined(Handle& h, std::vector<JobWs*>& js) {
+    CHK(split_pass(h, js));
+    CHK(pin_to_rank(h, js));
+    std::vector<JobWs*> ref;
+    for (JobWs* w : js) {
+        w->job->info.refine_rounds = 0;
+        if (wants_refine(*w)) ref.push_back(w);
+    }
+    if (!ref.empty()) CHK(refine(h, ref));
+    return SDC_OK;
+}
+
 // Accept / retry / classify one attempt (the oracle's rule, Alg. 4 line 5:
 // accept when the minimized norm is small, cross-checked with the rank the
 // GRURV diagonals reveal).  Returns true when the job is finished.
@@ -671,7 +890,7 @@ int run_split_jobs(Handle& h, std::vector<SplitJob>& jobs) {
     std::vector<JobWs*> redo;
     while (!live.empty()) {
         const size_t mark = h.desc_off;
-        CHK(split_pass(h, live));
+        CHK(split_pass_refined(h, live));
         h.desc_off = mark;
         std::vector<JobWs*> next;
         for (JobWs* w : live) {
@@ -688,14 +907,15 @@ int run_split_jobs(Handle& h, std::vector<SplitJob>& jobs) {
             keep.push_back(w->job->info);
             w->attempt = w->best_attempt;
         }
-        CHK(split_pass(h, redo));
+        CHK(split_pass_refined(h, redo));
         for (size_t q = 0; q < redo.size(); ++q) {
             SplitJob& j = *redo[q]->job;
-            const int k = j.info.k_lead;
+            const int k = j.info.k_lead, rr = j.info.refine_rounds;
             const double e = j.info.e21_rel;
             j.info = keep[q];
             j.info.k_lead = k;
             j.info.e21_rel = e;
+            j.info.refine_rounds = rr;
             j.info.n_inside = j.n - k;
         }
         h.desc_off = 0;

@@ -52,6 +52,25 @@ struct GershDesc {
 };
 void gersh_batch(const GershDesc* d, const GershDesc* h, int count, hipStream_t s);
 
+// Conjugate gradients on X A11 - A22 X = E (refine_kernels.hip).  X, R, P, Z
+// are m x k, contiguous (ld m); E has leading dimension lde.  rr is a ring of
+// 3 x kCgMaxBlocks partial sums (slot it % 3 holds rr_it), rr0 and pz hold
+// kCgMaxBlocks partials each; nblk = cg_blocks(m, k).
+constexpr int kCgMaxBlocks = 256;
+struct CgDesc {
+    int m, k;
+    const double* E; int lde;
+    double *X, *R, *P, *Z;
+    double *rr, *rr0, *pz;
+    double tol2;
+    int nblk;
+    int active;
+};
+int cg_blocks(int m, int k);
+void cg_init_batch(const CgDesc* d, const CgDesc* h, int count, hipStream_t s);
+// phase 0: <P, Z>; 1: X, R update; 2: new direction.
+void cg_iter_vec(const CgDesc* d, const CgDesc* h, int count, int it, int phase, hipStream_t s);
+
 template <typename Tin, typename Tout>
 void ew_batch(const EwDesc* d, const EwDesc* h, int count, hipStream_t s);
 template <typename T>
