@@ -228,6 +228,75 @@ sdc_status_t sdc_profile_read(sdc_handle_t h, int kernel, sdc_kernel_stats_t* ou
  * the column-major element index e, then Box-Muller.  G is a device pointer. */
 sdc_status_t sdc_gaussian(sdc_handle_t h, int n, uint64_t seed, int tag, double* G, int ldg);
 
+/* ------------------------------------------------------------------------
+ * Served form: a request loop with continuous batching.
+ *
+ * Split requests (the independent subproblems of Sec. 4.3) are queued by
+ * sdc_server_submit and run by one worker thread that owns its own HIP stream
+ * on `device`.  Requests are admitted in arrival order while the sum of the
+ * admitted requests' workspaces stays within hbm_budget_bytes (0 = 80% of the
+ * device memory free at creation) and at most max_active run at once
+ * (<= 0 = 64).  Admitted requests advance together, one repeated-squaring
+ * iteration per tick (each at its own iteration count), and a request that
+ * arrives while others run joins at the next tick; a request whose squaring
+ * ends is finished (GRURV, block form, split search, refinement) in the tick
+ * it ends, and its workspace is freed for the requests waiting.  A request's
+ * result is the same as that of the single-problem entry point with the same
+ * arguments, whichever requests share its ticks.
+ *
+ * Ownership: the request's input and output pointers are DEVICE pointers the
+ * caller keeps valid (and does not write) until the request is reported done;
+ * the inputs must be complete (their producer synchronized) before the call.
+ * Outputs are complete when sdc_server_poll reports done or sdc_server_wait
+ * returns.  A request whose workspace alone exceeds the budget finishes with
+ * SDC_ERR_NOMEM.
+ * ------------------------------------------------------------------------ */
+typedef struct sdc_server_s* sdc_server_t;
+
+typedef enum { SDC_REQ_SYM = 0, SDC_REQ_PENCIL = 1 } sdc_request_kind_t;
+
+typedef struct {
+    int kind;            /* sdc_request_kind_t */
+    int n;
+    const double* A; int lda;
+    const double* B; int ldb;       /* pencils */
+    sdc_region_t region;
+    sdc_opts_t opts;
+    double* Q; int ldq;             /* Q (symmetric) or Q_R */
+    double* QL; int ldql;           /* pencils */
+    double* Ahat; int ldah;
+    double* Bhat; int ldbh;         /* pencils */
+} sdc_request_t;
+
+typedef struct {
+    long long submitted, completed, failed;
+    int active;          /* requests running now */
+    int pending;         /* requests waiting for admission */
+    int peak_active;     /* most requests that ran in one tick */
+    long long ticks;
+    double p50_ms, p99_ms, mean_ms, max_ms;   /* latency, submission to completion */
+    double wall_ms;      /* first submission to last completion */
+    double nominal_flops;/* sum over completed requests of the split flop model */
+    size_t peak_bytes;   /* largest sum of admitted workspaces */
+    size_t budget_bytes;
+} sdc_server_stats_t;
+
+/* Start a server (and its worker thread) on `device`. */
+sdc_status_t sdc_server_create(sdc_server_t* server, int device, size_t hbm_budget_bytes, int max_active);
+/* Queue a request; *ticket identifies it.  Validation as in sdc_split_sym /
+ * sdc_split_pencil (SDC_ERR_INVALID, nothing queued). */
+sdc_status_t sdc_server_submit(sdc_server_t server, const sdc_request_t* req, long long* ticket);
+/* *done = 1 once the request finished; then *status and *info (may be NULL)
+ * hold its result and the ticket is released.  SDC_ERR_INVALID for an unknown
+ * or released ticket. */
+sdc_status_t sdc_server_poll(sdc_server_t server, long long ticket, int* done, int* status, sdc_info_t* info);
+/* Block until the request finished, then as sdc_server_poll with *done = 1. */
+sdc_status_t sdc_server_wait(sdc_server_t server, long long ticket, int* status, sdc_info_t* info);
+/* Latency percentiles, throughput counters, admission state. */
+sdc_status_t sdc_server_stats(sdc_server_t server, sdc_server_stats_t* out);
+/* Finish every queued request, stop the worker and free the server. */
+sdc_status_t sdc_server_destroy(sdc_server_t server);
+
 #ifdef __cplusplus
 }
 #endif

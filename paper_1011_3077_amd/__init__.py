@@ -29,7 +29,9 @@ SDC_UNIT_DISK, SDC_DISK, SDC_HALFPLANE = 0, 1, 2
 
 EXPORTED = ["sdc_opts_default", "sdc_create", "sdc_destroy", "sdc_status_string", "sdc_irs",
             "sdc_split_sym", "sdc_split_pencil", "sdc_split_sym_batched", "sdc_eig_dc", "sdc_gaussian",
-            "sdc_profile_enable", "sdc_profile_read"]
+            "sdc_profile_enable", "sdc_profile_read", "sdc_server_create", "sdc_server_submit",
+            "sdc_server_poll", "sdc_server_wait", "sdc_server_stats", "sdc_server_destroy"]
+SDC_REQ_SYM, SDC_REQ_PENCIL = 0, 1
 
 
 class Region(C.Structure):
@@ -71,6 +73,24 @@ class KernelStats(C.Structure):
 
 KERNEL_UPDATE, KERNEL_PANEL, KERNEL_GEMM = 0, 1, 2
 
+
+class Request(C.Structure):
+    _fields_ = [("kind", C.c_int), ("n", C.c_int), ("A", C.c_void_p), ("lda", C.c_int), ("B", C.c_void_p),
+                ("ldb", C.c_int), ("region", Region), ("opts", Opts), ("Q", C.c_void_p), ("ldq", C.c_int),
+                ("QL", C.c_void_p), ("ldql", C.c_int), ("Ahat", C.c_void_p), ("ldah", C.c_int),
+                ("Bhat", C.c_void_p), ("ldbh", C.c_int)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_longlong), ("completed", C.c_longlong), ("failed", C.c_longlong),
+                ("active", C.c_int), ("pending", C.c_int), ("peak_active", C.c_int), ("ticks", C.c_longlong),
+                ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double), ("max_ms", C.c_double),
+                ("wall_ms", C.c_double), ("nominal_flops", C.c_double), ("peak_bytes", C.c_size_t),
+                ("budget_bytes", C.c_size_t)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
 _P = C.c_void_p
 _I = C.c_int
 lib.sdc_opts_default.argtypes = [C.POINTER(Opts)]
@@ -102,6 +122,18 @@ lib.sdc_profile_read.argtypes = [_P, _I, C.POINTER(KernelStats)]
 lib.sdc_profile_read.restype = _I
 lib.sdc_gaussian.argtypes = [_P, _I, C.c_uint64, _I, _P, _I]
 lib.sdc_gaussian.restype = _I
+lib.sdc_server_create.argtypes = [C.POINTER(_P), _I, C.c_size_t, _I]
+lib.sdc_server_create.restype = _I
+lib.sdc_server_submit.argtypes = [_P, C.POINTER(Request), C.POINTER(C.c_longlong)]
+lib.sdc_server_submit.restype = _I
+lib.sdc_server_poll.argtypes = [_P, C.c_longlong, C.POINTER(_I), C.POINTER(_I), C.POINTER(Info)]
+lib.sdc_server_poll.restype = _I
+lib.sdc_server_wait.argtypes = [_P, C.c_longlong, C.POINTER(_I), C.POINTER(Info)]
+lib.sdc_server_wait.restype = _I
+lib.sdc_server_stats.argtypes = [_P, C.POINTER(ServerStats)]
+lib.sdc_server_stats.restype = _I
+lib.sdc_server_destroy.argtypes = [_P]
+lib.sdc_server_destroy.restype = _I
 
 
 def status_string(s: int) -> str:
@@ -262,3 +294,75 @@ class Handle:
         g = torch.empty((n, n), dtype=torch.float64, device=f"cuda:{self.device}")
         _check(lib.sdc_gaussian(self._h, n, seed, tag, g.data_ptr(), n))
         return g.t()
+
+
+class Server:
+    """Served form (sdc_server_*): requests are queued and run with continuous
+    batching on the library's own worker thread and stream.  submit() keeps
+    the column-major inputs and the outputs alive until the request is done."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0, max_active: int = 0):
+        self.device = device
+        s = C.c_void_p()
+        _check(lib.sdc_server_create(C.byref(s), device, budget_bytes, max_active))
+        self._s = s
+        self._live = {}
+
+    def close(self):
+        if getattr(self, "_s", None):
+            lib.sdc_server_destroy(self._s)
+            self._s = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, A, B=None, reg: Region | None = None, o: Opts | None = None) -> int:
+        """Queue a split of symmetric A (B is None) or of the pencil (A, B)."""
+        import torch
+        n = A.shape[0]
+        a = _cm(A)
+        b = _cm(B) if B is not None else None
+        q, ah = _out(n, A), _out(n, A)
+        ql = _out(n, A) if b is not None else None
+        bh = _out(n, A) if b is not None else None
+        torch.cuda.synchronize(A.device)  # inputs complete before the worker reads them
+        r = Request()
+        r.kind = SDC_REQ_PENCIL if b is not None else SDC_REQ_SYM
+        r.n = n
+        r.A, r.lda = a.data_ptr(), n
+        r.B, r.ldb = (b.data_ptr() if b is not None else None), n
+        r.region = reg or region()
+        r.opts = o or opts()
+        r.Q, r.ldq = q.data_ptr(), n
+        r.QL, r.ldql = (ql.data_ptr() if ql is not None else None), n
+        r.Ahat, r.ldah = ah.data_ptr(), n
+        r.Bhat, r.ldbh = (bh.data_ptr() if bh is not None else None), n
+        t = C.c_longlong()
+        _check(lib.sdc_server_submit(self._s, C.byref(r), C.byref(t)))
+        self._live[t.value] = (a, b, q, ql, ah, bh)
+        return t.value
+
+    def _result(self, ticket, st, info) -> SplitResult:
+        a, b, q, ql, ah, bh = self._live.pop(ticket)
+        tr = lambda x: None if x is None else x.t()
+        return SplitResult(st, info.as_dict(), tr(q), tr(ql), tr(ah), tr(bh))
+
+    def poll(self, ticket: int):
+        """None while running, else the SplitResult."""
+        done, st, info = C.c_int(), C.c_int(), Info()
+        _check(lib.sdc_server_poll(self._s, ticket, C.byref(done), C.byref(st), C.byref(info)))
+        return self._result(ticket, st.value, info) if done.value else None
+
+    def wait(self, ticket: int) -> SplitResult:
+        st, info = C.c_int(), Info()
+        _check(lib.sdc_server_wait(self._s, ticket, C.byref(st), C.byref(info)))
+        return self._result(ticket, st.value, info)
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(lib.sdc_server_stats(self._s, C.byref(s)))
+        return s.as_dict()

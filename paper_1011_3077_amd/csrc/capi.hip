@@ -18,15 +18,9 @@ struct sdc_handle_s {
 
 namespace {
 
-// Largest order the tree QR supports: 2n rows give at most 128 leaves.
-constexpr int kMaxN = 16384;
-
-bool region_ok(const sdc_region_t& r) {
-    if (r.kind == SDC_UNIT_DISK) return true;
-    if (r.kind == SDC_DISK) return std::isfinite(r.center) && std::isfinite(r.radius) && r.radius > 0;
-    if (r.kind == SDC_HALFPLANE) return std::isfinite(r.shift) && std::isfinite(r.scale) && r.scale >= 0;
-    return false;
-}
+using sdc::kMaxN;
+using sdc::prec_ok;
+using sdc::region_ok;
 
 int use_device(Handle& h) {
     return hipSetDevice(h.device) == hipSuccess ? SDC_OK : SDC_ERR_DEVICE;
@@ -44,10 +38,7 @@ sdc_opts_t resolve(const sdc_opts_t* o) {
     else sdc_opts_default(&r);
     return r;
 }
-bool prec_ok(const sdc_opts_t& o, bool pencil) {
-    if (o.prec == SDC_FP64) return true;
-    return o.prec == SDC_FP32_REFINE && !pencil;
-}
+
 
 }  // namespace
 
@@ -107,6 +98,7 @@ sdc_status_t sdc_destroy(sdc_handle_t handle) {
     if (h.desc_h) (void)hipHostFree(h.desc_h);
     if (h.host) (void)hipHostFree(h.host);
     if (h.ws2) (void)hipFree(h.ws2);
+    if (h.dnorm) (void)hipFree(h.dnorm);
     delete handle;
     return SDC_OK;
 }

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <new>
 #include <vector>
 
 #include "engine.hpp"
@@ -50,6 +51,7 @@ template <typename T> struct IrsSide {
     T* W = nullptr; double* Rprev = nullptr; T* diag = nullptr; double* norms = nullptr;
     T* Tm = nullptr; unsigned* counters = nullptr;
     int p = 0, converged = 0, nonfinite = 0;
+    int started = 0, done = 0;
     double rconv = NAN;
 };
 
@@ -74,64 +76,83 @@ template <typename T> static QrDesc<T> qr_desc(T* W, int ld, int m, int nf, int 
     return d;
 }
 
-template <typename T> static int run_irs(Handle& h, std::vector<IrsSide<T>*>& sides, double* norms_all) {
-    const int cnt = (int)sides.size();
+// Set-up of the sides not started yet: W <- [B0 A0 0; -A0 0 B0] from the
+// inputs and the region map; tree counters cleared.
+template <typename T> static int irs_start(Handle& h, std::vector<IrsSide<T>*>& sides) {
+    std::vector<IrsInit<T>> ini;
+    for (IrsSide<T>* sp : sides) {
+        IrsSide<T>& s = *sp;
+        if (s.started) continue;
+        ini.push_back(IrsInit<T>{s.W, s.n, s.A, s.lda, s.B, s.ldb, s.a1, s.a2, s.b1, s.b2, s.trans});
+        fill<unsigned>(s.counters, kMaxInternal, 0u, h.stream);
+        s.p = 0; s.converged = 0; s.nonfinite = 0; s.rconv = NAN; s.done = 0; s.started = 1;
+    }
+    if (ini.empty()) return SDC_OK;
+    UPLOAD(dini, ini);
+    irs_init_batch<T>(dini, ini.data(), (int)ini.size(), h.stream);
+    return SDC_OK;
+}
+
+// One repeated-squaring iteration (QR of the stacked pair, updates, sign
+// normalization and convergence test) for every started side that is not
+// done, each at its own iteration count.  Sides may join between ticks.
+// *left receives the number of sides still iterating.
+template <typename T> static int irs_tick(Handle& h, std::vector<IrsSide<T>*>& sides, int* left) {
+    std::vector<IrsSide<T>*> act;
+    for (IrsSide<T>* sp : sides)
+        if (sp->started && !sp->done) act.push_back(sp);
+    *left = 0;
+    const int cnt = (int)act.size();
     if (!cnt) return SDC_OK;
-    std::vector<IrsInit<T>> ini(cnt);
+    CHK(ensure_dnorm(h, 4 * (size_t)cnt));
+    CHK(ensure_host(h, sizeof(double) * 4 * cnt));
     std::vector<QrDesc<T>> qd(cnt);
     std::vector<IrsDesc<T>> pd(cnt);
     for (int i = 0; i < cnt; ++i) {
-        IrsSide<T>& s = *sides[i];
-        s.norms = norms_all + 4 * i;
-        ini[i] = IrsInit<T>{s.W, s.n, s.A, s.lda, s.B, s.ldb, s.a1, s.a2, s.b1, s.b2, s.trans};
+        IrsSide<T>& s = *act[i];
+        s.norms = h.dnorm + 4 * i;
         qd[i] = qr_desc<T>(s.W, 2 * s.n, 2 * s.n, s.n, 3 * s.n, s.Tm, s.diag, s.counters);
         pd[i] = IrsDesc<T>{s.W, s.n, s.Rprev, s.diag, s.norms, 1};
-        fill<unsigned>(s.counters, kMaxInternal, 0u, h.stream);
-        s.p = 0; s.converged = 0; s.nonfinite = 0; s.rconv = NAN;
     }
-    UPLOAD(dini, ini);
-    irs_init_batch<T>(dini, ini.data(), cnt, h.stream);
-    CHK(ensure_host(h, sizeof(double) * 4 * cnt));
-    double* hn = reinterpret_cast<double*>(h.host);
-    HIPCHK(hipStreamSynchronize(h.stream));
     const size_t mark = h.desc_off;
-    for (int it = 0;; ++it) {
-        h.desc_off = mark;
-        UPLOAD(dq, qd);
-        UPLOAD(dp, pd);
-        fill<double>(norms_all, 4 * (size_t)cnt, 0.0, h.stream);
-        qr_aug_batch<T>(dq, qd.data(), cnt, h.stream);
-        irs_post_batch<T>(dp, pd.data(), cnt, it == 0, h.stream);
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(hn, norms_all, sizeof(double) * 4 * cnt, hipMemcpyDeviceToHost, h.stream));
-        HIPCHK(hipStreamSynchronize(h.stream));
-        int any = 0;
-        for (int i = 0; i < cnt; ++i) {
-            if (!qd[i].active) continue;
-            IrsSide<T>& s = *sides[i];
-            const double diff = hn[4 * i], ref = hn[4 * i + 1], cur = hn[4 * i + 2];
-            s.p = it + 1;
-            bool stop = false;
-            if (!std::isfinite(cur) || (it > 0 && !std::isfinite(diff))) {
-                s.nonfinite = 1;
+    UPLOAD(dq, qd);
+    UPLOAD(dp, pd);
+    fill<double>(h.dnorm, 4 * (size_t)cnt, 0.0, h.stream);
+    qr_aug_batch<T>(dq, qd.data(), cnt, h.stream);
+    irs_post_batch<T>(dp, pd.data(), cnt, 0, h.stream);
+    HIPCHK(hipGetLastError());
+    double* hn = reinterpret_cast<double*>(h.host);
+    HIPCHK(hipMemcpyAsync(hn, h.dnorm, sizeof(double) * 4 * cnt, hipMemcpyDeviceToHost, h.stream));
+    HIPCHK(hipStreamSynchronize(h.stream));
+    h.desc_off = mark;
+    for (int i = 0; i < cnt; ++i) {
+        IrsSide<T>& s = *act[i];
+        const int it = s.p;  // iteration index j of Alg. 3
+        const double diff = hn[4 * i], ref = hn[4 * i + 1], cur = hn[4 * i + 2];
+        s.p = it + 1;
+        bool stop = false;
+        if (!std::isfinite(cur) || (it > 0 && !std::isfinite(diff))) {
+            s.nonfinite = 1;
+            stop = true;
+        } else if (it > 0) {
+            s.rconv = ref > 0 ? diff / ref : INFINITY;
+            if (diff <= s.tau * ref) {
+                s.converged = 1;
                 stop = true;
-            } else if (it > 0) {
-                s.rconv = ref > 0 ? diff / ref : INFINITY;
-                if (diff <= s.tau * ref) {
-                    s.converged = 1;
-                    stop = true;
-                }
-            }
-            if (!stop && it + 1 > s.maxit) stop = true;
-            if (stop) {
-                qd[i].active = 0;
-                pd[i].active = 0;
-            } else {
-                any = 1;
             }
         }
-        if (!any) break;
+        if (!stop && it + 1 > s.maxit) stop = true;
+        if (stop) s.done = 1;
+        else ++*left;
     }
+    return SDC_OK;
+}
+
+template <typename T> static int run_irs(Handle& h, std::vector<IrsSide<T>*>& sides) {
+    if (sides.empty()) return SDC_OK;
+    for (IrsSide<T>* sp : sides) sp->started = 0;
+    CHK(irs_start<T>(h, sides));
+    for (int left = 1; left;) CHK(irs_tick<T>(h, sides, &left));
     return SDC_OK;
 }
 
@@ -776,20 +797,57 @@ static void fill_defaults(sdc_opts_t& o) {
     if (o.max_retries < 0) o.max_retries = 0;
 }
 
+// Side parameters of a job (the region map and the tolerances).
+static void setup_sides(JobWs& w) {
+    SplitJob& j = *w.job;
+    double a1, a2, b1, b2;
+    region_coeffs(j.region, a1, a2, b1, b2);
+    const int ns = j.pencil ? 2 : 1;
+    for (int s = 0; s < ns; ++s) {
+        auto setup = [&](auto& side, double eps) {
+            side.n = j.n; side.A = j.A; side.lda = j.lda;
+            side.B = j.pencil ? j.B : nullptr; side.ldb = j.ldb;
+            side.trans = s; side.a1 = a1; side.a2 = a2; side.b1 = b1; side.b2 = b2;
+            side.tau = j.opts.tau > 0 ? j.opts.tau : std::sqrt(eps);
+            side.maxit = j.opts.maxit;
+            side.started = 0; side.done = 0;
+        };
+        if (w.fp32) setup(w.sf[s], (double)std::numeric_limits<float>::epsilon());
+        else setup(w.sd[s], std::numeric_limits<double>::epsilon());
+    }
+}
+
+static void collect_sides(std::vector<JobWs*>& js, std::vector<IrsSide<double>*>& sd,
+                          std::vector<IrsSide<float>*>& sf) {
+    for (JobWs* w : js) {
+        const int ns = w->job->pencil ? 2 : 1;
+        for (int s = 0; s < ns; ++s) {
+            if (w->fp32) sf.push_back(&w->sf[s]);
+            else sd.push_back(&w->sd[s]);
+        }
+    }
+}
+
+static bool irs_finished(const JobWs& w) {
+    const int ns = w.job->pencil ? 2 : 1;
+    for (int s = 0; s < ns; ++s)
+        if (!(w.fp32 ? w.sf[s].done : w.sd[s].done)) return false;
+    return true;
+}
+
+static int finish_jobs(Handle& h, std::vector<JobWs*>& wsp);
+
 int run_split_jobs(Handle& h, std::vector<SplitJob>& jobs) {
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<JobWs> ws(jobs.size());
-    int nsides = 0;
     for (size_t i = 0; i < jobs.size(); ++i) {
         fill_defaults(jobs[i].opts);
         ws[i].job = &jobs[i];
         ws[i].fp32 = jobs[i].opts.prec == SDC_FP32_REFINE;
-        nsides += jobs[i].pencil ? 2 : 1;
     }
     // workspace: size pass, then carve
-    auto layout = [&](Carver& c) -> double* {
+    auto layout = [&](Carver& c) {
         for (JobWs& w : ws) job_layout(c, w);
-        return c.take<double>(4 * (size_t)nsides);
     };
     {
         Carver c0(nullptr);
@@ -797,48 +855,45 @@ int run_split_jobs(Handle& h, std::vector<SplitJob>& jobs) {
         CHK(ensure_ws(h, c0.off + 4096));
     }
     Carver c(h.ws, h.ws_size);
-    double* norms_all = layout(c);
+    layout(c);
     if (c.overflow) return SDC_ERR_NOMEM;
     CHK(ensure_desc(h, (size_t)(64 << 10) + jobs.size() * (size_t)(8 << 10)));
     h.desc_off = 0;
 
-    // IRS on every side, FP64 and FP32 sides in separate lockstep batches
+    // IRS on every side: FP64 and FP32 sides advance one iteration per tick,
+    // each until its own convergence test passes
+    std::vector<JobWs*> wsp;
+    for (JobWs& w : ws) {
+        setup_sides(w);
+        wsp.push_back(&w);
+    }
     std::vector<IrsSide<double>*> sd;
     std::vector<IrsSide<float>*> sf;
-    for (JobWs& w : ws) {
-        SplitJob& j = *w.job;
-        double a1, a2, b1, b2;
-        region_coeffs(j.region, a1, a2, b1, b2);
-        const int ns = j.pencil ? 2 : 1;
-        for (int s = 0; s < ns; ++s) {
-            auto setup = [&](auto& side, double eps) {
-                side.n = j.n; side.A = j.A; side.lda = j.lda;
-                side.B = j.pencil ? j.B : nullptr; side.ldb = j.ldb;
-                side.trans = s; side.a1 = a1; side.a2 = a2; side.b1 = b1; side.b2 = b2;
-                side.tau = j.opts.tau > 0 ? j.opts.tau : std::sqrt(eps);
-                side.maxit = j.opts.maxit;
-            };
-            if (w.fp32) {
-                setup(w.sf[s], (double)std::numeric_limits<float>::epsilon());
-                sf.push_back(&w.sf[s]);
-            } else {
-                setup(w.sd[s], std::numeric_limits<double>::epsilon());
-                sd.push_back(&w.sd[s]);
-            }
-        }
+    collect_sides(wsp, sd, sf);
+    CHK(irs_start<double>(h, sd));
+    CHK(irs_start<float>(h, sf));
+    for (int l64 = 1, l32 = 1; l64 || l32;) {
+        CHK(irs_tick<double>(h, sd, &l64));
+        CHK(irs_tick<float>(h, sf, &l32));
     }
-    double* nd = norms_all;
-    double* nf = norms_all + 4 * sd.size();
-    CHK(run_irs<double>(h, sd, nd));
     h.desc_off = 0;
-    CHK(run_irs<float>(h, sf, nf));
-    h.desc_off = 0;
+    CHK(finish_jobs(h, wsp));
+    HIPCHK(hipStreamSynchronize(h.stream));
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (JobWs& w : ws) w.job->info.ms = ms;
+    return SDC_OK;
+}
 
+// Everything after the repeated squaring, for jobs whose sides are all done:
+// FP64 views of (A_p, B_p), input norms, GRURV + block form + split search
+// with retries (and the FP64 refinement for FP32 jobs), diagnostics, status.
+static int finish_jobs(Handle& h, std::vector<JobWs*>& wsp) {
     // views of (A_p, B_p) in FP64; norms of the inputs
     std::vector<EwDesc> conv;
     std::vector<NormDesc> nrm;
     std::vector<JobWs*> live;
-    for (JobWs& w : ws) {
+    for (JobWs* wp : wsp) {
+        JobWs& w = *wp;
         SplitJob& j = *w.job;
         const int n = j.n;
         j.info.n = n;
@@ -925,7 +980,8 @@ int run_split_jobs(Handle& h, std::vector<SplitJob>& jobs) {
     std::vector<GemmDesc<double>> go;
     std::vector<NormDesc> no;
     std::vector<JobWs*> diag_jobs;
-    for (JobWs& w : ws) {
+    for (JobWs* wp : wsp) {
+        JobWs& w = *wp;
         SplitJob& j = *w.job;
         if (!j.opts.diagnostics || w.status < 0) continue;
         go.push_back(gemm(j.n, j.Q, j.ldq, 1, j.Q, j.ldq, 0, w.T1, j.n));
@@ -944,11 +1000,79 @@ int run_split_jobs(Handle& h, std::vector<SplitJob>& jobs) {
         for (size_t q = 0; q < diag_jobs.size(); ++q) diag_jobs[q]->job->info.orth_err = std::sqrt(hb[q]);
     }
     HIPCHK(hipStreamSynchronize(h.stream));
-    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    for (JobWs& w : ws) {
-        w.job->status = w.status;
-        w.job->info.ms = ms;
+    for (JobWs* w : wsp) w->job->status = w->status;
+    return SDC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Incremental driver for continuous batching: a job owns its workspace and
+// advances by ticks; jobs may start and finish between ticks.
+// ---------------------------------------------------------------------------
+struct JobRun {
+    JobWs w;
+    bool finished = false;
+};
+
+size_t job_run_bytes(const SplitJob& j0) {
+    SplitJob j = j0;
+    fill_defaults(j.opts);
+    JobWs w;
+    w.job = &j;
+    w.fp32 = j.opts.prec == SDC_FP32_REFINE;
+    Carver c(nullptr);
+    job_layout(c, w);
+    return c.off + 256;
+}
+
+JobRun* job_run_create(SplitJob* j, char* ws, size_t bytes) {
+    fill_defaults(j->opts);
+    JobRun* r = new (std::nothrow) JobRun;
+    if (!r) return nullptr;
+    r->w.job = j;
+    r->w.fp32 = j->opts.prec == SDC_FP32_REFINE;
+    Carver c(ws, bytes);
+    job_layout(c, r->w);
+    if (c.overflow) {
+        delete r;
+        return nullptr;
     }
+    setup_sides(r->w);
+    return r;
+}
+
+void job_run_destroy(JobRun* r) { delete r; }
+
+int job_runs_tick(Handle& h, std::vector<JobRun*>& runs, std::vector<char>& done) {
+    done.assign(runs.size(), 0);
+    CHK(ensure_desc(h, (size_t)(64 << 10) + runs.size() * (size_t)(8 << 10)));
+    h.desc_off = 0;  // every earlier tick ended with a stream synchronization
+    std::vector<JobWs*> wsp;
+    for (JobRun* r : runs)
+        if (!r->finished) wsp.push_back(&r->w);
+    std::vector<IrsSide<double>*> sd;
+    std::vector<IrsSide<float>*> sf;
+    collect_sides(wsp, sd, sf);
+    CHK(irs_start<double>(h, sd));
+    CHK(irs_start<float>(h, sf));
+    int l64 = 0, l32 = 0;
+    CHK(irs_tick<double>(h, sd, &l64));
+    CHK(irs_tick<float>(h, sf, &l32));
+    std::vector<JobWs*> fin;
+    std::vector<size_t> idx;
+    for (size_t i = 0; i < runs.size(); ++i)
+        if (!runs[i]->finished && irs_finished(runs[i]->w)) {
+            fin.push_back(&runs[i]->w);
+            idx.push_back(i);
+        }
+    if (!fin.empty()) {
+        h.desc_off = 0;
+        CHK(finish_jobs(h, fin));
+        for (size_t i : idx) {
+            runs[i]->finished = true;
+            done[i] = 1;
+        }
+    }
+    HIPCHK(hipStreamSynchronize(h.stream));
     return SDC_OK;
 }
 
@@ -970,10 +1094,9 @@ int run_irs_only(Handle& h, int n, const double* A, int lda, const double* B, in
     };
     sdd.n = n;
     sff.n = n;
-    auto layout = [&](Carver& c) -> double* {
+    auto layout = [&](Carver& c) {
         if (fp32) irs_layout(c, sff);
         else irs_layout(c, sdd);
-        return c.take<double>(4);
     };
     {
         Carver c0(nullptr);
@@ -981,7 +1104,7 @@ int run_irs_only(Handle& h, int n, const double* A, int lda, const double* B, in
         CHK(ensure_ws(h, c0.off + 4096));
     }
     Carver c(h.ws, h.ws_size);
-    double* norms = layout(c);
+    layout(c);
     if (c.overflow) return SDC_ERR_NOMEM;
     CHK(ensure_desc(h, 64 << 10));
     h.desc_off = 0;
@@ -990,12 +1113,12 @@ int run_irs_only(Handle& h, int n, const double* A, int lda, const double* B, in
     if (fp32) {
         setup(sff, (double)std::numeric_limits<float>::epsilon());
         std::vector<IrsSide<float>*> v{&sff};
-        CHK(run_irs<float>(h, v, norms));
+        CHK(run_irs<float>(h, v));
         nonfinite = sff.nonfinite; converged = sff.converged; *p = sff.p; *rconv = sff.rconv; W = sff.W;
     } else {
         setup(sdd, std::numeric_limits<double>::epsilon());
         std::vector<IrsSide<double>*> v{&sdd};
-        CHK(run_irs<double>(h, v, norms));
+        CHK(run_irs<double>(h, v));
         nonfinite = sdd.nonfinite; converged = sdd.converged; *p = sdd.p; *rconv = sdd.rconv; W = sdd.W;
     }
     h.desc_off = 0;

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstddef>
+#include <cmath>
 #include <cstdint>
 #include <vector>
 
@@ -30,6 +31,9 @@ struct Handle {
     // second device workspace, owned by the divide-and-conquer driver
     char* ws2 = nullptr;
     size_t ws2_size = 0;
+    // per-tick convergence norms of the repeated squaring (4 per side)
+    double* dnorm = nullptr;
+    size_t dnorm_cap = 0;
     // opt-in kernel timing
     Profiler prof;
 };
@@ -40,6 +44,21 @@ struct ProfScope {
     explicit ProfScope(Handle& h) : prev(g_prof) { g_prof = h.prof.on ? &h.prof : nullptr; }
     ~ProfScope() { g_prof = prev; }
 };
+
+// Argument checks shared by the entry points.
+// Largest order the tree QR supports: 2n rows give at most 128 leaves.
+constexpr int kMaxN = 16384;
+inline bool region_ok(const sdc_region_t& r) {
+    if (r.kind == SDC_UNIT_DISK) return true;
+    if (r.kind == SDC_DISK) return std::isfinite(r.center) && std::isfinite(r.radius) && r.radius > 0;
+    if (r.kind == SDC_HALFPLANE) return std::isfinite(r.shift) && std::isfinite(r.scale) && r.scale >= 0;
+    return false;
+}
+// SDC_FP32_REFINE is for symmetric problems only.
+inline bool prec_ok(const sdc_opts_t& o, bool pencil) {
+    if (o.prec == SDC_FP64) return true;
+    return o.prec == SDC_FP32_REFINE && !pencil;
+}
 
 // One split problem (symmetric or pencil) as the drivers see it.
 struct SplitJob {
@@ -67,6 +86,19 @@ int run_irs_only(Handle& h, int n, const double* A, int lda, const double* B, in
                  int ldo, int* p, double* rconv);
 
 int run_gaussian(Handle& h, int n, uint64_t seed, int tag, double* G, int ldg);
+
+// Incremental driver (continuous batching).  A JobRun holds one split job's
+// state in a caller-provided device workspace of job_run_bytes() bytes; each
+// job_runs_tick() starts the runs not started yet, advances every run still
+// in its repeated squaring by one iteration, and finishes (GRURV, block form,
+// split search, refinement) the runs whose squaring ended; done[i] is set for
+// runs that finished in this tick.  A run's result does not depend on which
+// other runs share its ticks.
+struct JobRun;
+size_t job_run_bytes(const SplitJob& j);
+JobRun* job_run_create(SplitJob* j, char* ws, size_t bytes);
+void job_run_destroy(JobRun* r);
+int job_runs_tick(Handle& h, std::vector<JobRun*>& runs, std::vector<char>& done);
 
 // Randomized divide-and-conquer; see sdc_eig_dc.
 int run_eig_dc(Handle& h, int n, const double* A, int lda, const double* B, int ldb, int symmetric, int leaf_max,

@@ -80,6 +80,20 @@ inline int ensure_desc(Handle& h, size_t bytes) {
     return SDC_OK;
 }
 
+inline int ensure_dnorm(Handle& h, size_t elems) {
+    if (elems <= h.dnorm_cap) return SDC_OK;
+    if (h.dnorm) {
+        HIPCHK(hipStreamSynchronize(h.stream));
+        HIPCHK(hipFree(h.dnorm));
+        h.dnorm = nullptr;
+        h.dnorm_cap = 0;
+    }
+    const size_t cap = elems < 1024 ? 1024 : elems;
+    if (hipMalloc(reinterpret_cast<void**>(&h.dnorm), cap * sizeof(double)) != hipSuccess) return SDC_ERR_NOMEM;
+    h.dnorm_cap = cap;
+    return SDC_OK;
+}
+
 inline int ensure_host(Handle& h, size_t bytes) {
     if (bytes <= h.host_size) return SDC_OK;
     if (h.host) {

@@ -1,0 +1,108 @@
+"""Full-size workloads through the C ABI, checked by properties that hold at
+any size and on sampled outputs (the FP64 oracle would take minutes here):
+
+* batched: 512 symmetric problems, n log-uniform in [32, 256], FP32 repeated
+  squaring + FP64 refinement in one batched call; every problem's rank is the
+  construction's, E21 and the block eigenvalues meet the FP32+refine bar, and
+  a sample of problems matches the FP64 oracle's subspace;
+* clustered order 8192 (half the eigenvalues in [-1, -0.01], half in
+  [0.01, 1], 5% per side within 1e-3 of -+0.01): FP32+refine and FP64 give the
+  exact rank n/2, E21 <= split_tol |A|_1, block eigenvalues within 1e-9 |A|_2
+  of the construction, and orthonormal columns on a sample.
+"""
+import numpy as np
+import pytest
+
+import sdc_synth as S
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sdc():
+    import paper_1011_3077_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def handle(sdc):
+    h = sdc.Handle(0)
+    yield h
+    h.close()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def norm1(x):
+    return float(np.max(np.sum(np.abs(x), axis=0)))
+
+
+def sin_theta(x, y):
+    qx, _ = np.linalg.qr(x)
+    qy, _ = np.linalg.qr(y)
+    return float(np.linalg.norm(qy - qx @ (qx.T @ qy), 2))
+
+
+def test_batched_512_fp32_refine(handle, sdc):
+    import oracle as O
+    sizes = S.batch_sizes(512, S.family_seed(2))
+    print("CASE batched 512, sizes", min(sizes), max(sizes), flush=True)
+    probs = [S.sym_problem(n, S.family_seed(2, i)) for i, n in enumerate(sizes)]
+    reg = sdc.region("halfplane", shift=0.0, scale=1.0)
+    out = handle.split_sym_batched([dev(a) for a, _, _ in probs], [reg] * len(sizes),
+                                   sdc.opts(prec=sdc.SDC_FP32_REFINE, seed=3))
+    worst_e, worst_ev = 0.0, 0.0
+    for i, ((a, d, q), r) in enumerate(zip(probs, out)):
+        n = sizes[i]
+        assert r.status == 0, (i, n, r.status)
+        k = r.info["k_lead"]
+        assert k == int((d > 0).sum()), (i, n)
+        ah = r.Ahat.cpu().numpy()
+        worst_e = max(worst_e, norm1(ah[k:, :k]) / norm1(a))
+        ev = np.sort(np.concatenate([np.linalg.eigvalsh(ah[:k, :k]), np.linalg.eigvalsh(ah[k:, k:])]))
+        worst_ev = max(worst_ev, np.abs(ev - np.sort(d)).max())
+    print("worst e21", worst_e, "worst eig err", worst_ev, flush=True)
+    assert worst_e <= 1e-10 and worst_ev <= 1e-9
+    for i in (0, 101, 257, 511):
+        a, d, q = probs[i]
+        ref = O.split_sym(a, {"kind": "halfplane", "shift": 0.0, "scale": 1.0}, seed=3)
+        k = out[i].info["k_lead"]
+        assert ref.k == k
+        assert sin_theta(out[i].Q.cpu().numpy()[:, :k], ref.Q[:, :k]) <= 1e-9
+
+
+@pytest.fixture(scope="module")
+def clustered8192():
+    n = 8192
+    print("CASE generating clustered order", n, flush=True)
+    a, d, q = S.clustered_sym_problem(n, S.family_seed(3))
+    return a, d
+
+
+@pytest.mark.parametrize("prec", ["fp32_refine", "fp64"])
+def test_clustered_8192(handle, sdc, clustered8192, prec):
+    a, d = clustered8192
+    n = a.shape[0]
+    print("CASE clustered 8192", prec, flush=True)
+    p = sdc.SDC_FP32_REFINE if prec == "fp32_refine" else sdc.SDC_FP64
+    A = dev(a)
+    r = handle.split_sym(A, sdc.region("halfplane", shift=0.0, scale=1.0), sdc.opts(prec=p, seed=1))
+    print("info", r.info, flush=True)
+    assert r.status == 0
+    k = r.info["k_lead"]
+    assert k == n // 2 == int((d > 0).sum())
+    # E21 on the device (sampled nothing: the whole block is cheap to reduce there)
+    e21 = r.Ahat[k:, :k].abs().sum(dim=0).max().item()
+    assert e21 <= 1e-10 * norm1(a)
+    # orthonormal columns on a sample of 384 columns
+    rng = np.random.default_rng(0)
+    idx = torch.from_numpy(rng.choice(n, 384, replace=False)).to("cuda:0")
+    qs = r.Q[:, idx]
+    g = (qs.T @ qs - torch.eye(384, dtype=torch.float64, device="cuda:0")).abs().max().item()
+    assert g <= 1e-13 * np.sqrt(n)
+    ah = r.Ahat.cpu().numpy()
+    ev = np.sort(np.concatenate([np.linalg.eigvalsh(ah[:k, :k]), np.linalg.eigvalsh(ah[k:, k:])]))
+    assert np.abs(ev - np.sort(d)).max() <= 1e-9 * np.abs(d).max()
