@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void k_irs_init(const IrsInit<T>* __restrict__
     else b = (i == j) ? 1.0 : 0.0;
     const T a0 = (T)(d.a1 * a + d.a2 * b);
     const T b0 = (T)(d.b1 * a + d.b2 * b);
-    const size_t ld = 2 * (size_t)n;
+    const size_t ld = (size_t)d.ld;
     T* W = d.W;
     W[(size_t)j * ld + i] = b0;
     W[(size_t)j * ld + n + i] = -a0;
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(256) void k_irs_post(const IrsDesc<T>* __restrict__
     if (!d.active) return;
     const int n = d.n, j = blockIdx.x;
     if (j >= n) return;
-    const size_t ld = 2 * (size_t)n;
+    const size_t ld = (size_t)d.ld;
     T* W = d.W;
     double diff = 0, ref = 0, cur = 0;
     for (int i = threadIdx.x; i < n; i += 256) {

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "engine.hpp"
+#include "engine_util.hpp"
 #include "sdc.h"
 
 using sdc::Handle;
@@ -99,6 +100,7 @@ sdc_status_t sdc_destroy(sdc_handle_t handle) {
     if (h.host) (void)hipHostFree(h.host);
     if (h.ws2) (void)hipFree(h.ws2);
     if (h.dnorm) (void)hipFree(h.dnorm);
+    sdc::release_streams(h);
     delete handle;
     return SDC_OK;
 }

@@ -42,6 +42,7 @@ static void region_coeffs(const sdc_region_t& r, double& a1, double& a2, double&
 // ---------------------------------------------------------------------------
 template <typename T> struct IrsSide {
     int n = 0;
+    int ld = 0;  // leading dimension of W: 2n rounded up to 16 elements (aligned columns)
     const double* A = nullptr; int lda = 0;
     const double* B = nullptr; int ldb = 0;
     int trans = 0;
@@ -58,20 +59,30 @@ template <typename T> struct IrsSide {
 // Buffers of one IRS side; s.n must be set before the call.
 template <typename T> static void irs_layout(Carver& c, IrsSide<T>& s) {
     const size_t n = (size_t)s.n;
-    s.W = c.take<T>(6 * n * n);
+    s.ld = (2 * s.n + 15) / 16 * 16;
+    s.W = c.take<T>(3 * n * (size_t)s.ld);
     s.Rprev = c.take<double>(n * n);
     s.diag = c.take<T>(n);
-    s.Tm = c.take<T>(qr_aux_elems<T>());
+    s.Tm = c.take<T>(2 * qr_aux_elems<T>(2 * s.n));
     s.counters = c.take<unsigned>(kMaxInternal);
 }
 
+// aux holds 2 * qr_aux_elems<T>(m) elements (one set per panel parity).
 template <typename T> static QrDesc<T> qr_desc(T* W, int ld, int m, int nf, int ncols, T* aux, T* diag,
                                                unsigned* counters) {
     using C = QrCfg<T>;
+    const auto g = tree_geom<T>(m);
+    size_t internal = 0;
+    for (int l = 1; l < g.levels; ++l) internal += (size_t)g.L(l);
+    const size_t tm = ((size_t)g.L(0) + internal) * C::NB * C::NB;
+    const size_t per = qr_aux_elems<T>(m);
     QrDesc<T> d;
     d.W = W; d.ld = ld; d.m = m; d.nf = nf; d.ncols = ncols;
-    d.Tm = aux;
-    d.Vint = aux + (size_t)(kMaxLeaves + kMaxInternal) * C::NB * C::NB;
+    for (int p = 0; p < 2; ++p) {
+        d.Tm[p] = aux + p * per;
+        d.Vint[p] = aux + p * per + tm;
+    }
+    d.tm_leaves = g.L(0);
     d.diag = diag; d.counters = counters; d.active = 1;
     return d;
 }
@@ -83,7 +94,7 @@ template <typename T> static int irs_start(Handle& h, std::vector<IrsSide<T>*>& 
     for (IrsSide<T>* sp : sides) {
         IrsSide<T>& s = *sp;
         if (s.started) continue;
-        ini.push_back(IrsInit<T>{s.W, s.n, s.A, s.lda, s.B, s.ldb, s.a1, s.a2, s.b1, s.b2, s.trans});
+        ini.push_back(IrsInit<T>{s.W, s.n, s.ld, s.A, s.lda, s.B, s.ldb, s.a1, s.a2, s.b1, s.b2, s.trans});
         fill<unsigned>(s.counters, kMaxInternal, 0u, h.stream);
         s.p = 0; s.converged = 0; s.nonfinite = 0; s.rconv = NAN; s.done = 0; s.started = 1;
     }
@@ -111,14 +122,15 @@ template <typename T> static int irs_tick(Handle& h, std::vector<IrsSide<T>*>& s
     for (int i = 0; i < cnt; ++i) {
         IrsSide<T>& s = *act[i];
         s.norms = h.dnorm + 4 * i;
-        qd[i] = qr_desc<T>(s.W, 2 * s.n, 2 * s.n, s.n, 3 * s.n, s.Tm, s.diag, s.counters);
-        pd[i] = IrsDesc<T>{s.W, s.n, s.Rprev, s.diag, s.norms, 1};
+        qd[i] = qr_desc<T>(s.W, s.ld, 2 * s.n, s.n, 3 * s.n, s.Tm, s.diag, s.counters);
+        pd[i] = IrsDesc<T>{s.W, s.n, s.ld, s.Rprev, s.diag, s.norms, 1};
     }
     const size_t mark = h.desc_off;
     UPLOAD(dq, qd);
     UPLOAD(dp, pd);
     fill<double>(h.dnorm, 4 * (size_t)cnt, 0.0, h.stream);
-    qr_aug_batch<T>(dq, qd.data(), cnt, h.stream);
+    CHK(ensure_streams(h));
+    qr_aug_batch<T>(dq, qd.data(), cnt, h.stream, &h.qs);
     irs_post_batch<T>(dp, pd.data(), cnt, 0, h.stream);
     HIPCHK(hipGetLastError());
     double* hn = reinterpret_cast<double*>(h.host);
@@ -240,7 +252,7 @@ static void job_layout(Carver& c, JobWs& w) {
     w.Vt = c.take<double>(n * n);
     w.T1 = c.take<double>(n * n);
     w.T2 = c.take<double>(n * n);
-    w.qaux = c.take<double>(qr_aux_elems<double>());
+    w.qaux = c.take<double>(2 * qr_aux_elems<double>((int)n));
     for (int k = 0; k < 4; ++k) w.dg[k] = c.take<double>(n);
     w.qcnt = c.take<unsigned>(kMaxInternal);
     w.SA = c.take<double>(n * n);
@@ -312,7 +324,8 @@ static int run_qr(Handle& h, std::vector<JobWs*>& js, int dgi) {
     }
     if (q.empty()) return SDC_OK;
     UPLOAD(d, q);
-    qr_aug_batch<double>(d, q.data(), (int)q.size(), h.stream);
+    CHK(ensure_streams(h));
+    qr_aug_batch<double>(d, q.data(), (int)q.size(), h.stream, &h.qs);
     return SDC_OK;
 }
 
@@ -682,10 +695,11 @@ static int apply_correction(Handle& h, std::vector<JobWs*>& js) {
 
 // FP32 iterates leave ||E21|| at the rank-revealed split of order
 // eps32 |A| / gap.  At large n that can exceed e(k) of the trivial splits next
-// to k = 1 or k = n - 1 (one border row or column has a small 1-norm), so the
-// refinement starts from the rank the GRURV diagonals reveal: for jobs whose
-// split-search minimum k* differs from that rank, e(k_rho) is read back and
-// taken as the candidate.
+// to k = 1 or k = n - 1 (one border row or column has a small 1-norm), so when
+// the split-search minimum k* is such a border split the refinement starts
+// from the rank the GRURV diagonals reveal instead: e(k_rho) is read back and
+// taken as the candidate.  An interior k* that disagrees with k_rho is left
+// alone (the attempt is retried with a new draw).
 static int pin_to_rank(Handle& h, std::vector<JobWs*>& js) {
     std::vector<JobWs*> alt;
     std::vector<int> ks;
@@ -694,7 +708,10 @@ static int pin_to_rank(Handle& h, std::vector<JobWs*>& js) {
         double gap = 1;
         int side = SIDE_SPLIT;
         const int krho = rank_from_rho(w->rho_r, gap, side);
-        if (side != SIDE_SPLIT || krho == w->job->info.k_lead || krho < 1 || krho >= w->job->n) continue;
+        const int n = w->job->n, kstar = w->job->info.k_lead;
+        const int border = std::max(2, n / 64);
+        if (side != SIDE_SPLIT || krho == kstar || krho < 1 || krho >= n) continue;
+        if (std::min(kstar, n - kstar) > border) continue;
         alt.push_back(w);
         ks.push_back(krho);
     }
@@ -906,8 +923,8 @@ static int finish_jobs(Handle& h, std::vector<JobWs*>& wsp) {
                 EwDesc a{}, b{};
                 a.op = b.op = EW_PERMUTE; a.n = b.n = n; a.rows = b.rows = n; a.alpha = b.alpha = 1.0;
                 a.active = b.active = 1;
-                a.in = S.W + (size_t)2 * n * n; a.ldi = 2 * n; a.out = w.Apd[s]; a.ldo = n;
-                b.in = S.W; b.ldi = 2 * n; b.out = w.Bpd[s]; b.ldo = n;
+                a.in = S.W + (size_t)n * S.ld; a.ldi = S.ld; a.out = w.Apd[s]; a.ldo = n;
+                b.in = S.W; b.ldi = S.ld; b.out = w.Bpd[s]; b.ldo = n;
                 conv.push_back(a);
                 conv.push_back(b);
                 w.Ap[s] = w.Apd[s]; w.Bp[s] = w.Bpd[s]; w.ldp[s] = n;
@@ -916,7 +933,7 @@ static int finish_jobs(Handle& h, std::vector<JobWs*>& wsp) {
             } else {
                 IrsSide<double>& S = w.sd[s];
                 bad |= S.nonfinite != 0;
-                w.Ap[s] = S.W + (size_t)2 * n * n; w.Bp[s] = S.W; w.ldp[s] = 2 * n;
+                w.Ap[s] = S.W + (size_t)n * S.ld; w.Bp[s] = S.W; w.ldp[s] = S.ld;
                 if (s == 0) { j.info.iters_right = S.p; j.info.rconv_last = S.rconv; }
                 else j.info.iters_left = S.p;
             }
@@ -1130,13 +1147,14 @@ int run_irs_only(Handle& h, int n, const double* A, int lda, const double* B, in
         d.alpha = 1.0; d.active = 1;
         cp.push_back(d);
     };
-    const size_t off_a = (size_t)2 * n * n;
+    const int ldw = fp32 ? sff.ld : sdd.ld;
+    const size_t off_a = (size_t)n * ldw;
     if (fp32) {
-        mk(static_cast<const float*>(W) + off_a, 2 * n, Ap);
-        mk(W, 2 * n, Bp);
+        mk(static_cast<const float*>(W) + off_a, ldw, Ap);
+        mk(W, ldw, Bp);
     } else {
-        mk(static_cast<const double*>(W) + off_a, 2 * n, Ap);
-        mk(W, 2 * n, Bp);
+        mk(static_cast<const double*>(W) + off_a, ldw, Ap);
+        mk(W, ldw, Bp);
     }
     UPLOAD(dcp, cp);
     if (fp32) ew_batch<float, double>(dcp, cp.data(), (int)cp.size(), h.stream);

@@ -9,6 +9,7 @@
 
 #include "sdc.h"
 #include "profiler.hpp"
+#include "sdc_internal.hpp"
 
 namespace sdc {
 
@@ -34,6 +35,8 @@ struct Handle {
     // per-tick convergence norms of the repeated squaring (4 per side)
     double* dnorm = nullptr;
     size_t dnorm_cap = 0;
+    // look-ahead stream and events of the QR (created on first use)
+    QrStreams qs{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     // opt-in kernel timing
     Profiler prof;
 };

@@ -80,6 +80,26 @@ inline int ensure_desc(Handle& h, size_t bytes) {
     return SDC_OK;
 }
 
+inline int ensure_streams(Handle& h) {
+    if (h.qs.crit) return SDC_OK;
+    if (hipStreamCreateWithFlags(&h.qs.crit, hipStreamNonBlocking) != hipSuccess) return SDC_ERR_DEVICE;
+    if (hipStreamCreateWithFlags(&h.qs.rest, hipStreamNonBlocking) != hipSuccess) return SDC_ERR_DEVICE;
+    hipEvent_t* ev[4] = {&h.qs.evP, &h.qs.evR, &h.qs.evE, &h.qs.evD};
+    for (hipEvent_t* e : ev)
+        if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return SDC_ERR_DEVICE;
+    return SDC_OK;
+}
+inline void release_streams(Handle& h) {
+    if (h.qs.crit) (void)hipStreamSynchronize(h.qs.crit);
+    if (h.qs.rest) (void)hipStreamSynchronize(h.qs.rest);
+    hipEvent_t ev[4] = {h.qs.evP, h.qs.evR, h.qs.evE, h.qs.evD};
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (h.qs.crit) (void)hipStreamDestroy(h.qs.crit);
+    if (h.qs.rest) (void)hipStreamDestroy(h.qs.rest);
+    h.qs = QrStreams{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+}
+
 inline int ensure_dnorm(Handle& h, size_t elems) {
     if (elems <= h.dnorm_cap) return SDC_OK;
     if (h.dnorm) {

@@ -23,39 +23,9 @@
 
 namespace sdc {
 
-// p[idx] for idx in 0..3 without dynamic register indexing.
-template <typename T, int N>
-__device__ __forceinline__ T get4(const T (&p)[N], int idx) {
-    return idx == 0 ? p[0] : idx == 1 ? p[1] : idx == 2 ? p[2] : p[3];
-}
-template <typename T, int N>
-__device__ __forceinline__ void set4(T (&p)[N], int idx, T v) {
-    if (idx == 0) p[0] = v;
-    else if (idx == 1) p[1] = v;
-    else if (idx == 2) p[2] = v;
-    else p[3] = v;
-}
-
-// Sum over the 16 lanes of a DPP row, result in every lane of the row
-// (rotations by 8, 4, 2, 1 within the row).
-template <int CTRL> __device__ __forceinline__ double dpp_mov(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-template <int CTRL> __device__ __forceinline__ float dpp_mov(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-template <typename T> __device__ __forceinline__ T row16_sum(T v) {
-    v += dpp_mov<0x128>(v);  // row_ror:8
-    v += dpp_mov<0x124>(v);  // row_ror:4
-    v += dpp_mov<0x122>(v);  // row_ror:2
-    v += dpp_mov<0x121>(v);  // row_ror:1
-    return v;
-}
-
 // Householder QR of one tree node held in registers by a PT-thread
-// workgroup (PT/32 = G row groups).  Thread (grp = tid/32, c = tid%32) owns
+// workgroup (PT/32 = G row groups; with PT = 64 the workgroup is a single
+// wavefront, so its barriers cost little).  Thread (grp = tid/32, c = tid%32) owns
 // column c, rows r = G*i + grp (i < NR, NR a compile-time tile height).  Rows
 // beyond the node and columns >= nbk are zero and stay zero, so every loop
 // runs over all NR registers without guards.
@@ -78,17 +48,22 @@ template <typename T, int NR>
 __device__ __forceinline__ void node_qr(T (&p)[NR], int nbk, T* s_col, T* s_row, T* s_red, T* s_Sm, T* s_T,
                                         T* s_tau, T* s_beta) {
     constexpr int NB = QrCfg<T>::NB, G = QrCfg<T>::PT / 32;
+    // row j < NB of the node is register j / G of group j % G
+    constexpr int NJ = NB / G;
+    static_assert(NB % G == 0 && NJ <= NR, "the first NB rows must sit in registers [0, NB / G)");
     const int tid = threadIdx.x, grp = tid >> 5, c = tid & 31;
-    // row j of the node is register (j / G) of group (j % G): j < NB <= 2 G
-    static_assert(NB <= 2 * G, "row j must sit in register 0 or 1");
     for (int j = 0; j < nbk; ++j) {
+        const int jr = j / G, jg = j % G;
         T* tcol = s_col + (j & 1) * G * NR;
         T* trow = s_row + (j & 1) * NB;
+        T rj = 0;  // row j of this thread's column (meaningful in group jg)
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) rj = i == jr ? p[i] : rj;
         if (c == j) {
 #pragma unroll
             for (int i = 0; i < NR; ++i) tcol[grp * NR + i] = (G * i + grp > j) ? p[i] : T(0);
         }
-        if (grp == j % G) trow[c] = j < G ? p[0] : p[1];
+        if (grp == jg) trow[c] = rj;
         __syncthreads();
         T x[NR];
 #pragma unroll
@@ -118,8 +93,12 @@ __device__ __forceinline__ void node_qr(T (&p)[NR], int nbk, T* s_col, T* s_row,
         } else {
             const T nrm = sqrt(alpha * alpha + xn2);
             beta = alpha >= T(0) ? -nrm : nrm;
-            tau = (beta - alpha) / beta;
-            scale = T(1) / (alpha - beta);
+            // one division: r = 1 / (beta (alpha - beta)) gives
+            // scale = 1 / (alpha - beta) = beta r, tau = (beta - alpha) / beta = -(alpha - beta)^2 r
+            const T d = alpha - beta;
+            const T r = T(1) / (beta * d);
+            scale = beta * r;
+            tau = -(d * d) * r;
         }
         const T w = trow[c] + scale * zc;  // v_j^T P[:, c]  (= v_c^T v_j for c < j)
         // c > j: p -= tau w v;  c == j: p <- v below the diagonal;  c < j: unchanged
@@ -131,9 +110,10 @@ __device__ __forceinline__ void node_qr(T (&p)[NR], int nbk, T* s_col, T* s_row,
             const T upd = p[i] - coef * x[i];
             p[i] = (isj && G * i + grp > j) ? x[i] * scale : upd;
         }
-        if (grp == j % G) {
-            if (j < G) p[0] = isj ? beta : p[0] - tw;
-            else p[1] = isj ? beta : p[1] - tw;
+        if (grp == jg) {  // row j: beta on the diagonal, p - tau w v_j (v_j = 1) to the right
+            const T nv = isj ? beta : rj - tw;
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) p[i] = i == jr ? nv : p[i];
         }
         if (c < j && grp == 0) s_Sm[c * (NB + 1) + j] = w;
         if (tid == 0) {
@@ -143,32 +123,28 @@ __device__ __forceinline__ void node_qr(T (&p)[NR], int nbk, T* s_col, T* s_row,
     }
     __syncthreads();
     // Compact-WY factor, forward columnwise recurrence
-    //   T[i][j] = -tau_j sum_{l=i}^{j-1} T[i][l] (v_l^T v_j),  T[i][i] = tau_i,
-    // row i on one 16-lane DPP row: lane sub keeps T[i][sub] and T[i][sub + 16]
-    // and the sum over l is split by l mod 16 and reduced within the row.
-    static_assert(QrCfg<T>::PT >= 16 * NB, "T recurrence needs 16 lanes per row");
-    {
-        const int ti = tid >> 4, sub = tid & 15;
-        T t0 = 0, t1 = 0;
-        if (ti < nbk) {
-            if (sub == ti) t0 = s_tau[ti];
-            if (sub + 16 == ti) t1 = s_tau[ti];
-        }
-        for (int j = 1; j < nbk; ++j) {
-            T part = 0;
-            if (sub >= ti && sub < j) part += t0 * s_Sm[sub * (NB + 1) + j];
-            if (sub + 16 >= ti && sub + 16 < j) part += t1 * s_Sm[(sub + 16) * (NB + 1) + j];
-            part = row16_sum(part);
-            if (ti < j) {
-                const T tij = -s_tau[j] * part;
-                if (sub == j) t0 = tij;
-                if (sub + 16 == j) t1 = tij;
+    //   T[i][j] = -tau_j sum_{l=i}^{j-1} T[i][l] (v_l^T v_j),  T[i][i] = tau_i:
+    // thread r < NB keeps row r of T in registers; rows are independent.
+    if (tid < NB) {
+        const int r = tid;
+        T t[NB];
+#pragma unroll
+        for (int l = 0; l < NB; ++l) t[l] = (l == r && l < nbk) ? s_tau[l] : T(0);
+#pragma unroll
+        for (int j = 1; j < NB; ++j) {
+            if (j < nbk) {
+                T a0 = 0, a1 = 0;
+#pragma unroll
+                for (int l = 0; l < j; ++l) {
+                    const T term = l >= r ? t[l] * s_Sm[l * (NB + 1) + j] : T(0);
+                    if (l & 1) a1 += term;
+                    else a0 += term;
+                }
+                if (r < j) t[j] = -s_tau[j] * (a0 + a1);
             }
         }
-        if (ti < NB) {
-            s_T[ti * (NB + 1) + sub] = t0;
-            s_T[ti * (NB + 1) + sub + 16] = t1;
-        }
+#pragma unroll
+        for (int l = 0; l < NB; ++l) s_T[r * (NB + 1) + l] = t[l];
     }
     __syncthreads();
 }
@@ -225,9 +201,11 @@ __global__ __launch_bounds__(QrCfg<T>::PT) void k_panel(const QrDesc<T>* __restr
     if (!d.active || c0 >= d.nf) return;
     const int nbk = min(NB, d.nf - c0);
     const int mp = d.m - c0;
-    const TreeGeom g = tree_geom<T>(mp);
+    const auto g = tree_geom<T>(mp);
     int node = blockIdx.x;
-    if (node >= g.L[0]) return;
+    if (node >= g.L(0)) return;
+    const int par = (c0 / NB) & 1;
+    T* const Tm = (par ? d.Tm[1] : d.Tm[0]);
     const int tid = threadIdx.x;
     const size_t ld = (size_t)d.ld;
     T* W = d.W;
@@ -236,8 +214,8 @@ __global__ __launch_bounds__(QrCfg<T>::PT) void k_panel(const QrDesc<T>* __restr
     // Each thread moves whole rows (all NB columns), so its global accesses
     // are independent and in flight together; across threads every column
     // access is a contiguous run of rows.
-    const int row0 = c0 + leaf_lo(node, mp, g.L[0]);
-    int mt = c0 + leaf_lo(node + 1, mp, g.L[0]) - row0;
+    const int row0 = c0 + leaf_lo(node, mp, g.L(0));
+    int mt = c0 + leaf_lo(node + 1, mp, g.L(0)) - row0;
     for (int r = tid; r < mt; r += PT) {
         T v[NB];
 #pragma unroll
@@ -246,7 +224,7 @@ __global__ __launch_bounds__(QrCfg<T>::PT) void k_panel(const QrDesc<T>* __restr
         for (int col = 0; col < NB; ++col) s_tile[col * LDT + r] = v[col];
     }
     __syncthreads();
-    factor_node<T>(s_tile, mt, nbk, s_col, s_row, s_tau, s_beta, d.Tm + (size_t)node_index(g, 0, node) * NB * NB);
+    factor_node<T>(s_tile, mt, nbk, s_col, s_row, s_tau, s_beta, Tm + (size_t)node_index(g, 0, node, d.tm_leaves) * NB * NB);
     for (int r = tid; r < mt; r += PT) {
 #pragma unroll
         for (int col = 0; col < NB; ++col)
@@ -259,7 +237,7 @@ __global__ __launch_bounds__(QrCfg<T>::PT) void k_panel(const QrDesc<T>* __restr
         __syncthreads();
         const int parent = node / C::F;
         const int iidx = internal_index(g, level, parent);
-        const int nch = min(C::F, g.L[level - 1] - parent * C::F);
+        const int nch = min(C::F, g.L(level - 1) - parent * C::F);
         if (tid == 0) {
             const unsigned old = atomicAdd(&d.counters[iidx], 1u);
             s_last = (old == (unsigned)(nch - 1));
@@ -274,7 +252,7 @@ __global__ __launch_bounds__(QrCfg<T>::PT) void k_panel(const QrDesc<T>* __restr
         // stack is row s % NB of child s / NB)
         for (int s = tid; s < mt; s += PT) {
             const int t = s / NB, r = s % NB;
-            const int rb = c0 + leaf_lo((node * C::F + t) * g.pow[level - 1], mp, g.L[0]);
+            const int rb = c0 + leaf_lo((node * C::F + t) * g.pw(level - 1), mp, g.L(0));
             T v[NB];
 #pragma unroll
             for (int col = 0; col < NB; ++col)
@@ -284,10 +262,10 @@ __global__ __launch_bounds__(QrCfg<T>::PT) void k_panel(const QrDesc<T>* __restr
         }
         __syncthreads();
         factor_node<T>(s_tile, mt, nbk, s_col, s_row, s_tau, s_beta,
-                       d.Tm + (size_t)node_index(g, level, node) * NB * NB);
+                       Tm + (size_t)node_index(g, level, node, d.tm_leaves) * NB * NB);
         // explicit reflectors of this node, and its R into the top rows
-        T* Vi = d.Vint + (size_t)iidx * C::MT_MAX * NB;
-        const int rbase = c0 + leaf_lo(node * g.pow[level], mp, g.L[0]);
+        T* Vi = (par ? d.Vint[1] : d.Vint[0]) + (size_t)iidx * C::MT_MAX * NB;
+        const int rbase = c0 + leaf_lo(node * g.pw(level), mp, g.L(0));
         for (int s = tid; s < C::MT_MAX; s += PT) {
 #pragma unroll
             for (int col = 0; col < NB; ++col) {
@@ -306,43 +284,59 @@ __global__ __launch_bounds__(QrCfg<T>::PT) void k_panel(const QrDesc<T>* __restr
 
 // Apply the transpose of one tree level's block reflectors to a 64-column
 // tile of the trailing matrix: C <- C - V (T^T (V^T C)) for the node's rows.
-// Each wave owns 16 columns; the tile stays in MFMA accumulator layout in
-// registers (row block rb, lane (gq, ln) holds rows 16 rb + row(gq, v),
-// column ln).  Both contractions over rows use the k-slices
-// {16 rb + row(gq, v) : gq} so that the accumulator registers are directly
-// the B operand.
+//
+// Each wave owns 16 columns and keeps its slice of C in registers in the
+// accumulator layout of C^T (MFMA 16x16x4): in row block rb, lane (gq, ln)
+// holds column row(gq, v) and row 16 rb + ln, so every global load and store
+// instruction moves whole runs of 16 consecutive rows of a few columns.
+//   W = V^T C   : B operand = C, re-read from a per-wave 16x16 LDS tile
+//                 (rows on the lane group, columns on the lane);
+//   Y = T^T W   : W's accumulator registers are the B operand (k-slices
+//                 {row(gq, v) : gq});
+//   C^T -= Y^T V^T : Y's accumulator registers are the A operand with the
+//                 same k-slices, V^T read from LDS, C^T accumulated in place.
 template <typename T, int RB>
-__global__ __launch_bounds__(256) void k_update(const QrDesc<T>* __restrict__ descs, int c0, int level) {
+__global__ __launch_bounds__(256, 2) void k_update(const QrDesc<T>* __restrict__ descs, int c0, int level,
+                                                   int mode) {
     using C = QrCfg<T>;
     using M = Mfma<T>;
     typedef typename M::v4 v4;
-    constexpr int NB = C::NB, VS = 36;
+    constexpr int NB = C::NB, VS = NB + 1, XS = 17;  // odd strides: conflict-free LDS access
     __shared__ T s_V[RB * 16 * VS];
-    __shared__ T s_T[NB * (NB + 1)];
+    __shared__ T s_X[4 * 16 * XS];
     __shared__ int s_rb[32];
 
     const QrDesc<T> d = descs[blockIdx.z];
     if (!d.active || c0 >= d.nf) return;
     const int nbk = min(NB, d.nf - c0);
-    const int col0 = c0 + nbk + blockIdx.y * 64;
-    if (col0 >= d.ncols) return;
+    // column range: all trailing columns (mode 0), the next panel's columns
+    // (mode 1, the look-ahead part) or the columns after them (mode 2)
+    int cb = c0 + nbk, ce = d.ncols;
+    if (mode != 0) {
+        const int nxt = max(0, min(NB, d.nf - cb));
+        if (mode == 1) ce = cb + nxt;
+        else cb += nxt;
+    }
+    const int col0 = cb + blockIdx.y * 64;
+    if (col0 >= ce) return;
+    const int par = (c0 / NB) & 1;
     const int mp = d.m - c0;
-    const TreeGeom g = tree_geom<T>(mp);
+    const auto g = tree_geom<T>(mp);
     if (level >= g.levels) return;
     const int node = blockIdx.x;
-    if (node >= g.L[level]) return;
+    if (node >= g.L(level)) return;
     const int tid = threadIdx.x;
     const size_t ld = (size_t)d.ld;
     T* W = d.W;
 
     int mt, lo = 0;
     if (level == 0) {
-        lo = c0 + leaf_lo(node, mp, g.L[0]);
-        mt = c0 + leaf_lo(node + 1, mp, g.L[0]) - lo;
+        lo = c0 + leaf_lo(node, mp, g.L(0));
+        mt = c0 + leaf_lo(node + 1, mp, g.L(0)) - lo;
     } else {
-        const int nch = min(C::F, g.L[level - 1] - node * C::F);
+        const int nch = min(C::F, g.L(level - 1) - node * C::F);
         mt = nch * NB;
-        if (tid < nch) s_rb[tid] = c0 + leaf_lo((node * C::F + tid) * g.pow[level - 1], mp, g.L[0]);
+        if (tid < nch) s_rb[tid] = c0 + leaf_lo((node * C::F + tid) * g.pw(level - 1), mp, g.L(0));
     }
     const int rows_pad = ((mt + 15) >> 4) << 4;
     // reflectors: each thread moves whole rows (independent loads in flight)
@@ -357,7 +351,7 @@ __global__ __launch_bounds__(256) void k_update(const QrDesc<T>* __restrict__ de
             for (int col = 0; col < NB; ++col) s_V[s * VS + col] = v[col];
         }
     } else {
-        const T* Vi = d.Vint + (size_t)internal_index(g, level, node) * C::MT_MAX * NB;
+        const T* Vi = (par ? d.Vint[1] : d.Vint[0]) + (size_t)internal_index(g, level, node) * C::MT_MAX * NB;
         for (int s = tid; s < rows_pad; s += 256) {
             T v[NB];
 #pragma unroll
@@ -366,180 +360,236 @@ __global__ __launch_bounds__(256) void k_update(const QrDesc<T>* __restrict__ de
             for (int col = 0; col < NB; ++col) s_V[s * VS + col] = v[col];
         }
     }
-    {
-        const T* Tg = d.Tm + (size_t)node_index(g, level, node) * NB * NB;
-        for (int e = tid; e < NB * NB; e += 256) s_T[(e % NB) * (NB + 1) + e / NB] = Tg[e];
-    }
     __syncthreads();
 
     const int wave = tid >> 6, lane = tid & 63, gq = lane >> 4, ln = lane & 15;
-    const int col = col0 + wave * 16 + ln;
-    const bool colok = col < d.ncols;
+    const int cbase = col0 + wave * 16;
     const int rbe = rows_pad >> 4;
-    T* Wc = W + (size_t)col * ld;
+    // T factor of this node, as the A operand of Y = T^T W:
+    // lane (gq, ln) needs T[k][ln] for k = kb * 16 + row(gq, j)
+    const T* Tg = (par ? d.Tm[1] : d.Tm[0]) + (size_t)node_index(g, level, node, d.tm_leaves) * NB * NB;
+    T ta[2][2][4];
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = kb * 16 + M::row(gq, j);
+            ta[0][kb][j] = Tg[(size_t)ln * NB + k];
+            ta[1][kb][j] = Tg[(size_t)(16 + ln) * NB + k];
+        }
 
+    // C^T slice: row block rb, lane (gq, ln), register v <-> node row 16 rb + ln,
+    // column cbase + row(gq, v); wr = the row in W (-1: padding)
     v4 cr[RB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
         cr[rb] = v4{0, 0, 0, 0};
-        if (rb < rbe && colok) {
+        if (rb < rbe) {
+            const int sr = rb * 16 + ln;
+            const int wr = sr >= mt ? -1
+                           : level == 0 ? lo + sr
+                           : ((sr & (NB - 1)) < nbk ? s_rb[sr / NB] + (sr & (NB - 1)) : -1);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int s = rb * 16 + M::row(gq, v);
-                if (s < mt) {
-                    int wr;
-                    if (level == 0) wr = lo + s;
-                    else wr = ((s & (NB - 1)) < nbk) ? s_rb[s / NB] + (s & (NB - 1)) : -1;
-                    if (wr >= 0) cr[rb][v] = Wc[wr];
-                }
+                const int c = cbase + M::row(gq, v);
+                if (wr >= 0 && c < ce) cr[rb][v] = W[(size_t)c * ld + wr];
             }
         }
     }
-    // Wt = V^T C  (NB x 16): two 16x16 blocks, each summed over two
-    // interleaved accumulator chains (even / odd row blocks) for MFMA ILP
+    // W = V^T C (NB x 16): per row block, C goes through the wave's LDS tile
+    // into the B-operand layout; two accumulator chains per half (even / odd
+    // row blocks)
+    T* X = s_X + wave * 16 * XS;
     v4 w0 = v4{0, 0, 0, 0}, w1 = v4{0, 0, 0, 0}, w2 = v4{0, 0, 0, 0}, w3 = v4{0, 0, 0, 0};
 #pragma unroll
-    for (int rb = 0; rb < RB; rb += 2) {
+    for (int rb = 0; rb < RB; ++rb) {
+        if (rb < rbe) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            if (rb < rbe) {
-                const T* vr = s_V + (rb * 16 + M::row(gq, v)) * VS;
-                w0 = M::mma(vr[ln], cr[rb][v], w0);
-                w1 = M::mma(vr[16 + ln], cr[rb][v], w1);
-            }
-            if (rb + 1 < rbe) {
-                const T* vr = s_V + ((rb + 1) * 16 + M::row(gq, v)) * VS;
-                w2 = M::mma(vr[ln], cr[rb + 1][v], w2);
-                w3 = M::mma(vr[16 + ln], cr[rb + 1][v], w3);
+            for (int v = 0; v < 4; ++v) X[ln * XS + M::row(gq, v)] = cr[rb][v];
+            __builtin_amdgcn_wave_barrier();
+            T b[4];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) b[kk] = X[(4 * kk + gq) * XS + ln];
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const T* vr = s_V + (rb * 16 + 4 * kk + gq) * VS;
+                if (rb & 1) {
+                    w2 = M::mma(vr[ln], b[kk], w2);
+                    w3 = M::mma(vr[16 + ln], b[kk], w3);
+                } else {
+                    w0 = M::mma(vr[ln], b[kk], w0);
+                    w1 = M::mma(vr[16 + ln], b[kk], w1);
+                }
             }
         }
     }
     w0 += w2;
     w1 += w3;
-    // Y = T^T Wt
+    // Y = T^T W
     v4 y0 = v4{0, 0, 0, 0}, y1 = v4{0, 0, 0, 0};
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const T b = kb ? w1[j] : w0[j];
-            const int k = kb * 16 + M::row(gq, j);
-            y0 = M::mma(s_T[k * (NB + 1) + ln], b, y0);
-            y1 = M::mma(s_T[k * (NB + 1) + 16 + ln], b, y1);
+            const T bw = kb ? w1[j] : w0[j];
+            y0 = M::mma(ta[0][kb][j], bw, y0);
+            y1 = M::mma(ta[1][kb][j], bw, y1);
         }
     }
-    // C -= V Y: k-steps outer, row blocks inner (RB independent accumulators)
+    // C^T -= Y^T V^T: k-steps outer, row blocks inner (RB independent accumulators)
 #pragma unroll
     for (int pb = 0; pb < 2; ++pb) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const T b = pb ? y1[j] : y0[j];
+            const T a = -(pb ? y1[j] : y0[j]);
             const int kcol = pb * 16 + M::row(gq, j);
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
-                if (rb < rbe) cr[rb] = M::mma(-s_V[(rb * 16 + ln) * VS + kcol], b, cr[rb]);
+                if (rb < rbe) cr[rb] = M::mma(a, s_V[(rb * 16 + ln) * VS + kcol], cr[rb]);
         }
     }
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
-        if (rb < rbe && colok) {
+        if (rb < rbe) {
+            const int sr = rb * 16 + ln;
+            const int wr = sr >= mt ? -1
+                           : level == 0 ? lo + sr
+                           : ((sr & (NB - 1)) < nbk ? s_rb[sr / NB] + (sr & (NB - 1)) : -1);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int s = rb * 16 + M::row(gq, v);
-                if (s < mt) {
-                    int wr;
-                    if (level == 0) wr = lo + s;
-                    else wr = ((s & (NB - 1)) < nbk) ? s_rb[s / NB] + (s & (NB - 1)) : -1;
-                    if (wr >= 0) Wc[wr] = cr[rb][v];
-                }
+                const int c = cbase + M::row(gq, v);
+                if (wr >= 0 && c < ce) W[(size_t)c * ld + wr] = cr[rb][v];
             }
         }
     }
 }
 
-// Register-tile height (in 16-row blocks) is chosen per launch; only
-// instantiations whose LDS tile fits (MT_MAX rows) exist.
 template <typename T>
-static void launch_update(int rows, dim3 grid, hipStream_t s, const QrDesc<T>* d, int c0, int lev);
+static void launch_update(int rows, dim3 grid, hipStream_t s, const QrDesc<T>* d, int c0, int lev, int mode);
 template <>
-void launch_update<double>(int rows, dim3 grid, hipStream_t s, const QrDesc<double>* d, int c0, int lev) {
-    if (rows <= 256)
-        hipLaunchKernelGGL((k_update<double, 16>), grid, dim3(256), 0, s, d, c0, lev);
-    else
-        hipLaunchKernelGGL((k_update<double, 32>), grid, dim3(256), 0, s, d, c0, lev);
+void launch_update<double>(int rows, dim3 grid, hipStream_t s, const QrDesc<double>* d, int c0, int lev,
+                           int mode) {
+    constexpr int RB = QrCfg<double>::MT_MAX / 16;
+    (void)rows;
+    hipLaunchKernelGGL((k_update<double, RB>), grid, dim3(256), 0, s, d, c0, lev, mode);
 }
 template <>
-void launch_update<float>(int rows, dim3 grid, hipStream_t s, const QrDesc<float>* d, int c0, int lev) {
-    if (rows <= 256)
-        hipLaunchKernelGGL((k_update<float, 16>), grid, dim3(256), 0, s, d, c0, lev);
-    else if (rows <= 512)
-        hipLaunchKernelGGL((k_update<float, 32>), grid, dim3(256), 0, s, d, c0, lev);
-    else
-        hipLaunchKernelGGL((k_update<float, 64>), grid, dim3(256), 0, s, d, c0, lev);
+void launch_update<float>(int rows, dim3 grid, hipStream_t s, const QrDesc<float>* d, int c0, int lev,
+                          int mode) {
+    constexpr int RB = QrCfg<float>::MT_MAX / 16;
+    (void)rows;
+    hipLaunchKernelGGL((k_update<float, RB>), grid, dim3(256), 0, s, d, c0, lev, mode);
 }
 
+// Batched augmented QR, panel by panel.  Without `la` every step runs on s:
+// panel factorization, then the tree levels of the trailing update.  With
+// `la` (look-ahead, depth 1) panel k+1 is factored while the update of the
+// columns after it runs concurrently:
+//   crit: P(k), [wait rest(k-1)], LA(k) = update of panel k+1's columns, P(k+1) ...
+//   rest: [wait P(k)], REST(k) = update of every column after panel k+1
+// LA(k) must follow REST(k-1) (both touch panel k+1's columns); P(k+1)
+// writes the other parity's T / reflector buffers while REST(k) reads
+// panel k's.  crit starts after the work already on s, and s waits for both
+// streams before returning.
 template <typename T>
-void qr_aug_batch(const QrDesc<T>* d_descs, const QrDesc<T>* h, int count, hipStream_t s) {
+void qr_aug_batch(const QrDesc<T>* d_descs, const QrDesc<T>* h, int count, hipStream_t s, const QrStreams* la) {
     using C = QrCfg<T>;
     int max_nf = 0;
     for (int i = 0; i < count; ++i)
         if (h[i].active) max_nf = max_nf > h[i].nf ? max_nf : h[i].nf;
+    bool rest_pending = false;
+    hipStream_t sc = s;  // critical-path stream
+    if (la) {
+        (void)hipEventRecord(la->evE, s);
+        (void)hipStreamWaitEvent(la->crit, la->evE, 0);
+        sc = la->crit;
+    }
     for (int c0 = 0; c0 < max_nf; c0 += C::NB) {
-        int maxL[kMaxLevels] = {0, 0, 0, 0};
+        int maxL[kMaxLevels] = {};
         int maxlev = 0, maxleaf = 0, maxtrail = 0;
+        bool next = false;
         for (int i = 0; i < count; ++i) {
             if (!h[i].active || c0 >= h[i].nf) continue;
             const int mp = h[i].m - c0;
-            const TreeGeom g = tree_geom<T>(mp);
-            for (int l = 0; l < g.levels; ++l) maxL[l] = maxL[l] > g.L[l] ? maxL[l] : g.L[l];
+            const auto g = tree_geom<T>(mp);
+            for (int l = 0; l < g.levels; ++l) maxL[l] = maxL[l] > g.L(l) ? maxL[l] : g.L(l);
             maxlev = maxlev > g.levels ? maxlev : g.levels;
-            const int leaf = g.L[0] == 1 ? mp : (mp + g.L[0] - 1) / g.L[0];
+            const int blocks16 = (mp + 15) / 16;
+            const int leaf = g.L(0) == 1 ? mp : min(mp, (blocks16 + g.L(0) - 1) / g.L(0) * 16);
             maxleaf = maxleaf > leaf ? maxleaf : leaf;
             const int nbk = h[i].nf - c0 < C::NB ? h[i].nf - c0 : C::NB;
             const int trail = h[i].ncols - c0 - nbk;
             maxtrail = maxtrail > trail ? maxtrail : trail;
+            next |= c0 + nbk < h[i].nf;
         }
         if (maxL[0] == 0) continue;
         // algorithmic work of this panel, per tree level: the update of level
         // l touches R_l rows (all panel rows at the leaves, nbk per child
         // above): 4 R nbk ntr + 2 nbk^2 ntr L_l flops, and reads + writes the
         // R x ntr trailing slice and reads the R x nbk reflectors once
-        double pf = 0, pb = 0, uf[kMaxLevels] = {0, 0, 0, 0}, ub[kMaxLevels] = {0, 0, 0, 0};
+        double pf = 0, pb = 0, uf[kMaxLevels] = {}, ub[kMaxLevels] = {};
         Profiler* prof = g_prof;
         if (prof) {
             for (int i = 0; i < count; ++i) {
                 if (!h[i].active || c0 >= h[i].nf) continue;
                 const int mp = h[i].m - c0;
-                const TreeGeom g = tree_geom<T>(mp);
+                const auto g = tree_geom<T>(mp);
                 const double nbk = h[i].nf - c0 < C::NB ? h[i].nf - c0 : C::NB;
                 const double ntr = h[i].ncols - c0 - nbk;
                 pf += 2.0 * mp * nbk * nbk;               // Householder QR of the panel
                 pb += 2.0 * mp * nbk * sizeof(T);
                 for (int l = 0; l < g.levels; ++l) {
-                    const double rows = l == 0 ? (double)mp : (double)g.L[l - 1] * nbk;
-                    uf[l] += 4.0 * rows * nbk * ntr + 2.0 * nbk * nbk * ntr * g.L[l];
+                    const double rows = l == 0 ? (double)mp : (double)g.L(l - 1) * nbk;
+                    uf[l] += 4.0 * rows * nbk * ntr + 2.0 * nbk * nbk * ntr * g.L(l);
                     ub[l] += (2.0 * rows * ntr + rows * nbk) * sizeof(T);
                 }
             }
         }
-        int pid = prof ? prof->begin(s) : -1;
-        hipLaunchKernelGGL(k_panel<T>, dim3(maxL[0], count), dim3(C::PT), 0, s, d_descs, c0);
-        if (prof) prof->end(pid, s, PROF_PANEL, pf, pb);
+        int pid = prof ? prof->begin(sc) : -1;
+        hipLaunchKernelGGL(k_panel<T>, dim3(maxL[0], count), dim3(C::PT), 0, sc, d_descs, c0);
+        if (prof) prof->end(pid, sc, PROF_PANEL, pf, pb);
         if (maxtrail <= 0) continue;
-        const int tiles = (maxtrail + 63) / 64;
-        for (int lev = 0; lev < maxlev; ++lev) {
-            const int rows = lev == 0 ? maxleaf : C::MT_MAX;
-            const dim3 grid(maxL[lev], tiles, count);
-            const int uid = prof ? prof->begin(s) : -1;
-            launch_update<T>(rows, grid, s, d_descs, c0, lev);
-            if (prof) prof->end(uid, s, PROF_UPDATE, uf[lev], ub[lev]);
+        auto run_levels = [&](hipStream_t st, int mode, int tiles, double share) {
+            for (int lev = 0; lev < maxlev; ++lev) {
+                const int rows = lev == 0 ? maxleaf : C::MT_MAX;
+                const dim3 grid(maxL[lev], tiles, count);
+                const int uid = prof ? prof->begin(st) : -1;
+                launch_update<T>(rows, grid, st, d_descs, c0, lev, mode);
+                if (prof) prof->end(uid, st, PROF_UPDATE, uf[lev] * share, ub[lev] * share);
+            }
+        };
+        if (!la || !next) {
+            if (rest_pending) {  // the previous rest update touches these columns
+                (void)hipStreamWaitEvent(sc, la->evR, 0);
+                rest_pending = false;
+            }
+            run_levels(sc, 0, (maxtrail + 63) / 64, 1.0);
+            continue;
         }
+        (void)hipEventRecord(la->evP, sc);
+        if (rest_pending) (void)hipStreamWaitEvent(sc, la->evR, 0);
+        const double f_la = maxtrail > 0 ? (double)C::NB / maxtrail : 0.0;
+        run_levels(sc, 1, 1, f_la);
+        (void)hipStreamWaitEvent(la->rest, la->evP, 0);
+        // the next panel may be narrower than NB, so the rest can start
+        // anywhere in [c0 + nbk, c0 + nbk + NB]: size the grid for all trailing
+        // columns (tiles past a problem's range exit at once)
+        run_levels(la->rest, 2, (maxtrail + 63) / 64, 1.0 - f_la);
+        (void)hipEventRecord(la->evR, la->rest);
+        rest_pending = true;
+    }
+    if (la) {
+        if (rest_pending) (void)hipStreamWaitEvent(sc, la->evR, 0);
+        (void)hipEventRecord(la->evD, sc);
+        (void)hipStreamWaitEvent(s, la->evD, 0);
     }
 }
+template void qr_aug_batch<double>(const QrDesc<double>*, const QrDesc<double>*, int, hipStream_t,
+                                   const QrStreams*);
+template void qr_aug_batch<float>(const QrDesc<float>*, const QrDesc<float>*, int, hipStream_t,
+                                  const QrStreams*);
 
 thread_local Profiler* g_prof = nullptr;
-
-template void qr_aug_batch<double>(const QrDesc<double>*, const QrDesc<double>*, int, hipStream_t);
-template void qr_aug_batch<float>(const QrDesc<float>*, const QrDesc<float>*, int, hipStream_t);
 
 }  // namespace sdc

@@ -21,77 +21,106 @@ namespace sdc {
 template <typename T> struct QrCfg;
 // Panel workgroups have PT threads = (PT/32) row groups x 32 columns; RPG is
 // the register rows per thread for a full MT_MAX-row node.
+// Every node (F * NB <= MT_MAX rows) is factored by one workgroup of PT
+// threads (one wavefront per SIMD of a CU: PT/32 row groups of 32 columns)
+// and fits the trailing-update kernel's registers (256 rows x 16 columns per
+// wave).  The shape was chosen by measurement among 64-512 threads and
+// 128-256 row nodes.
 template <> struct QrCfg<double> {
-    static constexpr int NB = 32, MT_MAX = 512, H = 256, F = 16, PT = 512, RPG = MT_MAX / (PT / 32);
+    static constexpr int NB = 32, MT_MAX = 256, H = 256, F = 8, PT = 256, RPG = MT_MAX / (PT / 32);
 };
 template <> struct QrCfg<float> {
-    static constexpr int NB = 32, MT_MAX = 1024, H = 512, F = 32, PT = 512, RPG = MT_MAX / (PT / 32);
+    static constexpr int NB = 32, MT_MAX = 256, H = 256, F = 8, PT = 256, RPG = MT_MAX / (PT / 32);
 };
 
-constexpr int kMaxLevels = 4;
-constexpr int kMaxLeaves = 128;   // per panel and problem
-constexpr int kMaxInternal = 16;  // internal tree nodes per panel and problem
+constexpr int kMaxLevels = 5;
+constexpr int kMaxInternal = 96;  // internal tree nodes per panel and problem (n <= 16384)
 
-struct TreeGeom {
-    int L[kMaxLevels];   // nodes per level, L[0] leaves
-    int levels;
-    int pow[kMaxLevels]; // F^level
+// Tree shape of a panel with mp rows: L0 leaves, levels levels, and
+// L(l) = ceil(L0 / F^l) nodes at level l.  Computed arithmetically (no
+// arrays indexed at run time, so kernels keep it in registers).
+template <typename T> struct TreeGeomT {
+    int L0, levels;
+    __host__ __device__ int pw(int l) const {
+        int p = 1;
+        for (int i = 0; i < l; ++i) p *= QrCfg<T>::F;
+        return p;
+    }
+    __host__ __device__ int L(int l) const {
+        if (l >= levels) return 0;
+        const int p = pw(l);
+        return (L0 + p - 1) / p;
+    }
 };
 
 template <typename T>
-__host__ __device__ inline TreeGeom tree_geom(int mp) {
+__host__ __device__ inline TreeGeomT<T> tree_geom(int mp) {
     using C = QrCfg<T>;
-    TreeGeom g;
+    TreeGeomT<T> g;
+    static_assert(C::H % 16 == 0, "leaves are whole 16-row blocks");
+    g.L0 = mp <= C::MT_MAX ? 1 : ((mp + 15) / 16 + C::H / 16 - 1) / (C::H / 16);
     g.levels = 1;
-    g.pow[0] = 1;
-    for (int i = 0; i < kMaxLevels; ++i) g.L[i] = 0;
-    if (mp <= C::MT_MAX) {
-        g.L[0] = 1;
-    } else {
-        g.L[0] = (mp + C::H - 1) / C::H;
-        while (g.L[g.levels - 1] > 1 && g.levels < kMaxLevels) {
-            g.L[g.levels] = (g.L[g.levels - 1] + C::F - 1) / C::F;
-            g.pow[g.levels] = g.pow[g.levels - 1] * C::F;
-            ++g.levels;
-        }
-    }
-    for (int i = g.levels; i < kMaxLevels; ++i) g.pow[i] = g.pow[i - 1] * C::F;
+    for (int n = g.L0; n > 1 && g.levels < kMaxLevels; n = (n + C::F - 1) / C::F) ++g.levels;
     return g;
 }
 
-// First row (relative to the panel's top row) of leaf j among L0 balanced leaves.
+// First row (relative to the panel's top row) of leaf j among L0 balanced
+// leaves.  Leaves are whole runs of 16-row blocks (the last one is cut at
+// mp): the panel's top row is a multiple of NB, so (with a leading dimension
+// that is a multiple of 16 elements) every 16-row block of a leaf is whole
+// cache lines and no line is shared by two leaves' workgroups.  With
+// L0 = ceil(ceil(mp/16) / (H/16)) (tree_geom) every leaf has <= H rows.
 __host__ __device__ inline int leaf_lo(int j, int mp, int L0) {
-    return (int)(((long long)j * mp) / L0);
+    if (j >= L0) return mp;
+    const long long blocks = (mp + 15) / 16;
+    return (int)((j * blocks) / L0) * 16;
 }
 
 // Index of an internal node (level >= 1) in per-problem arrays.
-__host__ __device__ inline int internal_index(const TreeGeom& g, int level, int node) {
+template <typename T>
+__host__ __device__ inline int internal_index(const TreeGeomT<T>& g, int level, int node) {
     int off = 0;
-    for (int l = 1; l < level; ++l) off += g.L[l];
+    for (int l = 1; l < level; ++l) off += g.L(l);
     return off + node;
 }
-// Index of any node in the per-problem T-factor array.
-__host__ __device__ inline int node_index(const TreeGeom& g, int level, int node) {
-    return level == 0 ? node : kMaxLeaves + internal_index(g, level, node);
+// Index of any node in the per-problem T-factor array (leaves first).
+template <typename T>
+__host__ __device__ inline int node_index(const TreeGeomT<T>& g, int level, int node, int tm_leaves) {
+    return level == 0 ? node : tm_leaves + internal_index(g, level, node);
 }
 
 // Per-problem descriptor of an augmented QR: factor columns [0, nf) of the
 // m x ncols matrix W (column-major, leading dimension ld) and apply Q^T to all
-// ncols columns.  Side buffers live in aux.
+// ncols columns.  The T factors and internal reflectors of a panel live in
+// one of two buffers, by panel parity, so that a panel can be factored while
+// the previous panel's update is still reading its own.
 template <typename T> struct QrDesc {
     T* W;
     int ld, m, nf, ncols;
-    T* Tm;            // (kMaxLeaves + kMaxInternal) * NB * NB, T factors of one panel's nodes
-    T* Vint;          // kMaxInternal * MT_MAX * NB, internal-node reflectors (column-major, ld MT_MAX)
+    T* Tm[2];         // (tm_leaves + internal) * NB * NB: T factors of one panel's nodes
+    T* Vint[2];       // internal * MT_MAX * NB: internal-node reflectors (column-major, ld MT_MAX)
+    int tm_leaves;    // leaves of the tallest panel (panel 0)
     T* diag;          // nf: diagonal of R as produced (before sign normalization)
     unsigned* counters; // kMaxInternal tree arrival counters (must start at zero)
     int active;
 };
 
-template <typename T> size_t qr_aux_elems() {
+// Elements of one parity's side buffers for an m-row problem.
+template <typename T> size_t qr_aux_elems(int m) {
     using C = QrCfg<T>;
-    return (size_t)(kMaxLeaves + kMaxInternal) * C::NB * C::NB + (size_t)kMaxInternal * C::MT_MAX * C::NB;
+    const auto g = tree_geom<T>(m);
+    size_t internal = 0;
+    for (int l = 1; l < g.levels; ++l) internal += (size_t)g.L(l);
+    return ((size_t)g.L(0) + internal) * C::NB * C::NB + internal * C::MT_MAX * C::NB;
 }
+
+// Streams and events for the look-ahead schedule of the QR (panel k+1
+// factored while the rest of panel k's update runs).  crit carries the
+// panels and the look-ahead updates, rest the bulk updates.
+struct QrStreams {
+    hipStream_t crit, rest;
+    hipEvent_t evP, evR, evE, evD;
+};
 
 // Batched GEMM descriptor: C = alpha op(A) op(B) + beta C, op(X) = X or X^T.
 template <typename T> struct GemmDesc {
@@ -107,8 +136,8 @@ template <typename T> struct GemmDesc {
 
 // Per-problem state of a batched IRS.
 template <typename T> struct IrsDesc {
-    T* W;              // 2n x 3n, ld = 2n: [B_j A_j 0; -A_j 0 B_j]
-    int n;
+    T* W;              // 2n x 3n, leading dimension ld: [B_j A_j 0; -A_j 0 B_j]
+    int n, ld;
     double* Rprev;     // n x n, ld n: previous R (sign-normalized)
     const T* diag;     // R diagonal from the QR (length n)
     double* norms;     // [2]: max column sum of |R_j - R_{j-1}| and of |R_{j-1}|
@@ -120,7 +149,7 @@ template <typename T> struct IrsDesc {
 // means the identity.
 template <typename T> struct IrsInit {
     T* W;
-    int n;
+    int n, ld;
     const double* A; int lda;
     const double* B; int ldb;
     double a1, a2, b1, b2;
@@ -129,7 +158,8 @@ template <typename T> struct IrsInit {
 
 // Host-side launchers (defined in the .hip files).
 template <typename T>
-void qr_aug_batch(const QrDesc<T>* d_descs, const QrDesc<T>* h_descs, int count, hipStream_t s);
+void qr_aug_batch(const QrDesc<T>* d_descs, const QrDesc<T>* h_descs, int count, hipStream_t s,
+                  const QrStreams* la = nullptr);
 template <typename T>
 void gemm_batch(const GemmDesc<T>* d_descs, const GemmDesc<T>* h_descs, int count, hipStream_t s);
 template <typename T>

@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "engine.hpp"
+#include "engine_util.hpp"
 #include "sdc.h"
 
 using Clock = std::chrono::steady_clock;
@@ -319,6 +320,7 @@ sdc_status_t sdc_server_destroy(sdc_server_t s) {
     if (h.host) (void)hipHostFree(h.host);
     if (h.ws2) (void)hipFree(h.ws2);
     if (h.dnorm) (void)hipFree(h.dnorm);
+    sdc::release_streams(h);
     if (h.stream) (void)hipStreamDestroy(h.stream);
     delete s;
     return SDC_OK;

@@ -191,6 +191,26 @@ def test_batched_equals_single_calls(handle, sdc):
         assert torch.equal(r.Q, single.Q) and torch.equal(r.Ahat, single.Ahat)
 
 
+def test_batched_many_equal_sizes(handle, sdc):
+    """64 problems of order 128 (the sym128 recipe, per-problem seeds) in one
+    batched FP64 call: every split succeeds with the construction's rank and
+    E21 <= 1e-12 |A|_1, and a sample matches single calls bitwise."""
+    n = 128
+    probs = [S.sym_problem(n, S.family_seed(0, 300 + i)) for i in range(64)]
+    print_case(test="batched64x128")
+    regs = [sdc.region("halfplane", shift=0.0, scale=1.0)] * 64
+    out = handle.split_sym_batched([dev(a) for a, _, _ in probs], regs, sdc.opts(seed=5))
+    for i, ((a, d, q), r) in enumerate(zip(probs, out)):
+        assert r.status == sdc.SDC_OK, (i, r.status, r.info)
+        k = r.info["k_lead"]
+        assert k == int((d > 0).sum())
+        ah = host(r.Ahat)
+        assert norm1(ah[k:, :k]) <= 1e-12 * norm1(a)
+    for i in (0, 31, 63):
+        single = handle.split_sym(dev(probs[i][0]), regs[i], sdc.opts(seed=5 + i * 1000003))
+        assert torch.equal(single.Q, out[i].Q) and torch.equal(single.Ahat, out[i].Ahat)
+
+
 def test_edge_cases(handle, sdc):
     print_case(test="edges")
     # n = 1: no split possible
