@@ -59,9 +59,11 @@ __device__ __forceinline__ void node_qr(T (&p)[NR], int nbk, T* s_col, T* s_row,
         T rj = 0;  // row j of this thread's column (meaningful in group jg)
 #pragma unroll
         for (int i = 0; i < NJ; ++i) rj = i == jr ? p[i] : rj;
-        if (c == j) {
+        if (c == j) {  // rows <= j (only in registers < NJ) are zeroed
 #pragma unroll
-            for (int i = 0; i < NR; ++i) tcol[grp * NR + i] = (G * i + grp > j) ? p[i] : T(0);
+            for (int i = 0; i < NJ; ++i) tcol[grp * NR + i] = (G * i + grp > j) ? p[i] : T(0);
+#pragma unroll
+            for (int i = NJ; i < NR; ++i) tcol[grp * NR + i] = p[i];
         }
         if (grp == jg) trow[c] = rj;
         __syncthreads();
@@ -101,15 +103,21 @@ __device__ __forceinline__ void node_qr(T (&p)[NR], int nbk, T* s_col, T* s_row,
             tau = -(d * d) * r;
         }
         const T w = trow[c] + scale * zc;  // v_j^T P[:, c]  (= v_c^T v_j for c < j)
-        // c > j: p -= tau w v;  c == j: p <- v below the diagonal;  c < j: unchanged
+        // c > j: p -= tau w v = p - (tau w scale) x;  c < j: unchanged;
+        // c == j: v = x scale below the diagonal (x = 0 at rows <= j, which
+        // keep p; row j is set below).  Registers >= NJ hold rows >= NB > j,
+        // where the two cases are p * 1 + x * (-coef) and p * 0 + x * scale.
         const T tw = c > j ? tau * w : T(0);
-        const T coef = tw * scale;
         const bool isj = c == j;
+        const T coef = tw * scale;
 #pragma unroll
-        for (int i = 0; i < NR; ++i) {
+        for (int i = 0; i < NJ; ++i) {
             const T upd = p[i] - coef * x[i];
             p[i] = (isj && G * i + grp > j) ? x[i] * scale : upd;
         }
+        const T m1 = isj ? T(0) : T(1), m2 = isj ? scale : -coef;
+#pragma unroll
+        for (int i = NJ; i < NR; ++i) p[i] = x[i] * m2 + p[i] * m1;
         if (grp == jg) {  // row j: beta on the diagonal, p - tau w v_j (v_j = 1) to the right
             const T nv = isj ? beta : rj - tw;
 #pragma unroll
