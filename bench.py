@@ -37,9 +37,27 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp64_tflops": 78.6, "fp32_tflops": 157.3, "hbm_gbs": 8000.0}
 
+# HBM traffic of the dominant kernel (the tree-level trailing update), from
+# two rocprofv3 --pmc runs of `bench.py --steps 1 --warmup 0 --calibrate-copy`
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch): summed over the update's
+# dispatches in the step, each counter scaled by what it reads for a plain
+# 256 MiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), divided by the
+# number of dispatches.  Valid only for the kernel sources it was measured
+# on (their SHA-256 below); otherwise reported as null.
+TRAFFIC = {"bytes_per_launch": 36291814, "sha256": "6bf5be2748c635b134f42072ad7e26a95c98f1291795507d4b4a39cb3aa847af", "n": 2048, "leaf": 64, "note": "rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 over 20449 update dispatches of one step"}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sources_sha():
+    import hashlib
+    hsh = hashlib.sha256()
+    for f in ("qr_kernels.hip", "sdc_internal.hpp", "mfma.hpp"):
+        with open(os.path.join(ROOT, "paper_1011_3077_amd", "csrc", f), "rb") as fh:
+            hsh.update(fh.read())
+    return hsh.hexdigest()
 
 
 def cpu_baseline(n: int = 1024):
@@ -62,6 +80,89 @@ def cpu_baseline(n: int = 1024):
             "seconds": dt}
 
 
+def serve_main(args):
+    """Serving benchmark: Poisson arrivals of split requests (sizes
+    log-uniform in [nmin, nmax]; 70% symmetric, half of them FP32+refine; 30%
+    nonsymmetric pencils, FP64) into the continuous-batching server, inputs
+    resident in HBM; reports p50/p99 latency and throughput.  Requests reuse a
+    pool of distinct problems (each request draws its own Gaussian seed)."""
+    import numpy as np
+    import torch
+    import sdc_synth as S
+    import paper_1011_3077_amd as P
+
+    rng = np.random.default_rng(S.family_seed(4))
+    pool_size = 24
+    log(f"[serve] generating a pool of {pool_size} problems, n in [{args.nmin}, {args.nmax}]")
+    pool = []
+    for i in range(pool_size):
+        n = int(round(math.exp(rng.uniform(math.log(args.nmin), math.log(args.nmax)))))
+        u = rng.uniform()
+        if u < 0.7:
+            a, d, q = S.sym_problem(n, S.family_seed(4, i))
+            prec = P.SDC_FP32_REFINE if u < 0.35 else P.SDC_FP64
+            pool.append(dict(kind="sym", n=n, A=torch.from_numpy(a).to("cuda:0"), B=None,
+                             reg=P.region("halfplane", shift=0.0, scale=1.0), prec=prec, k=int((d > 0).sum())))
+        else:
+            pb = S.pencil_problem(n, S.family_seed(4, i))
+            pool.append(dict(kind="pencil", n=n, A=torch.from_numpy(pb["A"]).to("cuda:0"),
+                             B=torch.from_numpy(pb["B"]).to("cuda:0"), reg=P.region(), prec=P.SDC_FP64,
+                             k=int((np.abs(pb["lam"]) > 1).sum())))
+    torch.cuda.synchronize()
+    arrivals = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / args.rate)
+        if t > args.duration:
+            break
+        arrivals.append(t)
+    log(f"[serve] {len(arrivals)} arrivals over {args.duration} s at {args.rate}/s")
+    srv = P.Server(0)
+    tickets = []
+    t0 = time.perf_counter()
+    for i, ta in enumerate(arrivals):
+        dt = ta - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        q = pool[i % pool_size]
+        tickets.append((srv.submit(q["A"], q["B"], q["reg"], P.opts(prec=q["prec"], seed=1000 + i)), q))
+    bad = 0
+    statuses = {}
+    for tk, q in tickets:
+        r = srv.wait(tk)
+        statuses[r.status] = statuses.get(r.status, 0) + 1
+        if r.status != 0 or r.info["k_lead"] != q["k"]:
+            bad += 1
+    st = srv.stats()
+    srv.close()
+    wall = st["wall_ms"] / 1e3
+    out = {
+        "metric": "served split requests: p99 latency (submission to completion)",
+        "value": st["p99_ms"],
+        "unit": "ms",
+        "higher_is_better": False,
+        "n_gpus": 1,
+        "p50_ms": st["p50_ms"],
+        "mean_ms": st["mean_ms"],
+        "max_ms": st["max_ms"],
+        "throughput_req_s": st["completed"] / wall if wall > 0 else None,
+        "nominal_gflops": st["nominal_flops"] / wall / 1e9 if wall > 0 else None,
+        "offered_rate_req_s": args.rate,
+        "requests": st["completed"],
+        "wrong_or_failed": bad,
+        "statuses": {str(k): v for k, v in statuses.items()},
+        "peak_active": st["peak_active"],
+        "peak_bytes": st["peak_bytes"],
+        "budget_bytes": st["budget_bytes"],
+        "dtype": "f64 / f32+f64-refine",
+        "data": "synthetic",
+        "config": {"workload": f"Poisson {args.rate}/s for {args.duration} s, n log-uniform in "
+                               f"[{args.nmin}, {args.nmax}], 70% symmetric (half FP32+refine), 30% pencils",
+                   "pool": pool_size},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +172,13 @@ def main():
     ap.add_argument("--leaf", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-launch events")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 256 MiB device copy first (reference kernel for HBM counters)")
+    ap.add_argument("--serve", action="store_true", help="serving benchmark instead (see serve_main)")
+    ap.add_argument("--rate", type=float, default=4.0, help="--serve: Poisson arrival rate, requests/s")
+    ap.add_argument("--duration", type=float, default=15.0, help="--serve: seconds of arrivals")
+    ap.add_argument("--nmin", type=int, default=64)
+    ap.add_argument("--nmax", type=int, default=2048)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -83,6 +191,14 @@ def main():
     import sdc_synth as S
     import paper_1011_3077_amd as P
 
+    if args.serve:
+        return serve_main(args)
+    if args.calibrate_copy:
+        x = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     n, leaf = args.n, args.leaf
     log(f"[bench] generating order-{n} pencil")
     pb = S.pencil_problem(n, S.family_seed(1))
@@ -145,6 +261,10 @@ def main():
                     ach = sd["flops"] / secs / 1e12
                     roof = {"bound": "mfma", "achieved": ach, "peak": PEAK["fp64_tflops"], "unit": "TFLOP/s",
                             "frac": ach / PEAK["fp64_tflops"], "traffic": None}
+            if dom == P.KERNEL_UPDATE and TRAFFIC and TRAFFIC.get("sha256") == kernel_sources_sha() \
+                    and TRAFFIC.get("n") == n and TRAFFIC.get("leaf") == leaf:
+                roof["traffic"] = TRAFFIC["bytes_per_launch"]
+                roof["traffic_note"] = TRAFFIC["note"]
             roof["kernel"] = names[dom]
             roof["launches"] = sd["launches"]
             roof["avg_launch_us"] = sd["ms"] * 1e3 / max(sd["launches"], 1)
