@@ -29,8 +29,9 @@
  *     solving X A11 - A22 X = E21 by conjugate gradients, Q <- Q [I -X^T; X I]
  *     re-orthonormalized, up to 3 rounds, until ||E21||_1/||A||_1 <=
  *     split_tol.  The refinement needs the two eigenvalue groups separated by
- *     a point (a half-plane split); otherwise the split is reported as
- *     RANK_AMBIGUOUS.
+ *     a point (a half-plane split).  A problem whose FP32 attempts all fail
+ *     (any status other than SDC_OK and SDC_NO_SPLIT) is split again in FP64
+ *     and info->fp64_fallback is set.
  *   - Eigenvalues of the pencil A - lambda B are the roots of
  *     det(A - lambda B) = 0.  The region's boundary is mapped to the unit
  *     circle (Sec. 3.3): a half plane Re z < shift with scale s becomes the
@@ -111,6 +112,8 @@ typedef struct {
     double orth_err;     /* ||Q^T Q - I||_F of Q (Q_R), if diagnostics */
     double rank_gap;     /* ratio across the largest gap of the sorted diagonal ratios */
     double ms;           /* wall time of the call in milliseconds */
+    int fp64_fallback;   /* SDC_FP32_REFINE: 1 if every FP32 attempt failed and the split
+                            was redone in FP64 (the reported result is the FP64 one) */
 } sdc_info_t;
 
 /* Fill *opts with the defaults (FP64, tau = sqrt(eps), maxit 60, seed 0,

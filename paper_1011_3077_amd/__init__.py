@@ -49,7 +49,8 @@ class Info(C.Structure):
     _fields_ = [("n", C.c_int), ("k_lead", C.c_int), ("n_inside", C.c_int), ("iters_right", C.c_int),
                 ("iters_left", C.c_int), ("attempts", C.c_int), ("refine_rounds", C.c_int),
                 ("k_rho", C.c_int), ("rconv_last", C.c_double), ("e21_rel", C.c_double),
-                ("orth_err", C.c_double), ("rank_gap", C.c_double), ("ms", C.c_double)]
+                ("orth_err", C.c_double), ("rank_gap", C.c_double), ("ms", C.c_double),
+                ("fp64_fallback", C.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -854,6 +854,10 @@ static bool irs_finished(const JobWs& w) {
 
 static int finish_jobs(Handle& h, std::vector<JobWs*>& wsp);
 
+bool fp32_needs_fallback(int status) {
+    return status != SDC_OK && status != SDC_NO_SPLIT;
+}
+
 int run_split_jobs(Handle& h, std::vector<SplitJob>& jobs) {
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<JobWs> ws(jobs.size());
@@ -896,6 +900,25 @@ int run_split_jobs(Handle& h, std::vector<SplitJob>& jobs) {
     h.desc_off = 0;
     CHK(finish_jobs(h, wsp));
     HIPCHK(hipStreamSynchronize(h.stream));
+    // FP32 attempts that all failed: redo those problems in FP64 (the
+    // workspace above is free again; every result has reached its outputs)
+    std::vector<SplitJob> redo;
+    std::vector<size_t> at;
+    for (size_t i = 0; i < jobs.size(); ++i)
+        if (ws[i].fp32 && fp32_needs_fallback(jobs[i].status)) {
+            redo.push_back(jobs[i]);
+            redo.back().opts.prec = SDC_FP64;
+            redo.back().info = sdc_info_t{};
+            at.push_back(i);
+        }
+    if (!redo.empty()) {
+        CHK(run_split_jobs(h, redo));
+        for (size_t q = 0; q < redo.size(); ++q) {
+            jobs[at[q]].status = redo[q].status;
+            jobs[at[q]].info = redo[q].info;
+            jobs[at[q]].info.fp64_fallback = 1;
+        }
+    }
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     for (JobWs& w : ws) w.job->info.ms = ms;
     return SDC_OK;

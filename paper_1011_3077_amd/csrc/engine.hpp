@@ -82,6 +82,8 @@ struct SplitJob {
 // Runs every job; returns a negative status on argument/device failure,
 // else SDC_OK (per-job statuses in job.status).
 int run_split_jobs(Handle& h, std::vector<SplitJob>& jobs);
+// An SDC_FP32_REFINE split that ended with this status is redone in FP64.
+bool fp32_needs_fallback(int status);
 
 // IRS alone for one side; see sdc_irs.
 int run_irs_only(Handle& h, int n, const double* A, int lda, const double* B, int ldb, int transpose,

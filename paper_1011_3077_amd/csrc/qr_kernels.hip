@@ -405,33 +405,45 @@ __global__ __launch_bounds__(256, 2) void k_update(const QrDesc<T>* __restrict__
         }
     }
     // W = V^T C (NB x 16): per row block, C goes through the wave's LDS tile
-    // into the B-operand layout; two accumulator chains per half (even / odd
-    // row blocks)
+    // into the B-operand layout.  Software pipelined: the LDS traffic of row
+    // block rb + 1 (tile write, operand reads) is issued before the MFMAs of
+    // rb.  A wave's LDS operations complete in issue order, so the tile can be
+    // rewritten after the previous block's reads without a barrier.  Two
+    // accumulator chains per half (even / odd row blocks).
     T* X = s_X + wave * 16 * XS;
     v4 w0 = v4{0, 0, 0, 0}, w1 = v4{0, 0, 0, 0}, w2 = v4{0, 0, 0, 0}, w3 = v4{0, 0, 0, 0};
+    T ob[2][4], ova[2][4], ovb[2][4];
+#define SDC_STAGE_W(RBI, BUF)                                                     \
+    {                                                                             \
+        _Pragma("unroll") for (int v = 0; v < 4; ++v) X[ln * XS + M::row(gq, v)] = cr[RBI][v]; \
+        _Pragma("unroll") for (int kk = 0; kk < 4; ++kk) {                        \
+            ob[BUF][kk] = X[(4 * kk + gq) * XS + ln];                             \
+            const T* vr = s_V + ((RBI) * 16 + 4 * kk + gq) * VS;                  \
+            ova[BUF][kk] = vr[ln];                                                \
+            ovb[BUF][kk] = vr[16 + ln];                                           \
+        }                                                                         \
+    }
+    if (rbe > 0) SDC_STAGE_W(0, 0)
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
         if (rb < rbe) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) X[ln * XS + M::row(gq, v)] = cr[rb][v];
-            __builtin_amdgcn_wave_barrier();
-            T b[4];
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) b[kk] = X[(4 * kk + gq) * XS + ln];
-            __builtin_amdgcn_wave_barrier();
+            if (rb + 1 < RB && rb + 1 < rbe) SDC_STAGE_W(rb + 1 < RB ? rb + 1 : rb, (rb + 1) & 1)
+            __builtin_amdgcn_sched_barrier(0);
+            const int bf = rb & 1;
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
-                const T* vr = s_V + (rb * 16 + 4 * kk + gq) * VS;
                 if (rb & 1) {
-                    w2 = M::mma(vr[ln], b[kk], w2);
-                    w3 = M::mma(vr[16 + ln], b[kk], w3);
+                    w2 = M::mma(ova[bf][kk], ob[bf][kk], w2);
+                    w3 = M::mma(ovb[bf][kk], ob[bf][kk], w3);
                 } else {
-                    w0 = M::mma(vr[ln], b[kk], w0);
-                    w1 = M::mma(vr[16 + ln], b[kk], w1);
+                    w0 = M::mma(ova[bf][kk], ob[bf][kk], w0);
+                    w1 = M::mma(ovb[bf][kk], ob[bf][kk], w1);
                 }
             }
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
+#undef SDC_STAGE_W
     w0 += w2;
     w1 += w3;
     // Y = T^T W
@@ -445,16 +457,23 @@ __global__ __launch_bounds__(256, 2) void k_update(const QrDesc<T>* __restrict__
             y1 = M::mma(ta[1][kb][j], bw, y1);
         }
     }
-    // C^T -= Y^T V^T: k-steps outer, row blocks inner (RB independent accumulators)
+    // C^T -= Y^T V^T: k-steps outer, row blocks inner (RB independent
+    // accumulators); each k-step's V^T operands are read from LDS together
+    // before its MFMAs
 #pragma unroll
     for (int pb = 0; pb < 2; ++pb) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const T a = -(pb ? y1[j] : y0[j]);
             const int kcol = pb * 16 + M::row(gq, j);
+            T vb[RB];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) vb[rb] = rb < rbe ? s_V[(rb * 16 + ln) * VS + kcol] : T(0);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
-                if (rb < rbe) cr[rb] = M::mma(a, s_V[(rb * 16 + ln) * VS + kcol], cr[rb]);
+                if (rb < rbe) cr[rb] = M::mma(a, vb[rb], cr[rb]);
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 #pragma unroll

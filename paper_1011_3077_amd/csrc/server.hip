@@ -30,6 +30,7 @@ namespace {
 
 struct Request {
     long long ticket = 0;
+    bool fallback = false;  // redone in FP64 after failed FP32 attempts
     sdc::SplitJob job;
     Clock::time_point t_submit;
     size_t bytes = 0;
@@ -80,6 +81,7 @@ struct sdc_server_s {
         res.status = status;
         res.info = r->job.info;
         res.info.ms = ms;
+        res.info.fp64_fallback = r->fallback ? 1 : 0;
         lat_ms.push_back(ms);
         ++completed;
         if (status < 0) ++failed;
@@ -156,7 +158,22 @@ void sdc_server_s::loop() {
         std::vector<Request*> keep;
         for (size_t i = 0; i < active.size(); ++i) {
             Request* r = active[i];
-            if (rc < 0 || done[i]) {
+            if (rc >= 0 && done[i] && r->job.opts.prec == SDC_FP32_REFINE &&
+                sdc::fp32_needs_fallback(r->job.status)) {
+                // every FP32 attempt failed: requeue first in line, in FP64
+                used -= r->bytes;
+                sdc::job_run_destroy(r->run);
+                r->run = nullptr;
+                (void)hipFree(r->ws);
+                r->ws = nullptr;
+                r->fallback = true;
+                r->job.opts.prec = SDC_FP64;
+                r->job.status = 0;
+                r->job.info = sdc_info_t{};
+                r->job.info.n = r->job.n;
+                r->bytes = sdc::job_run_bytes(r->job);
+                pending.push_front(r);
+            } else if (rc < 0 || done[i]) {
                 used -= r->bytes;
                 complete(r, rc < 0 ? rc : r->job.status);
                 release(r);

@@ -157,3 +157,39 @@ def test_fp32_refine_rejected_for_pencils(handle, sdc):
     p = S.pencil_problem(16, S.family_seed(1, 3))
     with pytest.raises(sdc.SdcError):
         handle.split_pencil(dev(p["A"]), dev(p["B"]), sdc.region(), sdc.opts(prec=sdc.SDC_FP32_REFINE))
+
+
+def near_shift_problem(n, seed, d0):
+    """Symmetric problem with one eigenvalue at d0 (next to the split point 0)
+    and the others with |d| >= 0.05: FP32 iterates cannot resolve its side."""
+    a, d, q = S.sym_problem(n, seed)
+    d = d.copy()
+    d[0] = d0
+    a = (q * d[None, :]) @ q.T
+    return np.asfortranarray(0.5 * (a + a.T)), d
+
+
+def test_fp32_falls_back_to_fp64(handle, sdc):
+    """An eigenvalue 1e-12 from the split point is below FP32 resolution: the
+    FP32 attempts fail, the split is redone in FP64 and is exact."""
+    n = 64
+    print("CASE fp32 fallback", n, flush=True)
+    a, d = near_shift_problem(n, S.family_seed(2, 77), 1e-12)
+    res = handle.split_sym(dev(a), sdc.region("halfplane", shift=0.0, scale=1.0),
+                           sdc.opts(prec=sdc.SDC_FP32_REFINE, seed=9))
+    assert res.info["fp64_fallback"] == 1
+    check_split(res, a, d, n, eig_tol=1e-12)
+
+
+def test_fp32_fallback_in_server(handle, sdc):
+    n = 64
+    a, d = near_shift_problem(n, S.family_seed(2, 78), -1e-12)
+    srv = sdc.Server(0)
+    try:
+        t = srv.submit(dev(a), None, sdc.region("halfplane", shift=0.0, scale=1.0),
+                       sdc.opts(prec=sdc.SDC_FP32_REFINE, seed=9))
+        r = srv.wait(t)
+    finally:
+        srv.close()
+    assert r.info["fp64_fallback"] == 1
+    check_split(r, a, d, n, eig_tol=1e-12)
