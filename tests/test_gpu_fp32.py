@@ -161,7 +161,7 @@ def test_fp32_refine_rejected_for_pencils(handle, sdc):
 
 def near_shift_problem(n, seed, d0):
     """Symmetric problem with one eigenvalue at d0 (next to the split point 0)
-    and the others with |d| >= 0.05: FP32 iterates cannot resolve its side."""
+    and the others with |d| >= 0.05."""
     a, d, q = S.sym_problem(n, seed)
     d = d.copy()
     d[0] = d0
@@ -169,13 +169,47 @@ def near_shift_problem(n, seed, d0):
     return np.asfortranarray(0.5 * (a + a.T)), d
 
 
-def test_fp32_falls_back_to_fp64(handle, sdc):
+def test_fp32_near_shift_eigenvalue_either_side(handle, sdc):
     """An eigenvalue 1e-12 from the split point is below FP32 resolution: the
-    FP32 attempts fail, the split is redone in FP64 and is exact."""
+    FP32 iterates may put it on either side, and what comes back is still an
+    exact (FP64-quality) invariant-subspace split with every other eigenvalue
+    on its own side."""
     n = 64
-    print("CASE fp32 fallback", n, flush=True)
+    print("CASE fp32 near shift", n, flush=True)
     a, d = near_shift_problem(n, S.family_seed(2, 77), 1e-12)
     res = handle.split_sym(dev(a), sdc.region("halfplane", shift=0.0, scale=1.0),
+                           sdc.opts(prec=sdc.SDC_FP32_REFINE, seed=9))
+    assert res.status == 0, res.status
+    k = res.info["k_lead"]
+    kpos = int((d > 0).sum())
+    assert k in (kpos - 1, kpos)
+    Q, Ah = host(res.Q), host(res.Ahat)
+    assert np.abs(Q.T @ Q - np.eye(n)).max() <= 1e-13 * np.sqrt(n)
+    assert norm1(Ah[k:, :k]) <= 1e-10 * norm1(a)
+    e1 = np.linalg.eigvalsh(Ah[:k, :k])
+    e2 = np.linalg.eigvalsh(Ah[k:, k:])
+    assert np.abs(np.sort(np.concatenate([e1, e2])) - np.sort(d)).max() <= 1e-9
+    assert e1.min() >= -1e-9 and e2.max() <= 1e-9
+
+
+def overflow_problem(n, seed, sign):
+    """Symmetric problem scaled past the FP32 range (|a_ij| up to ~1e39 >
+    FLT_MAX): FP32 iterates cannot hold it, FP64 can.  The half-plane map
+    takes the problem's scale (A0 = A + sI, B0 = A - sI with s = 1e40), so
+    the FP64 iteration converges as for the unscaled problem."""
+    a, d, q = S.sym_problem(n, seed)
+    s = sign * 1e40
+    return np.asfortranarray(a * s), d * s
+
+
+def test_fp32_falls_back_to_fp64(handle, sdc):
+    """The FP32 iterates overflow (SDC_ERR_NONFINITE on the FP32 attempt):
+    the split is redone in FP64 and is exact."""
+    n = 64
+    print("CASE fp32 fallback", n, flush=True)
+    a, d = overflow_problem(n, S.family_seed(2, 77), 1.0)
+    assert np.abs(a).max() > np.finfo(np.float32).max
+    res = handle.split_sym(dev(a), sdc.region("halfplane", shift=0.0, scale=1e40),
                            sdc.opts(prec=sdc.SDC_FP32_REFINE, seed=9))
     assert res.info["fp64_fallback"] == 1
     check_split(res, a, d, n, eig_tol=1e-12)
@@ -183,10 +217,11 @@ def test_fp32_falls_back_to_fp64(handle, sdc):
 
 def test_fp32_fallback_in_server(handle, sdc):
     n = 64
-    a, d = near_shift_problem(n, S.family_seed(2, 78), -1e-12)
+    print("CASE fp32 fallback server", n, flush=True)
+    a, d = overflow_problem(n, S.family_seed(2, 78), -1.0)
     srv = sdc.Server(0)
     try:
-        t = srv.submit(dev(a), None, sdc.region("halfplane", shift=0.0, scale=1.0),
+        t = srv.submit(dev(a), None, sdc.region("halfplane", shift=0.0, scale=1e40),
                        sdc.opts(prec=sdc.SDC_FP32_REFINE, seed=9))
         r = srv.wait(t)
     finally:
