@@ -23,185 +23,312 @@
 
 namespace sdc {
 
-// Householder QR of one tree node held in registers by a PT-thread
-// workgroup (PT/32 = G row groups; with PT = 64 the workgroup is a single
-// wavefront, so its barriers cost little).  Thread (grp = tid/32, c = tid%32) owns
-// column c, rows r = G*i + grp (i < NR, NR a compile-time tile height).  Rows
-// beyond the node and columns >= nbk are zero and stay zero, so every loop
-// runs over all NR registers without guards.
-//
-// Column step j (the usual reflector H_j = I - tau v v^T, v_j = 1,
-// beta = -sign(alpha) ||x||, tau = (beta - alpha)/beta, v = x/(alpha - beta)):
-// one reduction gives, for every column c, the dot product of column c with
-// the part of column j below the diagonal; from it each thread gets the
-// norm, the reflector scalars, w_c = v^T P[:, c] and (for c < j) the entries
-// v_c^T v_j needed for the compact-WY factor T.  The broadcast column is read
-// from LDS once into registers and serves both the reduction and the update;
-// the broadcast buffers alternate between steps.
-//
-// On return the registers hold R (upper part, diagonal = beta) and V
-// (strictly lower part); s_tau/s_beta hold tau and beta, s_T the
-// upper-triangular T (stride NB+1) with H_0 ... H_{nbk-1} = I - V T V^T.
-// Always inlined: a call would pass the register tile by reference and so
-// force it into scratch memory.
-template <typename T, int NR>
-__device__ __forceinline__ void node_qr(T (&p)[NR], int nbk, T* s_col, T* s_row, T* s_red, T* s_Sm, T* s_T,
-                                        T* s_tau, T* s_beta) {
-    constexpr int NB = QrCfg<T>::NB, G = QrCfg<T>::PT / 32;
-    // row j < NB of the node is register j / G of group j % G
-    constexpr int NJ = NB / G;
-    static_assert(NB % G == 0 && NJ <= NR, "the first NB rows must sit in registers [0, NB / G)");
-    const int tid = threadIdx.x, grp = tid >> 5, c = tid & 31;
-    for (int j = 0; j < nbk; ++j) {
-        const int jr = j / G, jg = j % G;
-        T* tcol = s_col + (j & 1) * G * NR;
-        T* trow = s_row + (j & 1) * NB;
-        T rj = 0;  // row j of this thread's column (meaningful in group jg)
-#pragma unroll
-        for (int i = 0; i < NJ; ++i) rj = i == jr ? p[i] : rj;
-        if (c == j) {  // rows <= j (only in registers < NJ) are zeroed
-#pragma unroll
-            for (int i = 0; i < NJ; ++i) tcol[grp * NR + i] = (G * i + grp > j) ? p[i] : T(0);
-#pragma unroll
-            for (int i = NJ; i < NR; ++i) tcol[grp * NR + i] = p[i];
-        }
-        if (grp == jg) trow[c] = rj;
-        __syncthreads();
-        T x[NR];
-#pragma unroll
-        for (int i = 0; i < NR; ++i) x[i] = tcol[grp * NR + i];  // zero at rows <= j
-        T z0 = 0, z1 = 0, z2 = 0, z3 = 0;
-#pragma unroll
-        for (int i = 0; i < NR; i += 4) {
-            z0 += x[i] * p[i];
-            if (i + 1 < NR) z1 += x[i + 1] * p[i + 1];
-            if (i + 2 < NR) z2 += x[i + 2] * p[i + 2];
-            if (i + 3 < NR) z3 += x[i + 3] * p[i + 3];
-        }
-        s_red[grp * NB + c] = (z0 + z1) + (z2 + z3);
-        __syncthreads();
-        T zc = 0, xn2 = 0;
-#pragma unroll
-        for (int q = 0; q < G; ++q) {
-            zc += s_red[q * NB + c];
-            xn2 += s_red[q * NB + j];
-        }
-        const T alpha = trow[j];
-        T beta, tau, scale;
-        if (xn2 == T(0)) {
-            beta = alpha;
-            tau = 0;
-            scale = 0;
-        } else {
-            const T nrm = sqrt(alpha * alpha + xn2);
-            beta = alpha >= T(0) ? -nrm : nrm;
-            // one division: r = 1 / (beta (alpha - beta)) gives
-            // scale = 1 / (alpha - beta) = beta r, tau = (beta - alpha) / beta = -(alpha - beta)^2 r
-            const T d = alpha - beta;
-            const T r = T(1) / (beta * d);
-            scale = beta * r;
-            tau = -(d * d) * r;
-        }
-        const T w = trow[c] + scale * zc;  // v_j^T P[:, c]  (= v_c^T v_j for c < j)
-        // c > j: p -= tau w v = p - (tau w scale) x;  c < j: unchanged;
-        // c == j: v = x scale below the diagonal (x = 0 at rows <= j, which
-        // keep p; row j is set below).  Registers >= NJ hold rows >= NB > j,
-        // where the two cases are p * 1 + x * (-coef) and p * 0 + x * scale.
-        const T tw = c > j ? tau * w : T(0);
-        const bool isj = c == j;
-        const T coef = tw * scale;
-#pragma unroll
-        for (int i = 0; i < NJ; ++i) {
-            const T upd = p[i] - coef * x[i];
-            p[i] = (isj && G * i + grp > j) ? x[i] * scale : upd;
-        }
-        const T m1 = isj ? T(0) : T(1), m2 = isj ? scale : -coef;
-#pragma unroll
-        for (int i = NJ; i < NR; ++i) p[i] = x[i] * m2 + p[i] * m1;
-        if (grp == jg) {  // row j: beta on the diagonal, p - tau w v_j (v_j = 1) to the right
-            const T nv = isj ? beta : rj - tw;
-#pragma unroll
-            for (int i = 0; i < NJ; ++i) p[i] = i == jr ? nv : p[i];
-        }
-        if (c < j && grp == 0) s_Sm[c * (NB + 1) + j] = w;
-        if (tid == 0) {
-            s_tau[j] = tau;
-            s_beta[j] = beta;
-        }
+// ---------------------------------------------------------------------------
+// Cross-lane moves inside one wavefront (T = float or double).
+// ---------------------------------------------------------------------------
+template <int CTRL, typename T> __device__ __forceinline__ T lane_dpp(T v) {
+    return __builtin_amdgcn_update_dpp(T(0), v, CTRL, 0xF, 0xF, false);
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]: lane ^ 1
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]: lane ^ 2
+constexpr int kDppHalfMirror = 0x141; // lane ^ 7 within each 8 lanes
+constexpr int kDppMirror = 0x140;     // lane ^ 15 within each 16 lanes
+
+// v(lane) + v(lane ^ 16) (R16) or v(lane) + v(lane ^ 32) (R32) in every lane,
+// with the gfx950 row swaps: swapping a value with itself across 16-lane
+// (32-lane) rows leaves one copy of the pair in each result, so their sum is
+// the pair sum, in the same order in both lanes of a pair.
+template <bool R32> __device__ __forceinline__ void row_swap(unsigned& x, unsigned& y) {
+    if constexpr (R32) {
+        const auto p = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+        x = p[0];
+        y = p[1];
+    } else {
+        const auto p = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+        x = p[0];
+        y = p[1];
     }
-    __syncthreads();
-    // Compact-WY factor, forward columnwise recurrence
-    //   T[i][j] = -tau_j sum_{l=i}^{j-1} T[i][l] (v_l^T v_j),  T[i][i] = tau_i:
-    // thread r < NB keeps row r of T in registers; rows are independent.
-    if (tid < NB) {
-        const int r = tid;
-        T t[NB];
-#pragma unroll
-        for (int l = 0; l < NB; ++l) t[l] = (l == r && l < nbk) ? s_tau[l] : T(0);
-#pragma unroll
-        for (int j = 1; j < NB; ++j) {
-            if (j < nbk) {
-                T a0 = 0, a1 = 0;
-#pragma unroll
-                for (int l = 0; l < j; ++l) {
-                    const T term = l >= r ? t[l] * s_Sm[l * (NB + 1) + j] : T(0);
-                    if (l & 1) a1 += term;
-                    else a0 += term;
-                }
-                if (r < j) t[j] = -s_tau[j] * (a0 + a1);
-            }
-        }
-#pragma unroll
-        for (int l = 0; l < NB; ++l) s_T[r * (NB + 1) + l] = t[l];
+}
+template <bool R32, typename T> __device__ __forceinline__ T pair_sum(T v) {
+    if constexpr (sizeof(T) == 8) {
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+        unsigned lo0 = (unsigned)b, lo1 = lo0, hi0 = (unsigned)(b >> 32), hi1 = hi0;
+        row_swap<R32>(lo0, lo1);
+        row_swap<R32>(hi0, hi1);
+        const T u = __builtin_bit_cast(T, ((unsigned long long)hi0 << 32) | lo0);
+        const T w = __builtin_bit_cast(T, ((unsigned long long)hi1 << 32) | lo1);
+        return u + w;
+    } else {
+        unsigned x = __builtin_bit_cast(unsigned, v), y = x;
+        row_swap<R32>(x, y);
+        return __builtin_bit_cast(T, x) + __builtin_bit_cast(T, y);
     }
-    __syncthreads();
 }
 
-// Factor the mt x nbk node staged column-major in s_tile (stride LDT) with an
-// NR-row register tile: load, QR, write T (NB x NB, column-major) to Tg, and
-// put R/V back into s_tile.  s_red/s_Sm/s_T alias the start of s_tile.
-template <typename T, int NR>
-__device__ __forceinline__ void factor_tile(T* s_tile, int mt, int nbk, T* s_col, T* s_row, T* s_tau, T* s_beta,
-                                            T* Tg) {
-    constexpr int NB = QrCfg<T>::NB, LDT = QrCfg<T>::MT_MAX + 1, G = QrCfg<T>::PT / 32, PT = QrCfg<T>::PT;
-    const int tid = threadIdx.x, grp = tid >> 5, c = tid & 31;
-    T* s_red = s_tile;
-    T* s_Sm = s_tile + G * NB;
-    T* s_T = s_Sm + NB * (NB + 1);
-    T p[NR];
+// Value of v in lane `lane` (a wave-uniform index), for every lane.
+template <typename T> __device__ __forceinline__ T lane_read(T v, int lane) {
+    if constexpr (sizeof(T) == 8) {
+        const long long b = __builtin_bit_cast(long long, v);
+        const int lo = __builtin_amdgcn_readlane((int)b, lane);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+        return __builtin_bit_cast(T, ((long long)hi << 32) | (long long)(unsigned)lo);
+    } else {
+        return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+    }
+}
+
+// Sum of v over the 64 lanes, in every lane (each stage adds the partner's
+// value, a + b in one lane and b + a in the other, so all lanes agree bitwise).
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+    v += lane_dpp<kDppXor1>(v);
+    v += lane_dpp<kDppXor2>(v);
+    v += lane_dpp<kDppHalfMirror>(v);
+    v += lane_dpp<kDppMirror>(v);
+    v = pair_sum<false>(v);
+    return pair_sum<true>(v);
+}
+
+// Sums over the 64 lanes of eight values q[0..7] at once: each exchange
+// stage halves the values a lane carries (it keeps one half, adds the
+// partner's copy of it, and hands over the other half), so that after the
+// three 16-lane stages lane l carries column c(l) = (l >> 1) & 7 summed over
+// its 16-lane row; three plain stages finish the sum over the wave.  The
+// total of column c is then in lane 2c (among others).
+template <typename T> __device__ __forceinline__ T wave_sum8(const T (&q)[8], int lane) {
+    const bool b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+    T h[4], g[2];
 #pragma unroll
-    for (int i = 0; i < NR; ++i) {
-        const int r = G * i + grp;
-        p[i] = r < mt ? s_tile[c * LDT + r] : T(0);
+    for (int k = 0; k < 4; ++k) {  // partner lane ^ 15: columns by bit 3
+        const T keep = b3 ? q[k + 4] : q[k], send = b3 ? q[k] : q[k + 4];
+        h[k] = keep + lane_dpp<kDppMirror>(send);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {  // partner lane ^ 7: by bit 2
+        const T keep = b2 ? h[k + 2] : h[k], send = b2 ? h[k] : h[k + 2];
+        g[k] = keep + lane_dpp<kDppHalfMirror>(send);
+    }
+    const T keep = b1 ? g[1] : g[0], send = b1 ? g[0] : g[1];  // partner lane ^ 2: by bit 1
+    T f = keep + lane_dpp<kDppXor2>(send);
+    f += lane_dpp<kDppXor1>(f);
+    f = pair_sum<false>(f);
+    return pair_sum<true>(f);
+}
+
+// ---------------------------------------------------------------------------
+// Householder QR of one tree node held in registers, row-owner layout: wave
+// wv = tid / 64 owns columns [8 wv, 8 wv + 8) and lane l its rows l + 64 i
+// (i < NRW), so a wave holds whole columns and the dot products of a step
+// are summed inside the wave by lane exchanges, not through LDS.  Only
+// column j crosses waves: its owner publishes it to LDS, with its squared
+// norm below the diagonal and its diagonal entry alpha, before the step's
+// single barrier.
+//
+// Step j (H_j = I - tau v v^T, v_j = 1, beta = -sign(alpha) ||x||,
+// d = alpha - beta, v = x / d below the diagonal, tau = -d / beta): with
+// xh = x below the diagonal, xh_j = d and 0 above, v = xh / d on rows >= j, so
+//   S_c = sum_r xh_r a_rc   (one eight-column wave sum),
+//   w_c = v^T a_c = S_c / d (for c < j this is v_c^T v_j),
+//   a_c <- a_c - (tau w_c / d) xh   for c > j,
+// and column j becomes beta on the diagonal and v below it.  Rows beyond the
+// node and columns >= nbk are zero and stay zero.
+//
+// The compact-WY factor (H_0 ... H_{nbk-1} = I - V T V^T, T upper
+// triangular) follows the forward recurrence
+//   T[i][j] = -tau_j sum_{l=i}^{j-1} T[i][l] (v_l^T v_j),  T[j][j] = tau_j,
+// built alongside: lanes i < NB of wave wv keep T[i][l] for the wave's
+// columns l; at step j each wave adds up its columns' share of the sum with
+// the w_l it already has, leaves it in LDS, and the owner of column j
+// finishes that column after the next barrier.
+// ---------------------------------------------------------------------------
+template <typename T, int NRW, int CC>
+__device__ __forceinline__ void qr_publish(const T (&a)[NRW][8], int jn, T* xs, T* sc) {
+    const int l = threadIdx.x & 63;
+    T nsq = 0;
+#pragma unroll
+    for (int i = 0; i < NRW; ++i) {
+        const int r = l + 64 * i;
+        const T v = a[i][CC];
+        xs[r] = v;
+        nsq += r > jn ? v * v : T(0);
+    }
+    nsq = wave_sum(nsq);
+    const T al = lane_read(a[0][CC], jn);  // row jn < 64 is register 0 of lane jn
+    if (l == 0) {
+        sc[0] = nsq;
+        sc[1] = al;
+    }
+}
+
+// T column j of the node from the waves' partial sums p[4][32] (lanes i < NB).
+template <typename T>
+__device__ __forceinline__ T qr_tcol(const T* p, int j, T tauj) {
+    const int i = threadIdx.x & 31, l = threadIdx.x & 63;
+    const T s = (p[i] + p[32 + i]) + (p[64 + i] + p[96 + i]);
+    return l < j ? -tauj * s : (l == j ? tauj : T(0));
+}
+
+template <typename T, int NRW, int JJ>
+__device__ __forceinline__ bool qr_step(T (&a)[NRW][8], T (&tc)[8], T& tau_prev, int jw, int nbk, T* s_x, T* s_sc,
+                                        T* s_P, T* s_tau, T* s_beta) {
+    const int j = 8 * jw + JJ;
+    if (j >= nbk) return false;
+    const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
+    const int par = j & 1;
+    const T* xs = s_x + par * 256;
+    const T xn2 = s_sc[par * 2], alpha = s_sc[par * 2 + 1];
+    T xh[NRW];
+#pragma unroll
+    for (int i = 0; i < NRW; ++i) {
+        const int r = l + 64 * i;
+        const T x = xs[r];
+        xh[i] = r > j ? x : T(0);
+    }
+    // finish T column j - 1 (its owner, register (JJ + 7) % 8)
+    if (j > 0 && wv == ((j - 1) >> 3)) tc[(JJ + 7) & 7] = qr_tcol(s_P + (par ^ 1) * 128, j - 1, tau_prev);
+    // reflector scalars, without branches (the zero-norm case selected at the end)
+    const T nrm = sqrt(alpha * alpha + xn2);
+    const T b0 = alpha >= T(0) ? -nrm : nrm;
+    const T d0 = alpha - b0;
+    // one division: rr = 1 / (beta d) gives 1 / d = beta rr, tau = -d / beta = -d^2 rr
+    const T rr = T(1) / (b0 * d0);
+    const bool zero = xn2 == T(0);
+    const T beta = zero ? alpha : b0;
+    const T scale = zero ? T(0) : b0 * rr;
+    const T tau = zero ? T(0) : -(d0 * d0) * rr;
+    const T dd = zero ? T(0) : d0;
+    // products over the rows below the diagonal, then row j's term (row j < 64:
+    // register 0 of lane j) once d is known
+    T q[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        T s = xh[0] * a[0][c];
+#pragma unroll
+        for (int i = 1; i < NRW; ++i) s = fma(xh[i], a[i][c], s);
+        q[c] = s;
+    }
+    const bool rowj = l == j;
+    const T dj = rowj ? dd : T(0);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) q[c] = fma(dj, a[0][c], q[c]);
+    xh[0] = rowj ? dd : xh[0];
+    const T f = wave_sum8(q, l);
+    T w[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) w[c] = scale * lane_read(f, 2 * c);
+    // this wave's share of T column j (tc is zero for columns >= j)
+    T pj = tc[0] * w[0];
+#pragma unroll
+    for (int c = 1; c < 8; ++c) pj = fma(tc[c], w[c], pj);
+    if (l < 32) s_P[par * 128 + wv * 32 + l] = pj;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int col = 8 * wv + c;
+        const T coef = col > j ? tau * w[c] * scale : T(0);
+#pragma unroll
+        for (int i = 0; i < NRW; ++i) a[i][c] = fma(-coef, xh[i], a[i][c]);
+    }
+    if (wv == jw) {
+#pragma unroll
+        for (int i = 0; i < NRW; ++i) {
+            const int r = l + 64 * i;
+            a[i][JJ] = r > j ? xh[i] * scale : (r == j ? beta : a[i][JJ]);
+        }
+    }
+    if (tid == 0) {
+        s_tau[j] = tau;
+        s_beta[j] = beta;
+    }
+    tau_prev = tau;
+    if (j + 1 < nbk) {
+        if (wv == (j + 1) >> 3)
+            qr_publish<T, NRW, (JJ + 1) & 7>(a, j + 1, s_x + ((j + 1) & 1) * 256, s_sc + ((j + 1) & 1) * 2);
+        __syncthreads();
+    }
+    return true;
+}
+
+// Factor the node; T (NB x NB, column-major) goes to Tg.  s_P holds 256
+// elements of scratch.
+template <typename T, int NRW>
+__device__ __forceinline__ void node_qr_rows(T (&a)[NRW][8], int nbk, T* s_x, T* s_sc, T* s_P, T* s_tau, T* s_beta,
+                                             T* Tg) {
+    constexpr int NB = QrCfg<T>::NB;
+    static_assert(NB == 32 && QrCfg<T>::PT == 256, "four waves of eight columns");
+    const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
+    T tc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) tc[c] = 0;
+    T tau_prev = 0;
+    if (tid < 64) qr_publish<T, NRW, 0>(a, 0, s_x, s_sc);
+    __syncthreads();
+    for (int jw = 0; jw < 4; ++jw) {
+        if (!qr_step<T, NRW, 0>(a, tc, tau_prev, jw, nbk, s_x, s_sc, s_P, s_tau, s_beta)) break;
+        if (!qr_step<T, NRW, 1>(a, tc, tau_prev, jw, nbk, s_x, s_sc, s_P, s_tau, s_beta)) break;
+        if (!qr_step<T, NRW, 2>(a, tc, tau_prev, jw, nbk, s_x, s_sc, s_P, s_tau, s_beta)) break;
+        if (!qr_step<T, NRW, 3>(a, tc, tau_prev, jw, nbk, s_x, s_sc, s_P, s_tau, s_beta)) break;
+        if (!qr_step<T, NRW, 4>(a, tc, tau_prev, jw, nbk, s_x, s_sc, s_P, s_tau, s_beta)) break;
+        if (!qr_step<T, NRW, 5>(a, tc, tau_prev, jw, nbk, s_x, s_sc, s_P, s_tau, s_beta)) break;
+        if (!qr_step<T, NRW, 6>(a, tc, tau_prev, jw, nbk, s_x, s_sc, s_P, s_tau, s_beta)) break;
+        if (!qr_step<T, NRW, 7>(a, tc, tau_prev, jw, nbk, s_x, s_sc, s_P, s_tau, s_beta)) break;
     }
     __syncthreads();
-    node_qr<T, NR>(p, nbk, s_col, s_row, s_red, s_Sm, s_T, s_tau, s_beta);
-    for (int e = tid; e < NB * NB; e += PT) {
-        const int i = e % NB, j = e / NB;
-        Tg[e] = (i <= j && j < nbk) ? s_T[i * (NB + 1) + j] : T(0);
-    }
-    __syncthreads();
-    // rows >= mt hold zeros; the tile has LDT >= G NR rows, so store them all
+    // last column of T
+    const int jl = nbk - 1;
+    if (wv == (jl >> 3)) {
+        const T t = qr_tcol(s_P + (jl & 1) * 128, jl, tau_prev);
 #pragma unroll
-    for (int i = 0; i < NR; ++i) s_tile[c * LDT + G * i + grp] = p[i];
+        for (int c = 0; c < 8; ++c) tc[c] = c == (jl & 7) ? t : tc[c];
+    }
+    if (l < NB) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int col = 8 * wv + c;
+            Tg[col * NB + l] = (l <= col && col < nbk) ? tc[c] : T(0);
+        }
+    }
+}
+
+// Factor the mt x nbk node staged column-major in s_tile (stride LDT) with
+// NRW register rows per lane (64 NRW >= mt): load, QR, write T (NB x NB,
+// column-major) to Tg, and put R/V back into s_tile.  The start of s_tile
+// serves as scratch while the node is in registers.
+template <typename T, int NRW>
+__device__ __forceinline__ void factor_tile_rows(T* s_tile, int mt, int nbk, T* s_x, T* s_sc, T* s_tau, T* s_beta,
+                                                 T* Tg) {
+    constexpr int LDT = QrCfg<T>::MT_MAX + 1;
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+    T a[NRW][8];
+#pragma unroll
+    for (int i = 0; i < NRW; ++i)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int r = l + 64 * i;
+            a[i][c] = r < mt ? s_tile[(8 * wv + c) * LDT + r] : T(0);
+        }
+    __syncthreads();
+    node_qr_rows<T, NRW>(a, nbk, s_x, s_sc, s_tile, s_tau, s_beta, Tg);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NRW; ++i)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) s_tile[(8 * wv + c) * LDT + l + 64 * i] = a[i][c];
     __syncthreads();
 }
 
 template <typename T>
-__device__ __forceinline__ void factor_node(T* s_tile, int mt, int nbk, T* s_col, T* s_row, T* s_tau, T* s_beta,
-                                            T* Tg) {
-    constexpr int NRL = QrCfg<T>::RPG, NRS = QrCfg<T>::RPG / 2, G = QrCfg<T>::PT / 32;
-    if (mt <= G * NRS) factor_tile<T, NRS>(s_tile, mt, nbk, s_col, s_row, s_tau, s_beta, Tg);
-    else factor_tile<T, NRL>(s_tile, mt, nbk, s_col, s_row, s_tau, s_beta, Tg);
+__device__ __forceinline__ void factor_node(T* s_tile, int mt, int nbk, T* s_x, T* s_sc, T* s_tau, T* s_beta, T* Tg) {
+    if (mt <= 64) factor_tile_rows<T, 1>(s_tile, mt, nbk, s_x, s_sc, s_tau, s_beta, Tg);
+    else if (mt <= 128) factor_tile_rows<T, 2>(s_tile, mt, nbk, s_x, s_sc, s_tau, s_beta, Tg);
+    else factor_tile_rows<T, 4>(s_tile, mt, nbk, s_x, s_sc, s_tau, s_beta, Tg);
 }
 
 template <typename T>
 __global__ __launch_bounds__(QrCfg<T>::PT) void k_panel(const QrDesc<T>* __restrict__ descs, int c0) {
     using C = QrCfg<T>;
-    constexpr int NB = C::NB, RPG = C::RPG, LDT = C::MT_MAX + 1, PT = C::PT, G = PT / 32;
+    constexpr int NB = C::NB, LDT = C::MT_MAX + 1, PT = C::PT;
     __shared__ T s_tile[LDT * NB];
-    __shared__ T s_col[2 * G * RPG];
-    __shared__ T s_row[2 * NB];
+    __shared__ T s_x[2 * C::MT_MAX];  // published column, two steps in flight
+    __shared__ T s_sc[4];
     __shared__ T s_tau[NB], s_beta[NB];
     __shared__ int s_last;
 
@@ -232,7 +359,7 @@ __global__ __launch_bounds__(QrCfg<T>::PT) void k_panel(const QrDesc<T>* __restr
         for (int col = 0; col < NB; ++col) s_tile[col * LDT + r] = v[col];
     }
     __syncthreads();
-    factor_node<T>(s_tile, mt, nbk, s_col, s_row, s_tau, s_beta, Tm + (size_t)node_index(g, 0, node, d.tm_leaves) * NB * NB);
+    factor_node<T>(s_tile, mt, nbk, s_x, s_sc, s_tau, s_beta, Tm + (size_t)node_index(g, 0, node, d.tm_leaves) * NB * NB);
     for (int r = tid; r < mt; r += PT) {
 #pragma unroll
         for (int col = 0; col < NB; ++col)
@@ -269,7 +396,7 @@ __global__ __launch_bounds__(QrCfg<T>::PT) void k_panel(const QrDesc<T>* __restr
             for (int col = 0; col < NB; ++col) s_tile[col * LDT + s] = v[col];
         }
         __syncthreads();
-        factor_node<T>(s_tile, mt, nbk, s_col, s_row, s_tau, s_beta,
+        factor_node<T>(s_tile, mt, nbk, s_x, s_sc, s_tau, s_beta,
                        Tm + (size_t)node_index(g, level, node, d.tm_leaves) * NB * NB);
         // explicit reflectors of this node, and its R into the top rows
         T* Vi = (par ? d.Vint[1] : d.Vint[0]) + (size_t)iidx * C::MT_MAX * NB;

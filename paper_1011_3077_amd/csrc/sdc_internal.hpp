@@ -19,18 +19,16 @@ namespace sdc {
 // columns and lives in one workgroup's registers.
 // ---------------------------------------------------------------------------
 template <typename T> struct QrCfg;
-// Panel workgroups have PT threads = (PT/32) row groups x 32 columns; RPG is
-// the register rows per thread for a full MT_MAX-row node.
-// Every node (F * NB <= MT_MAX rows) is factored by one workgroup of PT
-// threads (one wavefront per SIMD of a CU: PT/32 row groups of 32 columns)
-// and fits the trailing-update kernel's registers (256 rows x 16 columns per
-// wave).  The shape was chosen by measurement among 64-512 threads and
-// 128-256 row nodes.
+// Panel workgroups have PT = 256 threads (four wavefronts, one per SIMD of a
+// CU); a node (at most MT_MAX rows, NB columns) is factored in registers
+// with each wavefront owning NB/4 columns and each lane up to MT_MAX/64 rows.
+// Every node (F * NB <= MT_MAX rows) fits the trailing-update kernel's
+// registers (256 rows x 16 columns per wave).
 template <> struct QrCfg<double> {
-    static constexpr int NB = 32, MT_MAX = 256, H = 256, F = 8, PT = 256, RPG = MT_MAX / (PT / 32);
+    static constexpr int NB = 32, MT_MAX = 256, H = 256, F = 8, PT = 256;
 };
 template <> struct QrCfg<float> {
-    static constexpr int NB = 32, MT_MAX = 256, H = 256, F = 8, PT = 256, RPG = MT_MAX / (PT / 32);
+    static constexpr int NB = 32, MT_MAX = 256, H = 256, F = 8, PT = 256;
 };
 
 constexpr int kMaxLevels = 5;
