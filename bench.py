@@ -223,7 +223,7 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     log(f"[bench] timed {args.steps} steps: {dt:.3f} s")
-    stats = {k: h.profile_read(k) for k in (P.KERNEL_UPDATE, P.KERNEL_PANEL, P.KERNEL_GEMM)}
+    stats = {k: h.profile_read(k) for k in (P.KERNEL_UPDATE, P.KERNEL_PANEL, P.KERNEL_GEMM, P.KERNEL_LA)}
     h.profile_enable(False)
 
     # accuracy of the last step against the construction (outside the timed region)
@@ -240,7 +240,8 @@ def main():
     value = flops / dt / 1e9
     names = {P.KERNEL_UPDATE: "k_update (tree-level trailing update, MFMA f64)",
              P.KERNEL_PANEL: "k_panel (TSQR panel Householder)",
-             P.KERNEL_GEMM: "k_gemm (MFMA f64)"}
+             P.KERNEL_GEMM: "k_gemm (MFMA f64)",
+             P.KERNEL_LA: "k_la (look-ahead update of the next panel, MFMA f64)"}
     roof = None
     if not args.no_profile:
         dom = max(stats, key=lambda k: stats[k]["ms"])

@@ -184,6 +184,9 @@ typedef struct {
                             or (40/3 p + 16) m^3 (symmetric), the flop model of the
                             paper's cost analysis with LAPACK leading terms */
     double ms;
+    double e21_max;      /* largest e21_rel (sdc_info_t) among the accepted splits:
+                            the coupling blocks set to zero, relative to their
+                            subproblem in the 1-norm */
 } sdc_dc_info_t;
 
 /* Randomized spectral divide-and-conquer to blocks of order <= leaf_max
@@ -212,8 +215,9 @@ sdc_status_t sdc_eig_dc(sdc_handle_t h, int n, const double* A, int lda, const d
  * algorithmic work is recorded: kernel 0 = tree-level trailing update of the
  * QR (4 R nb ntr + 2 nb^2 ntr flops, 2 R ntr + R nb words for R rows, nb
  * panel columns, ntr trailing columns), 1 = panel factorization
- * (2 m nb^2 flops), 2 = GEMM (2 M N K flops).  Events serialize nothing but
- * add a few microseconds per launch. */
+ * (2 m nb^2 flops), 2 = GEMM (2 M N K flops), 3 = look-ahead update of the
+ * next panel's columns (the kernel-0 figures with ntr = nb).  Events
+ * serialize nothing but add a few microseconds per launch. */
 typedef struct {
     long long launches;
     double ms;          /* summed event time */
@@ -223,7 +227,7 @@ typedef struct {
 
 /* Enable (on != 0) or disable profiling; either way the totals are reset. */
 sdc_status_t sdc_profile_enable(sdc_handle_t h, int on);
-/* Totals of `kernel` (0, 1, 2 as above) since the last enable. */
+/* Totals of `kernel` (0 to 3 as above) since the last enable. */
 sdc_status_t sdc_profile_read(sdc_handle_t h, int kernel, sdc_kernel_stats_t* out);
 
 /* The Gaussian n x n matrix the library draws when opts->G is NULL:

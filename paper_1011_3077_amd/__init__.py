@@ -59,7 +59,7 @@ class Info(C.Structure):
 class DcInfo(C.Structure):
     _fields_ = [("n", C.c_int), ("nblocks", C.c_int), ("splits", C.c_int), ("accepted", C.c_int),
                 ("levels", C.c_int), ("unsplit", C.c_int), ("iters_total", C.c_int),
-                ("nominal_flops", C.c_double), ("ms", C.c_double)]
+                ("nominal_flops", C.c_double), ("ms", C.c_double), ("e21_max", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -72,7 +72,7 @@ class KernelStats(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
-KERNEL_UPDATE, KERNEL_PANEL, KERNEL_GEMM = 0, 1, 2
+KERNEL_UPDATE, KERNEL_PANEL, KERNEL_GEMM, KERNEL_LA = 0, 1, 2, 3
 
 
 class Request(C.Structure):

@@ -265,6 +265,7 @@ int run_eig_dc(Handle& h, int n, const double* A, int lda, const double* B, int 
                 continue;
             }
             ++st.accepted;
+            st.e21_max = std::max(st.e21_max, j.info.e21_rel);
             double* o = base + off[i];
             const double* Qr = j.Q;
             const double* Ql = symmetric ? j.Q : j.QL;

@@ -51,6 +51,7 @@ struct ProfScope {
 // Argument checks shared by the entry points.
 // Largest order the tree QR supports: 2n rows give at most 128 leaves.
 constexpr int kMaxN = 16384;
+static_assert(2 * kMaxN <= kMaxPanelRows, "QR tree counters sized for augmented matrices of order kMaxN");
 inline bool region_ok(const sdc_region_t& r) {
     if (r.kind == SDC_UNIT_DISK) return true;
     if (r.kind == SDC_DISK) return std::isfinite(r.center) && std::isfinite(r.radius) && r.radius > 0;

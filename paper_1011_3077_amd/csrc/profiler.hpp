@@ -9,7 +9,7 @@
 
 namespace sdc {
 
-enum ProfKernel { PROF_UPDATE = 0, PROF_PANEL = 1, PROF_GEMM = 2, PROF_POST = 3, PROF_NKERNELS = 4 };
+enum ProfKernel { PROF_UPDATE = 0, PROF_PANEL = 1, PROF_GEMM = 2, PROF_LA = 3, PROF_NKERNELS = 4 };
 
 struct Profiler {
     bool on = false;

@@ -444,14 +444,11 @@ __global__ __launch_bounds__(256, 2) void k_update(const QrDesc<T>* __restrict__
     const QrDesc<T> d = descs[blockIdx.z];
     if (!d.active || c0 >= d.nf) return;
     const int nbk = min(NB, d.nf - c0);
-    // column range: all trailing columns (mode 0), the next panel's columns
-    // (mode 1, the look-ahead part) or the columns after them (mode 2)
-    int cb = c0 + nbk, ce = d.ncols;
-    if (mode != 0) {
-        const int nxt = max(0, min(NB, d.nf - cb));
-        if (mode == 1) ce = cb + nxt;
-        else cb += nxt;
-    }
+    // column range: all trailing columns (mode 0) or the columns after the
+    // next panel's (mode 2; the next panel's own columns are k_la's)
+    int cb = c0 + nbk;
+    const int ce = d.ncols;
+    if (mode != 0) cb += max(0, min(NB, d.nf - cb));
     const int col0 = cb + blockIdx.y * 64;
     if (col0 >= ce) return;
     const int par = (c0 / NB) & 1;
@@ -619,6 +616,248 @@ __global__ __launch_bounds__(256, 2) void k_update(const QrDesc<T>* __restrict__
     }
 }
 
+// Look-ahead update: the transpose of panel c0's orthogonal factor (every
+// tree level) applied to the next panel's columns, in one launch.  A
+// workgroup owns one node and one 16-column group of the next panel; its four
+// waves split the node's rows (row blocks [RBW w, RBW w + RBW) of wave w),
+// each forms its share of W = V^T C, the shares are summed through LDS, and
+// each wave applies C <- C - V (T^T W) to its rows.  The last workgroup to
+// finish among a node's children (counted per column group) goes on to the
+// parent, as in the panel factorization, so the tree levels need no further
+// launches.  The MFMA layouts are those of k_update.
+template <typename T>
+__global__ __launch_bounds__(256) void k_la(const QrDesc<T>* __restrict__ descs, int c0) {
+    using C = QrCfg<T>;
+    using M = Mfma<T>;
+    typedef typename M::v4 v4;
+    constexpr int NB = C::NB, VS = NB + 1, XS = 17, RBW = C::MT_MAX / 64;
+    constexpr int kCounterStride = kMaxInternal / 2;  // counters of column group 1
+    __shared__ T s_V[C::MT_MAX * VS];
+    __shared__ T s_X[4 * 16 * XS];  // per-wave transpose tiles, then the W / Y exchange
+    __shared__ int s_rb[C::F];
+    __shared__ int s_last;
+    static_assert(4 * 16 * XS >= 1024, "exchange space for two 32 x 16 partial sums per lane set");
+
+    const QrDesc<T> d = descs[blockIdx.z];
+    if (!d.active || c0 >= d.nf) return;
+    const int nbk = min(NB, d.nf - c0);
+    const int cb = c0 + nbk;
+    const int nxt = min(NB, d.nf - cb);
+    const int cgrp = blockIdx.y;
+    if (nxt <= 16 * cgrp) return;  // no columns in this group (for every node alike)
+    const int cbase = cb + 16 * cgrp, ce = cb + nxt;
+    const int mp = d.m - c0;
+    const auto g = tree_geom<T>(mp);
+    int node = blockIdx.x;
+    if (node >= g.L(0)) return;
+    const int par = (c0 / NB) & 1;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, gq = lane >> 4, ln = lane & 15;
+    const size_t ld = (size_t)d.ld;
+    T* W = d.W;
+    int level = 0;
+    const int lo = c0 + leaf_lo(node, mp, g.L(0));
+    int mt = c0 + leaf_lo(node + 1, mp, g.L(0)) - lo;
+    for (;;) {
+        const int rows_pad = ((mt + 15) >> 4) << 4;
+        const int rbe = rows_pad >> 4;
+        // explicit reflectors of the node (unit diagonal, zero above it and
+        // beyond the node), one row per thread
+        if (level == 0) {
+            for (int s = tid; s < rows_pad; s += 256) {
+                T v[NB];
+#pragma unroll
+                for (int col = 0; col < NB; ++col)
+                    v[col] = (s < mt && col < nbk)
+                                 ? (s > col ? W[(size_t)(c0 + col) * ld + lo + s] : (s == col ? T(1) : T(0)))
+                                 : T(0);
+#pragma unroll
+                for (int col = 0; col < NB; ++col) s_V[s * VS + col] = v[col];
+            }
+        } else {
+            const T* Vi = (par ? d.Vint[1] : d.Vint[0]) + (size_t)internal_index(g, level, node) * C::MT_MAX * NB;
+            for (int s = tid; s < rows_pad; s += 256) {
+                T v[NB];
+#pragma unroll
+                for (int col = 0; col < NB; ++col) v[col] = (s < mt && col < nbk) ? Vi[(size_t)col * C::MT_MAX + s] : T(0);
+#pragma unroll
+                for (int col = 0; col < NB; ++col) s_V[s * VS + col] = v[col];
+            }
+        }
+        const T* Tg = (par ? d.Tm[1] : d.Tm[0]) + (size_t)node_index(g, level, node, d.tm_leaves) * NB * NB;
+        T ta[2][2][4];
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = kb * 16 + M::row(gq, j);
+                ta[0][kb][j] = Tg[(size_t)ln * NB + k];
+                ta[1][kb][j] = Tg[(size_t)(16 + ln) * NB + k];
+            }
+        // this wave's rows of C^T (layout of k_update)
+        v4 cr[RBW];
+#pragma unroll
+        for (int i = 0; i < RBW; ++i) {
+            const int rb = wave * RBW + i;
+            cr[i] = v4{0, 0, 0, 0};
+            if (rb < rbe) {
+                const int sr = rb * 16 + ln;
+                const int wr = sr >= mt ? -1
+                               : level == 0 ? lo + sr
+                               : ((sr & (NB - 1)) < nbk ? s_rb[sr / NB] + (sr & (NB - 1)) : -1);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int c = cbase + M::row(gq, v);
+                    if (wr >= 0 && c < ce) cr[i][v] = W[(size_t)c * ld + wr];
+                }
+            }
+        }
+        __syncthreads();  // s_V complete
+        // this wave's share of W = V^T C (rows: V's columns; two accumulator
+        // chains per half)
+        T* X = s_X + wave * 16 * XS;
+        v4 w0 = v4{0, 0, 0, 0}, w1 = v4{0, 0, 0, 0}, w2 = v4{0, 0, 0, 0}, w3 = v4{0, 0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < RBW; ++i) {
+            const int rb = wave * RBW + i;
+            if (rb < rbe) {
+                T ob[4], ova[4], ovb[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) X[ln * XS + M::row(gq, v)] = cr[i][v];
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    ob[kk] = X[(4 * kk + gq) * XS + ln];
+                    const T* vr = s_V + (rb * 16 + 4 * kk + gq) * VS;
+                    ova[kk] = vr[ln];
+                    ovb[kk] = vr[16 + ln];
+                }
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    if (i & 1) {
+                        w2 = M::mma(ova[kk], ob[kk], w2);
+                        w3 = M::mma(ovb[kk], ob[kk], w3);
+                    } else {
+                        w0 = M::mma(ova[kk], ob[kk], w0);
+                        w1 = M::mma(ovb[kk], ob[kk], w1);
+                    }
+                }
+            }
+        }
+        w0 += w2;
+        w1 += w3;
+        // sum of the four shares, (P0 + P2) + (P1 + P3), then Y = T^T W by
+        // wave 0, handed to every wave
+        T* E = s_X;
+        __syncthreads();  // transpose tiles free
+        if (wave >= 2) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                E[(wave - 2) * 512 + lane * 8 + v] = w0[v];
+                E[(wave - 2) * 512 + lane * 8 + 4 + v] = w1[v];
+            }
+        }
+        __syncthreads();
+        if (wave < 2) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                w0[v] += E[wave * 512 + lane * 8 + v];
+                w1[v] += E[wave * 512 + lane * 8 + 4 + v];
+            }
+        }
+        __syncthreads();
+        if (wave == 1) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                E[lane * 8 + v] = w0[v];
+                E[lane * 8 + 4 + v] = w1[v];
+            }
+        }
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                w0[v] += E[lane * 8 + v];
+                w1[v] += E[lane * 8 + 4 + v];
+            }
+            v4 y0 = v4{0, 0, 0, 0}, y1 = v4{0, 0, 0, 0};
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const T bw = kb ? w1[j] : w0[j];
+                    y0 = M::mma(ta[0][kb][j], bw, y0);
+                    y1 = M::mma(ta[1][kb][j], bw, y1);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                E[512 + lane * 8 + v] = y0[v];
+                E[512 + lane * 8 + 4 + v] = y1[v];
+            }
+        }
+        __syncthreads();
+        T yv[2][4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            yv[0][v] = E[512 + lane * 8 + v];
+            yv[1][v] = E[512 + lane * 8 + 4 + v];
+        }
+        // C^T -= Y^T V^T on this wave's rows
+#pragma unroll
+        for (int pb = 0; pb < 2; ++pb) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const T a = -yv[pb][j];
+                const int kcol = pb * 16 + M::row(gq, j);
+                T vb[RBW];
+#pragma unroll
+                for (int i = 0; i < RBW; ++i) {
+                    const int rb = wave * RBW + i;
+                    vb[i] = rb < rbe ? s_V[(rb * 16 + ln) * VS + kcol] : T(0);
+                }
+#pragma unroll
+                for (int i = 0; i < RBW; ++i)
+                    if (wave * RBW + i < rbe) cr[i] = M::mma(a, vb[i], cr[i]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < RBW; ++i) {
+            const int rb = wave * RBW + i;
+            if (rb < rbe) {
+                const int sr = rb * 16 + ln;
+                const int wr = sr >= mt ? -1
+                               : level == 0 ? lo + sr
+                               : ((sr & (NB - 1)) < nbk ? s_rb[sr / NB] + (sr & (NB - 1)) : -1);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int c = cbase + M::row(gq, v);
+                    if (wr >= 0 && c < ce) W[(size_t)c * ld + wr] = cr[i][v];
+                }
+            }
+        }
+        // climb: the last child to arrive updates the parent's rows
+        if (level + 1 >= g.levels) return;
+        __threadfence();
+        __syncthreads();
+        const int parent = node / C::F;
+        const int iidx = internal_index(g, level + 1, parent);
+        const int nch = min(C::F, g.L(level) - parent * C::F);
+        if (tid == 0) {
+            unsigned* cnt = d.counters + cgrp * kCounterStride + iidx;
+            const unsigned old = atomicAdd(cnt, 1u);
+            s_last = (old == (unsigned)(nch - 1));
+            if (s_last) *cnt = 0u;
+        }
+        __syncthreads();
+        if (!s_last) return;
+        __threadfence();
+        node = parent;
+        ++level;
+        mt = nch * NB;
+        if (tid < nch) s_rb[tid] = c0 + leaf_lo((node * C::F + tid) * g.pw(level - 1), mp, g.L(0));
+        __syncthreads();
+    }
+}
+
 template <typename T>
 static void launch_update(int rows, dim3 grid, hipStream_t s, const QrDesc<T>* d, int c0, int lev, int mode);
 template <>
@@ -640,8 +879,11 @@ void launch_update<float>(int rows, dim3 grid, hipStream_t s, const QrDesc<float
 // panel factorization, then the tree levels of the trailing update.  With
 // `la` (look-ahead, depth 1) panel k+1 is factored while the update of the
 // columns after it runs concurrently:
-//   crit: P(k), [wait rest(k-1)], LA(k) = update of panel k+1's columns, P(k+1) ...
-//   rest: [wait P(k)], REST(k) = update of every column after panel k+1
+//   crit: P(k), [wait rest(k-1)], LA(k) = update of panel k+1's columns
+//         (k_la, every tree level in one launch), P(k+1) ...
+//   rest: [wait LA(k)], REST(k) = update of every column after panel k+1
+// so P(k+1) runs beside REST(k) and LA(k) runs alone (it is short, and a
+// small grid queued behind a large one is dispatched only after it).
 // LA(k) must follow REST(k-1) (both touch panel k+1's columns); P(k+1)
 // writes the other parity's T / reflector buffers while REST(k) reads
 // panel k's.  crit starts after the work already on s, and s waits for both
@@ -721,10 +963,21 @@ void qr_aug_batch(const QrDesc<T>* d_descs, const QrDesc<T>* h, int count, hipSt
             run_levels(sc, 0, (maxtrail + 63) / 64, 1.0);
             continue;
         }
-        (void)hipEventRecord(la->evP, sc);
         if (rest_pending) (void)hipStreamWaitEvent(sc, la->evR, 0);
         const double f_la = maxtrail > 0 ? (double)C::NB / maxtrail : 0.0;
-        run_levels(sc, 1, 1, f_la);
+        {
+            double lf = 0, lb = 0;
+            for (int lev = 0; lev < maxlev; ++lev) {
+                lf += uf[lev] * f_la;
+                lb += ub[lev] * f_la;
+            }
+            const int lid = prof ? prof->begin(sc) : -1;
+            hipLaunchKernelGGL(k_la<T>, dim3(maxL[0], 2, count), dim3(256), 0, sc, d_descs, c0);
+            if (prof) prof->end(lid, sc, PROF_LA, lf, lb);
+        }
+        // REST(k) is released after LA(k): a short LA launched while the
+        // large REST grid is being dispatched would wait for all of it
+        (void)hipEventRecord(la->evP, sc);
         (void)hipStreamWaitEvent(la->rest, la->evP, 0);
         // the next panel may be narrower than NB, so the rest can start
         // anywhere in [c0 + nbk, c0 + nbk + NB]: size the grid for all trailing

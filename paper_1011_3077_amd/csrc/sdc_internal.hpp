@@ -32,7 +32,11 @@ template <> struct QrCfg<float> {
 };
 
 constexpr int kMaxLevels = 5;
-constexpr int kMaxInternal = 96;  // internal tree nodes per panel and problem (n <= 16384)
+// Tree arrival counters per problem: the panel factorization counts arrivals
+// at internal nodes in the first half, the look-ahead update (two column
+// groups) in [0, kMaxInternal / 2) and [kMaxInternal / 2, kMaxInternal).
+constexpr int kMaxInternal = 96;
+constexpr int kMaxPanelRows = 2 * 16384;  // augmented matrices of order <= 16384
 
 // Tree shape of a panel with mp rows: L0 leaves, levels levels, and
 // L(l) = ceil(L0 / F^l) nodes at level l.  Computed arithmetically (no
@@ -73,6 +77,19 @@ __host__ __device__ inline int leaf_lo(int j, int mp, int L0) {
     const long long blocks = (mp + 15) / 16;
     return (int)((j * blocks) / L0) * 16;
 }
+
+// Internal nodes of the tallest supported panel (checked against the counters).
+template <typename T> constexpr int max_internal_nodes() {
+    using C = QrCfg<T>;
+    int n = ((kMaxPanelRows + 15) / 16 + C::H / 16 - 1) / (C::H / 16), total = 0;
+    while (n > 1) {
+        n = (n + C::F - 1) / C::F;
+        total += n;
+    }
+    return total;
+}
+static_assert(max_internal_nodes<double>() <= kMaxInternal / 2 && max_internal_nodes<float>() <= kMaxInternal / 2,
+              "two column groups of look-ahead counters per internal node");
 
 // Index of an internal node (level >= 1) in per-problem arrays.
 template <typename T>

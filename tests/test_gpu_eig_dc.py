@@ -47,6 +47,26 @@ def block_spectrum(t, s, starts):
     return np.concatenate(ev)
 
 
+def check_residual(d, a, starts, info, split_tol=1e-10):
+    """d = Q_L^T A Q_R - T.  On and above the diagonal blocks T is the exact
+    transformation, so d is rounding there (64 n eps |A|_2).  Below them d is
+    what the accepted splits set to zero: each level's part is block diagonal
+    with blocks E of 1-norm e21 |A_i|_1 <= e21_max sqrt(n) |A|_2 (A_i a
+    diagonal block of an orthogonal transformation of A), so the 1-norm of the
+    lower part is at most levels sqrt(n) e21_max |A|_2."""
+    n = a.shape[0]
+    blk = np.zeros(n, dtype=int)
+    for i, (a0, a1) in enumerate(zip(starts[:-1], starts[1:])):
+        blk[a0:a1] = i
+    low = blk[:, None] > blk[None, :]
+    na2 = np.linalg.norm(a, 2)
+    rnd = 64 * n * np.finfo(float).eps * na2
+    assert 0 <= info["e21_max"] <= split_tol
+    assert np.linalg.norm(np.where(low, 0.0, d), 2) <= rnd
+    bound = info["levels"] * np.sqrt(n) * info["e21_max"] * na2 + rnd
+    assert np.abs(np.where(low, d, 0.0)).sum(axis=0).max() <= bound
+
+
 def check_pencil(res, a, b, lam, leaf, rel_tol):
     st, t, s, ql, qr, starts, info = res
     t, s, ql, qr = (x.cpu().numpy() for x in (t, s, ql, qr))
@@ -59,8 +79,8 @@ def check_pencil(res, a, b, lam, leaf, rel_tol):
     eye = np.eye(n)
     assert np.abs(ql.T @ ql - eye).max() <= 1e-12 * np.sqrt(n) * 10
     assert np.abs(qr.T @ qr - eye).max() <= 1e-12 * np.sqrt(n) * 10
-    assert np.linalg.norm(ql.T @ a @ qr - t, 2) <= 1e-10 * np.linalg.norm(a, 2)
-    assert np.linalg.norm(ql.T @ b @ qr - s, 2) <= 1e-10 * np.linalg.norm(b, 2)
+    check_residual(ql.T @ a @ qr - t, a, starts, info)
+    check_residual(ql.T @ b @ qr - s, b, starts, info)
     got = np.sort_complex(block_spectrum(t, s, starts))
     want = np.sort_complex(lam.astype(complex))
     err = np.max(np.abs(got - want) / np.abs(want))
