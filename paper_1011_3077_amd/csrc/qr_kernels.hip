@@ -417,6 +417,32 @@ __global__ __launch_bounds__(QrCfg<T>::PT) void k_panel(const QrDesc<T>* __restr
     if (tid < nbk) d.diag[c0 + tid] = s_beta[tid];
 }
 
+// Raw buffer access (gfx9 resource word 3 for untyped, unswizzled data):
+// a load at a byte offset outside [0, bytes) returns zero and a store there
+// is dropped, so padding rows and columns need no branches, and offsets are
+// 32 bits.  The whole offset is passed as the per-lane offset (the range
+// check applies to it; the scalar offset is left at zero).  kOob is an
+// offset past every range used here, with room for the largest column step
+// added to it (all ranges and steps are below 2^31 bytes).
+constexpr unsigned kOob = 0x80000000u;
+template <typename T> struct RawBuf {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ RawBuf(const T* base, unsigned bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, (int)bytes, 0x00020000)) {}
+    __device__ T load(unsigned off) const {
+        if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+        else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    }
+    __device__ void store(T x, unsigned off) const {
+        if constexpr (sizeof(T) == 8) {
+            typedef unsigned u2 __attribute__((ext_vector_type(2)));
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, off, 0, 0);
+        } else {
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, off, 0, 0);
+        }
+    }
+};
+
 // Apply the transpose of one tree level's block reflectors to a 64-column
 // tile of the trailing matrix: C <- C - V (T^T (V^T C)) for the node's rows.
 //
@@ -469,65 +495,83 @@ __global__ __launch_bounds__(256, 2) void k_update(const QrDesc<T>* __restrict__
         const int nch = min(C::F, g.L(level - 1) - node * C::F);
         mt = nch * NB;
         if (tid < nch) s_rb[tid] = c0 + leaf_lo((node * C::F + tid) * g.pw(level - 1), mp, g.L(0));
+        __syncthreads();
     }
     const int rows_pad = ((mt + 15) >> 4) << 4;
-    // reflectors: each thread moves whole rows (independent loads in flight)
-    if (level == 0) {
-        for (int s = tid; s < rows_pad; s += 256) {
-            T v[NB];
-#pragma unroll
-            for (int col = 0; col < NB; ++col)
-                v[col] = (s < mt && col < nbk) ? (s > col ? W[(size_t)(c0 + col) * ld + lo + s] : (s == col ? T(1) : T(0)))
-                                               : T(0);
-#pragma unroll
-            for (int col = 0; col < NB; ++col) s_V[s * VS + col] = v[col];
-        }
-    } else {
-        const T* Vi = (par ? d.Vint[1] : d.Vint[0]) + (size_t)internal_index(g, level, node) * C::MT_MAX * NB;
-        for (int s = tid; s < rows_pad; s += 256) {
-            T v[NB];
-#pragma unroll
-            for (int col = 0; col < NB; ++col) v[col] = (s < mt && col < nbk) ? Vi[(size_t)col * C::MT_MAX + s] : T(0);
-#pragma unroll
-            for (int col = 0; col < NB; ++col) s_V[s * VS + col] = v[col];
-        }
-    }
-    __syncthreads();
-
     const int wave = tid >> 6, lane = tid & 63, gq = lane >> 4, ln = lane & 15;
     const int cbase = col0 + wave * 16;
     const int rbe = rows_pad >> 4;
-    // T factor of this node, as the A operand of Y = T^T W:
-    // lane (gq, ln) needs T[k][ln] for k = kb * 16 + row(gq, j)
-    const T* Tg = (par ? d.Tm[1] : d.Tm[0]) + (size_t)node_index(g, level, node, d.tm_leaves) * NB * NB;
+    // Global traffic goes through raw buffers (reads outside a range give
+    // zero, writes there are dropped), so it has no branches: the compiler
+    // counts the loads exactly and each consumer waits only for its own
+    // data.  The C slice streams in while the reflectors go to LDS and while
+    // the first row blocks are multiplied.
+    // Reflectors: thread s holds row s of the node (explicit: unit diagonal,
+    // zero above it and beyond the node).
+    static_assert(C::MT_MAX <= 256, "one reflector row per thread");
+    const int s = tid;
+    T v[NB];
+    if (level == 0) {
+        const RawBuf<T> bv(W + (size_t)c0 * ld, (unsigned)(nbk * ld * sizeof(T)));
+        const unsigned vo = s < mt ? (unsigned)((lo + s) * sizeof(T)) : kOob;
+#pragma unroll
+        for (int col = 0; col < NB; ++col) {
+            const T x = bv.load(vo + (unsigned)(col * ld * sizeof(T)));
+            v[col] = s > col ? x : ((s == col && s < mt && col < nbk) ? T(1) : T(0));
+        }
+    } else {
+        const T* Vi = (par ? d.Vint[1] : d.Vint[0]) + (size_t)internal_index(g, level, node) * C::MT_MAX * NB;
+        const RawBuf<T> bv(Vi, (unsigned)(nbk * C::MT_MAX * sizeof(T)));
+        const unsigned vo = s < mt ? (unsigned)(s * sizeof(T)) : kOob;
+#pragma unroll
+        for (int col = 0; col < NB; ++col) v[col] = bv.load(vo + (unsigned)(col * C::MT_MAX * sizeof(T)));
+    }
+    // C^T slice: row block rb, lane (gq, ln), register q <-> node row 16 rb + ln,
+    // column cbase + row(gq, q) (row(g, q) = row(g, 0) + row(0, q)); the
+    // wave's buffer covers its valid columns only.  The first half of the
+    // row blocks is requested before the reflectors go to LDS, the second
+    // half after (registers: the reflector row and half the slice).
+    const RawBuf<T> bc(W + (size_t)cbase * ld, (unsigned)(max(0, min(16, ce - cbase)) * ld * sizeof(T)));
+    auto c_off = [&](int rb) -> unsigned {
+        const int sr = rb * 16 + ln;
+        const int wr = (rb >= rbe || sr >= mt) ? -1
+                       : level == 0 ? lo + sr
+                       : ((sr & (NB - 1)) < nbk ? s_rb[sr / NB] + (sr & (NB - 1)) : -1);
+        return wr >= 0 ? (unsigned)((M::row(gq, 0) * ld + wr) * sizeof(T)) : kOob;
+    };
+    v4 cr[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB / 2; ++rb) {
+        const unsigned o = c_off(rb);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cr[rb][q] = bc.load(o + (unsigned)(M::row(0, q) * ld * sizeof(T)));
+    }
+    // every row of s_V (zero beyond the node), without a branch
+#pragma unroll
+    for (int col = 0; col < NB; ++col) s_V[s * VS + col] = v[col];
+    __syncthreads();
+#pragma unroll
+    for (int rb = RB / 2; rb < RB; ++rb) {
+        const unsigned o = c_off(rb);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cr[rb][q] = bc.load(o + (unsigned)(M::row(0, q) * ld * sizeof(T)));
+    }
+    // T factor of this node, as the A operand of Y = T^T W: lane (gq, ln)
+    // needs T[k][ln] for k = kb * 16 + row(gq, j); through a buffer (a
+    // generic-pointer load would be a flat access, which the wait counters
+    // cannot tell apart from the LDS traffic).
+    const RawBuf<T> bt((par ? d.Tm[1] : d.Tm[0]) + (size_t)node_index(g, level, node, d.tm_leaves) * NB * NB,
+                       (unsigned)(NB * NB * sizeof(T)));
     T ta[2][2][4];
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int k = kb * 16 + M::row(gq, j);
-            ta[0][kb][j] = Tg[(size_t)ln * NB + k];
-            ta[1][kb][j] = Tg[(size_t)(16 + ln) * NB + k];
+            ta[0][kb][j] = bt.load((unsigned)((ln * NB + k) * sizeof(T)));
+            ta[1][kb][j] = bt.load((unsigned)(((16 + ln) * NB + k) * sizeof(T)));
         }
 
-    // C^T slice: row block rb, lane (gq, ln), register v <-> node row 16 rb + ln,
-    // column cbase + row(gq, v); wr = the row in W (-1: padding)
-    v4 cr[RB];
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-        cr[rb] = v4{0, 0, 0, 0};
-        if (rb < rbe) {
-            const int sr = rb * 16 + ln;
-            const int wr = sr >= mt ? -1
-                           : level == 0 ? lo + sr
-                           : ((sr & (NB - 1)) < nbk ? s_rb[sr / NB] + (sr & (NB - 1)) : -1);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int c = cbase + M::row(gq, v);
-                if (wr >= 0 && c < ce) cr[rb][v] = W[(size_t)c * ld + wr];
-            }
-        }
-    }
     // W = V^T C (NB x 16): per row block, C goes through the wave's LDS tile
     // into the B-operand layout.  Software pipelined: the LDS traffic of row
     // block rb + 1 (tile write, operand reads) is issued before the MFMAs of
@@ -602,17 +646,9 @@ __global__ __launch_bounds__(256, 2) void k_update(const QrDesc<T>* __restrict__
     }
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
-        if (rb < rbe) {
-            const int sr = rb * 16 + ln;
-            const int wr = sr >= mt ? -1
-                           : level == 0 ? lo + sr
-                           : ((sr & (NB - 1)) < nbk ? s_rb[sr / NB] + (sr & (NB - 1)) : -1);
+        const unsigned o = c_off(rb);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int c = cbase + M::row(gq, v);
-                if (wr >= 0 && c < ce) W[(size_t)c * ld + wr] = cr[rb][v];
-            }
-        }
+        for (int q = 0; q < 4; ++q) bc.store(cr[rb][q], o + (unsigned)(M::row(0, q) * ld * sizeof(T)));
     }
 }
 
