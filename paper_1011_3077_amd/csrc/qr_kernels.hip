@@ -23,6 +23,32 @@
 
 namespace sdc {
 
+// Raw buffer access (gfx9 resource word 3 for untyped, unswizzled data):
+// a load at a byte offset outside [0, bytes) returns zero and a store there
+// is dropped, so padding rows and columns need no branches, and offsets are
+// 32 bits.  The whole offset is passed as the per-lane offset (the range
+// check applies to it; the scalar offset is left at zero).  kOob is an
+// offset past every range used here, with room for the largest column step
+// added to it (all ranges and steps are below 2^31 bytes).
+constexpr unsigned kOob = 0x80000000u;
+template <typename T> struct RawBuf {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ RawBuf(const T* base, unsigned bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, (int)bytes, 0x00020000)) {}
+    __device__ T load(unsigned off) const {
+        if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+        else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    }
+    __device__ void store(T x, unsigned off) const {
+        if constexpr (sizeof(T) == 8) {
+            typedef unsigned u2 __attribute__((ext_vector_type(2)));
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, off, 0, 0);
+        } else {
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, off, 0, 0);
+        }
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Cross-lane moves inside one wavefront (T = float or double).
 // ---------------------------------------------------------------------------
@@ -342,28 +368,32 @@ __global__ __launch_bounds__(QrCfg<T>::PT) void k_panel(const QrDesc<T>* __restr
     const int par = (c0 / NB) & 1;
     T* const Tm = (par ? d.Tm[1] : d.Tm[0]);
     const int tid = threadIdx.x;
-    const size_t ld = (size_t)d.ld;
+    const int ld = d.ld;
     T* W = d.W;
+    static_assert(C::MT_MAX <= PT, "one node row per thread");
+    // the panel's columns as a raw buffer (reads outside it give zero,
+    // writes there are dropped: no branches for the columns >= nbk or the
+    // rows beyond a node)
+    const RawBuf<T> bw(W + (size_t)c0 * ld, (unsigned)(nbk * ld * sizeof(T)));
 
     // ---- leaf: rows [row0, row0 + mt) of the panel columns
-    // Each thread moves whole rows (all NB columns), so its global accesses
-    // are independent and in flight together; across threads every column
-    // access is a contiguous run of rows.
+    // Each thread moves one whole row (all NB columns), so its global
+    // accesses are independent and in flight together; across threads every
+    // column access is a contiguous run of rows.
     const int row0 = c0 + leaf_lo(node, mp, g.L(0));
     int mt = c0 + leaf_lo(node + 1, mp, g.L(0)) - row0;
-    for (int r = tid; r < mt; r += PT) {
+    {
+        const unsigned vo = tid < mt ? (unsigned)((row0 + tid) * sizeof(T)) : kOob;
         T v[NB];
 #pragma unroll
-        for (int col = 0; col < NB; ++col) v[col] = col < nbk ? W[(size_t)(c0 + col) * ld + row0 + r] : T(0);
+        for (int col = 0; col < NB; ++col) v[col] = bw.load(vo + (unsigned)(col * ld * sizeof(T)));
 #pragma unroll
-        for (int col = 0; col < NB; ++col) s_tile[col * LDT + r] = v[col];
-    }
-    __syncthreads();
-    factor_node<T>(s_tile, mt, nbk, s_x, s_sc, s_tau, s_beta, Tm + (size_t)node_index(g, 0, node, d.tm_leaves) * NB * NB);
-    for (int r = tid; r < mt; r += PT) {
+        for (int col = 0; col < NB; ++col) s_tile[col * LDT + tid] = v[col];
+        __syncthreads();
+        factor_node<T>(s_tile, mt, nbk, s_x, s_sc, s_tau, s_beta,
+                       Tm + (size_t)node_index(g, 0, node, d.tm_leaves) * NB * NB);
 #pragma unroll
-        for (int col = 0; col < NB; ++col)
-            if (col < nbk) W[(size_t)(c0 + col) * ld + row0 + r] = s_tile[col * LDT + r];
+        for (int col = 0; col < NB; ++col) bw.store(s_tile[col * LDT + tid], vo + (unsigned)(col * ld * sizeof(T)));
     }
 
     // ---- climb the tree: the last child to arrive factors the parent
@@ -385,13 +415,16 @@ __global__ __launch_bounds__(QrCfg<T>::PT) void k_panel(const QrDesc<T>* __restr
         mt = nch * NB;
         // stacked upper-triangular R factors of the children (row s of the
         // stack is row s % NB of child s / NB)
-        for (int s = tid; s < mt; s += PT) {
-            const int t = s / NB, r = s % NB;
-            const int rb = c0 + leaf_lo((node * C::F + t) * g.pw(level - 1), mp, g.L(0));
+        {
+            const int s = tid, t = s / NB, r = s % NB;
+            const int rb = s < mt ? c0 + leaf_lo((node * C::F + t) * g.pw(level - 1), mp, g.L(0)) : 0;
+            const unsigned vo = s < mt ? (unsigned)((rb + r) * sizeof(T)) : kOob;
             T v[NB];
 #pragma unroll
-            for (int col = 0; col < NB; ++col)
-                v[col] = (col < nbk && r <= col) ? W[(size_t)(c0 + col) * ld + rb + r] : T(0);
+            for (int col = 0; col < NB; ++col) {
+                const T x = bw.load(vo + (unsigned)(col * ld * sizeof(T)));
+                v[col] = r <= col ? x : T(0);
+            }
 #pragma unroll
             for (int col = 0; col < NB; ++col) s_tile[col * LDT + s] = v[col];
         }
@@ -399,49 +432,23 @@ __global__ __launch_bounds__(QrCfg<T>::PT) void k_panel(const QrDesc<T>* __restr
         factor_node<T>(s_tile, mt, nbk, s_x, s_sc, s_tau, s_beta,
                        Tm + (size_t)node_index(g, level, node, d.tm_leaves) * NB * NB);
         // explicit reflectors of this node, and its R into the top rows
-        T* Vi = (par ? d.Vint[1] : d.Vint[0]) + (size_t)iidx * C::MT_MAX * NB;
+        const RawBuf<T> bvi((par ? d.Vint[1] : d.Vint[0]) + (size_t)iidx * C::MT_MAX * NB,
+                            (unsigned)(C::MT_MAX * NB * sizeof(T)));
         const int rbase = c0 + leaf_lo(node * g.pw(level), mp, g.L(0));
-        for (int s = tid; s < C::MT_MAX; s += PT) {
+        {
+            const int s = tid;
 #pragma unroll
             for (int col = 0; col < NB; ++col) {
-                T v = 0;
-                if (s < mt && col < nbk) v = s > col ? s_tile[col * LDT + s] : (s == col ? T(1) : T(0));
-                Vi[(size_t)col * C::MT_MAX + s] = v;
+                const T x = s_tile[col * LDT + s];
+                const T v = (s < mt && col < nbk) ? (s > col ? x : (s == col ? T(1) : T(0))) : T(0);
+                bvi.store(v, (unsigned)((col * C::MT_MAX + s) * sizeof(T)));
+                // R: the upper triangle into the first child's top rows
+                if (s < NB) bw.store(x, s <= col ? (unsigned)(((size_t)col * ld + rbase + s) * sizeof(T)) : kOob);
             }
-        }
-        for (int e = tid; e < nbk * nbk; e += PT) {
-            const int col = e / nbk, s = e % nbk;
-            if (s <= col) W[(size_t)(c0 + col) * ld + rbase + s] = s_tile[col * LDT + s];
         }
     }
     if (tid < nbk) d.diag[c0 + tid] = s_beta[tid];
 }
-
-// Raw buffer access (gfx9 resource word 3 for untyped, unswizzled data):
-// a load at a byte offset outside [0, bytes) returns zero and a store there
-// is dropped, so padding rows and columns need no branches, and offsets are
-// 32 bits.  The whole offset is passed as the per-lane offset (the range
-// check applies to it; the scalar offset is left at zero).  kOob is an
-// offset past every range used here, with room for the largest column step
-// added to it (all ranges and steps are below 2^31 bytes).
-constexpr unsigned kOob = 0x80000000u;
-template <typename T> struct RawBuf {
-    __amdgpu_buffer_rsrc_t r;
-    __device__ RawBuf(const T* base, unsigned bytes)
-        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, (int)bytes, 0x00020000)) {}
-    __device__ T load(unsigned off) const {
-        if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-        else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-    }
-    __device__ void store(T x, unsigned off) const {
-        if constexpr (sizeof(T) == 8) {
-            typedef unsigned u2 __attribute__((ext_vector_type(2)));
-            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, off, 0, 0);
-        } else {
-            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, off, 0, 0);
-        }
-    }
-};
 
 // Apply the transpose of one tree level's block reflectors to a 64-column
 // tile of the trailing matrix: C <- C - V (T^T (V^T C)) for the node's rows.
@@ -688,7 +695,7 @@ __global__ __launch_bounds__(256) void k_la(const QrDesc<T>* __restrict__ descs,
     if (node >= g.L(0)) return;
     const int par = (c0 / NB) & 1;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, gq = lane >> 4, ln = lane & 15;
-    const size_t ld = (size_t)d.ld;
+    const int ld = d.ld;
     T* W = d.W;
     int level = 0;
     const int lo = c0 + leaf_lo(node, mp, g.L(0));
@@ -698,54 +705,55 @@ __global__ __launch_bounds__(256) void k_la(const QrDesc<T>* __restrict__ descs,
         const int rbe = rows_pad >> 4;
         // explicit reflectors of the node (unit diagonal, zero above it and
         // beyond the node), one row per thread
-        if (level == 0) {
-            for (int s = tid; s < rows_pad; s += 256) {
-                T v[NB];
+        // (raw buffers: reads outside a range give zero, so no branches and
+        // exact wait counts; a generic-pointer load would be a flat access)
+        {
+            const int s = tid;
+            T v[NB];
+            if (level == 0) {
+                const RawBuf<T> bv(W + (size_t)c0 * ld, (unsigned)(nbk * ld * sizeof(T)));
+                const unsigned vo = s < mt ? (unsigned)((lo + s) * sizeof(T)) : kOob;
 #pragma unroll
-                for (int col = 0; col < NB; ++col)
-                    v[col] = (s < mt && col < nbk)
-                                 ? (s > col ? W[(size_t)(c0 + col) * ld + lo + s] : (s == col ? T(1) : T(0)))
-                                 : T(0);
+                for (int col = 0; col < NB; ++col) {
+                    const T x = bv.load(vo + (unsigned)(col * ld * sizeof(T)));
+                    v[col] = s > col ? x : ((s == col && s < mt && col < nbk) ? T(1) : T(0));
+                }
+            } else {
+                const T* Vi = (par ? d.Vint[1] : d.Vint[0]) + (size_t)internal_index(g, level, node) * C::MT_MAX * NB;
+                const RawBuf<T> bv(Vi, (unsigned)(nbk * C::MT_MAX * sizeof(T)));
+                const unsigned vo = s < mt ? (unsigned)(s * sizeof(T)) : kOob;
 #pragma unroll
-                for (int col = 0; col < NB; ++col) s_V[s * VS + col] = v[col];
+                for (int col = 0; col < NB; ++col) v[col] = bv.load(vo + (unsigned)(col * C::MT_MAX * sizeof(T)));
             }
-        } else {
-            const T* Vi = (par ? d.Vint[1] : d.Vint[0]) + (size_t)internal_index(g, level, node) * C::MT_MAX * NB;
-            for (int s = tid; s < rows_pad; s += 256) {
-                T v[NB];
 #pragma unroll
-                for (int col = 0; col < NB; ++col) v[col] = (s < mt && col < nbk) ? Vi[(size_t)col * C::MT_MAX + s] : T(0);
-#pragma unroll
-                for (int col = 0; col < NB; ++col) s_V[s * VS + col] = v[col];
-            }
+            for (int col = 0; col < NB; ++col) s_V[s * VS + col] = v[col];
         }
-        const T* Tg = (par ? d.Tm[1] : d.Tm[0]) + (size_t)node_index(g, level, node, d.tm_leaves) * NB * NB;
+        const RawBuf<T> bt((par ? d.Tm[1] : d.Tm[0]) + (size_t)node_index(g, level, node, d.tm_leaves) * NB * NB,
+                           (unsigned)(NB * NB * sizeof(T)));
         T ta[2][2][4];
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int k = kb * 16 + M::row(gq, j);
-                ta[0][kb][j] = Tg[(size_t)ln * NB + k];
-                ta[1][kb][j] = Tg[(size_t)(16 + ln) * NB + k];
+                ta[0][kb][j] = bt.load((unsigned)((ln * NB + k) * sizeof(T)));
+                ta[1][kb][j] = bt.load((unsigned)(((16 + ln) * NB + k) * sizeof(T)));
             }
-        // this wave's rows of C^T (layout of k_update)
+        // this wave's rows of C^T (layout of k_update); the buffer covers the
+        // group's valid columns only
+        const RawBuf<T> bc(W + (size_t)cbase * ld, (unsigned)(max(0, min(16, ce - cbase)) * ld * sizeof(T)));
+        unsigned co[RBW];
         v4 cr[RBW];
 #pragma unroll
         for (int i = 0; i < RBW; ++i) {
             const int rb = wave * RBW + i;
-            cr[i] = v4{0, 0, 0, 0};
-            if (rb < rbe) {
-                const int sr = rb * 16 + ln;
-                const int wr = sr >= mt ? -1
-                               : level == 0 ? lo + sr
-                               : ((sr & (NB - 1)) < nbk ? s_rb[sr / NB] + (sr & (NB - 1)) : -1);
+            const int sr = rb * 16 + ln;
+            const int wr = (rb >= rbe || sr >= mt) ? -1
+                           : level == 0 ? lo + sr
+                           : ((sr & (NB - 1)) < nbk ? s_rb[sr / NB] + (sr & (NB - 1)) : -1);
+            co[i] = wr >= 0 ? (unsigned)((M::row(gq, 0) * ld + wr) * sizeof(T)) : kOob;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int c = cbase + M::row(gq, v);
-                    if (wr >= 0 && c < ce) cr[i][v] = W[(size_t)c * ld + wr];
-                }
-            }
+            for (int q = 0; q < 4; ++q) cr[i][q] = bc.load(co[i] + (unsigned)(M::row(0, q) * ld * sizeof(T)));
         }
         __syncthreads();  // s_V complete
         // this wave's share of W = V^T C (rows: V's columns; two accumulator
@@ -856,20 +864,9 @@ __global__ __launch_bounds__(256) void k_la(const QrDesc<T>* __restrict__ descs,
             }
         }
 #pragma unroll
-        for (int i = 0; i < RBW; ++i) {
-            const int rb = wave * RBW + i;
-            if (rb < rbe) {
-                const int sr = rb * 16 + ln;
-                const int wr = sr >= mt ? -1
-                               : level == 0 ? lo + sr
-                               : ((sr & (NB - 1)) < nbk ? s_rb[sr / NB] + (sr & (NB - 1)) : -1);
+        for (int i = 0; i < RBW; ++i)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int c = cbase + M::row(gq, v);
-                    if (wr >= 0 && c < ce) W[(size_t)c * ld + wr] = cr[i][v];
-                }
-            }
-        }
+            for (int q = 0; q < 4; ++q) bc.store(cr[i][q], co[i] + (unsigned)(M::row(0, q) * ld * sizeof(T)));
         // climb: the last child to arrive updates the parent's rows
         if (level + 1 >= g.levels) return;
         __threadfence();
