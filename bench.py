@@ -214,7 +214,7 @@ def main():
         r = step()
         log(f"[bench] warmup {i}: {r[-1]['ms']:.1f} ms, splits {r[-1]['splits']}")
     torch.cuda.synchronize()
-    h.profile_enable(not args.no_profile)
+    # throughput: the timed steps without per-launch events
     flops = 0.0
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -223,8 +223,22 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     log(f"[bench] timed {args.steps} steps: {dt:.3f} s")
-    stats = {k: h.profile_read(k) for k in (P.KERNEL_UPDATE, P.KERNEL_PANEL, P.KERNEL_GEMM, P.KERNEL_LA)}
-    h.profile_enable(False)
+    # per-kernel times: the same steps again with HIP events around every
+    # launch of the hot kernels (on the launch's stream); the events add
+    # host calls and GPU packets to every launch (about a fifth of the step
+    # time), so they stay out of the throughput pass above
+    stats = {}
+    dt_prof = None
+    if not args.no_profile:
+        h.profile_enable(True)
+        t1 = time.perf_counter()
+        for i in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        dt_prof = time.perf_counter() - t1
+        log(f"[bench] profiled {args.steps} steps: {dt_prof:.3f} s")
+        stats = {k: h.profile_read(k) for k in (P.KERNEL_UPDATE, P.KERNEL_PANEL, P.KERNEL_GEMM, P.KERNEL_LA)}
+        h.profile_enable(False)
 
     # accuracy of the last step against the construction (outside the timed region)
     st, t, s, ql, qr, starts, info = r
@@ -311,6 +325,8 @@ def main():
         "blocks": info["nblocks"],
         "eig_rel_err_vs_construction": eig_err,
         "kernels": {names[k]: v for k, v in stats.items()},
+        "kernel_timing": "HIP events around every launch, in a second pass of the same steps "
+                         "(ms_per_step of that pass: %s)" % (None if dt_prof is None else round(dt_prof / args.steps * 1e3, 1)),
         "roofline": roof,
         "roofline_update": roof_upd,
         "cpu_baseline": cpu,

@@ -515,4 +515,13 @@ void gauss_batch(const GaussDesc* d, const GaussDesc* h, int count, hipStream_t 
     hipLaunchKernelGGL(k_gauss, dim3((n + 63) / 64, (n + 3) / 4, count), dim3(256), 0, s, d);
 }
 
+__global__ __launch_bounds__(256) void k_gather(const GatherDesc* __restrict__ descs, double* __restrict__ dst) {
+    const GatherDesc d = descs[blockIdx.x];
+    for (int i = threadIdx.x; i < d.n; i += 256) dst[d.off + i] = d.src[i];
+}
+
+void gather_batch(const GatherDesc* d, int count, double* dst, hipStream_t s) {
+    if (count > 0) hipLaunchKernelGGL(k_gather, dim3(count), dim3(256), 0, s, d, dst);
+}
+
 }  // namespace sdc

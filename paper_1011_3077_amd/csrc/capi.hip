@@ -100,6 +100,8 @@ sdc_status_t sdc_destroy(sdc_handle_t handle) {
     if (h.host) (void)hipHostFree(h.host);
     if (h.ws2) (void)hipFree(h.ws2);
     if (h.dnorm) (void)hipFree(h.dnorm);
+    if (h.dstage) (void)hipFree(h.dstage);
+    if (h.ev_sync) (void)hipEventDestroy(h.ev_sync);
     sdc::release_streams(h);
     delete handle;
     return SDC_OK;

@@ -135,7 +135,7 @@ template <typename T> static int irs_tick(Handle& h, std::vector<IrsSide<T>*>& s
     HIPCHK(hipGetLastError());
     double* hn = reinterpret_cast<double*>(h.host);
     HIPCHK(hipMemcpyAsync(hn, h.dnorm, sizeof(double) * 4 * cnt, hipMemcpyDeviceToHost, h.stream));
-    HIPCHK(hipStreamSynchronize(h.stream));
+    CHK(sync_spin(h));
     h.desc_off = mark;
     for (int i = 0; i < cnt; ++i) {
         IrsSide<T>& s = *act[i];
@@ -486,18 +486,16 @@ static int split_search(Handle& h, std::vector<JobWs*>& js) {
 // Read back the diagonals of the GRURV triangular factors and form the rank
 // statistic rho = |diag(R1^{m1} R2^{m2})|.
 static int fetch_rho(Handle& h, std::vector<JobWs*>& js, bool left) {
-    size_t need = 0;
-    for (JobWs* w : js) need += 2 * (size_t)w->job->n;
-    CHK(ensure_host(h, need * sizeof(double) + 64));
-    double* hb = reinterpret_cast<double*>(h.host);
+    std::vector<GatherDesc> gd;
     size_t off = 0;
     for (JobWs* w : js) {
         const int n = w->job->n;
-        HIPCHK(hipMemcpyAsync(hb + off, w->dg[1], sizeof(double) * n, hipMemcpyDeviceToHost, h.stream));
-        HIPCHK(hipMemcpyAsync(hb + off + n, w->dg[2], sizeof(double) * n, hipMemcpyDeviceToHost, h.stream));
+        gd.push_back(GatherDesc{w->dg[1], (long long)off, n});
+        gd.push_back(GatherDesc{w->dg[2], (long long)(off + n), n});
         off += 2 * (size_t)n;
     }
-    HIPCHK(hipStreamSynchronize(h.stream));
+    double* hb = nullptr;
+    CHK(read_back(h, gd, hb));
     off = 0;
     for (JobWs* w : js) {
         const int n = w->job->n;
@@ -517,11 +515,10 @@ static int fetch_rho(Handle& h, std::vector<JobWs*>& js, bool left) {
 }
 
 static int fetch_search(Handle& h, std::vector<JobWs*>& js) {
-    CHK(ensure_host(h, js.size() * 2 * sizeof(double) + 64));
-    double* hb = reinterpret_cast<double*>(h.host);
-    for (size_t q = 0; q < js.size(); ++q)
-        HIPCHK(hipMemcpyAsync(hb + 2 * q, js[q]->out, sizeof(double) * 2, hipMemcpyDeviceToHost, h.stream));
-    HIPCHK(hipStreamSynchronize(h.stream));
+    std::vector<GatherDesc> gd;
+    for (size_t q = 0; q < js.size(); ++q) gd.push_back(GatherDesc{js[q]->out, (long long)(2 * q), 2});
+    double* hb = nullptr;
+    CHK(read_back(h, gd, hb));
     for (size_t q = 0; q < js.size(); ++q) {
         js[q]->job->info.k_lead = (int)hb[2 * q];
         js[q]->job->info.e21_rel = hb[2 * q + 1];
@@ -612,6 +609,7 @@ static int cg_solve(Handle& h, std::vector<JobWs*>& js) {
     size_t need = 0;
     for (const CgDesc& d : cg) need += 2 * (size_t)d.nblk;
     CHK(ensure_host(h, need * sizeof(double) + 64));
+    CHK(ensure_dstage(h, need + 1));
     cg_init_batch(dcg, cg.data(), count, h.stream);
     for (int it = 0; it < kCgMaxIt; ++it) {
         gemm_batch<double>(dg1, g1.data(), count, h.stream);
@@ -621,16 +619,15 @@ static int cg_solve(Handle& h, std::vector<JobWs*>& js) {
         HIPCHK(hipGetLastError());
         // stop launching once every problem is frozen (the device decides;
         // this only saves launches)
-        double* hb = reinterpret_cast<double*>(h.host);
+        std::vector<GatherDesc> gd;
         size_t off = 0;
         for (const CgDesc& d : cg) {
-            HIPCHK(hipMemcpyAsync(hb + off, d.rr + ((it + 1) % 3) * kCgMaxBlocks, sizeof(double) * d.nblk,
-                                  hipMemcpyDeviceToHost, h.stream));
-            HIPCHK(hipMemcpyAsync(hb + off + d.nblk, d.rr0, sizeof(double) * d.nblk, hipMemcpyDeviceToHost,
-                                  h.stream));
+            gd.push_back(GatherDesc{d.rr + ((it + 1) % 3) * kCgMaxBlocks, (long long)off, d.nblk});
+            gd.push_back(GatherDesc{d.rr0, (long long)(off + d.nblk), d.nblk});
             off += 2 * (size_t)d.nblk;
         }
-        HIPCHK(hipStreamSynchronize(h.stream));
+        double* hb = nullptr;
+        CHK(read_back(h, gd, hb));
         bool all = true;
         off = 0;
         for (const CgDesc& d : cg) {
@@ -716,11 +713,10 @@ static int pin_to_rank(Handle& h, std::vector<JobWs*>& js) {
         ks.push_back(krho);
     }
     if (alt.empty()) return SDC_OK;
-    CHK(ensure_host(h, alt.size() * sizeof(double) + 64));
-    double* hb = reinterpret_cast<double*>(h.host);
-    for (size_t q = 0; q < alt.size(); ++q)
-        HIPCHK(hipMemcpyAsync(hb + q, alt[q]->e + ks[q], sizeof(double), hipMemcpyDeviceToHost, h.stream));
-    HIPCHK(hipStreamSynchronize(h.stream));
+    std::vector<GatherDesc> gd;
+    for (size_t q = 0; q < alt.size(); ++q) gd.push_back(GatherDesc{alt[q]->e + ks[q], (long long)q, 1});
+    double* hb = nullptr;
+    CHK(read_back(h, gd, hb));
     for (size_t q = 0; q < alt.size(); ++q) {
         alt[q]->job->info.k_lead = ks[q];
         alt[q]->job->info.e21_rel = hb[q];
@@ -1032,11 +1028,10 @@ static int finish_jobs(Handle& h, std::vector<JobWs*>& wsp) {
         CHK(run_gemm(h, go));
         UPLOAD(dno, no);
         orth_err_batch(dno, no.data(), (int)no.size(), h.stream);
-        CHK(ensure_host(h, diag_jobs.size() * sizeof(double) + 64));
-        double* hb = reinterpret_cast<double*>(h.host);
-        for (size_t q = 0; q < diag_jobs.size(); ++q)
-            HIPCHK(hipMemcpyAsync(hb + q, diag_jobs[q]->orth, sizeof(double), hipMemcpyDeviceToHost, h.stream));
-        HIPCHK(hipStreamSynchronize(h.stream));
+        std::vector<GatherDesc> gd;
+        for (size_t q = 0; q < diag_jobs.size(); ++q) gd.push_back(GatherDesc{diag_jobs[q]->orth, (long long)q, 1});
+        double* hb = nullptr;
+        CHK(read_back(h, gd, hb));
         for (size_t q = 0; q < diag_jobs.size(); ++q) diag_jobs[q]->job->info.orth_err = std::sqrt(hb[q]);
     }
     HIPCHK(hipStreamSynchronize(h.stream));

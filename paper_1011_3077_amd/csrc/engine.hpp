@@ -35,6 +35,11 @@ struct Handle {
     // per-tick convergence norms of the repeated squaring (4 per side)
     double* dnorm = nullptr;
     size_t dnorm_cap = 0;
+    // device staging of small per-problem results read back in one copy
+    double* dstage = nullptr;
+    size_t dstage_cap = 0;
+    // event polled by sync_spin (created on first use)
+    hipEvent_t ev_sync = nullptr;
     // look-ahead stream and events of the QR (created on first use)
     QrStreams qs{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     // opt-in kernel timing

@@ -3,10 +3,12 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
 #include "engine.hpp"
+#include "sdc_aux.hpp"
 #include "sdc.h"
 
 namespace sdc {
@@ -114,6 +116,34 @@ inline int ensure_dnorm(Handle& h, size_t elems) {
     return SDC_OK;
 }
 
+// Wait for the handle's stream by polling an event: at the per-iteration
+// decision points (convergence norms, ranks, split points) the host must act
+// as soon as the data is there, and a blocking synchronization can put the
+// thread to sleep for tens of microseconds.
+inline int sync_spin(Handle& h) {
+    if (!h.ev_sync) HIPCHK(hipEventCreateWithFlags(&h.ev_sync, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(h.ev_sync, h.stream));
+    hipError_t e;
+    while ((e = hipEventQuery(h.ev_sync)) == hipErrorNotReady) {
+    }
+    HIPCHK(e);
+    return SDC_OK;
+}
+
+inline int ensure_dstage(Handle& h, size_t elems) {
+    if (elems <= h.dstage_cap) return SDC_OK;
+    if (h.dstage) {
+        HIPCHK(hipStreamSynchronize(h.stream));
+        HIPCHK(hipFree(h.dstage));
+        h.dstage = nullptr;
+        h.dstage_cap = 0;
+    }
+    const size_t cap = elems < 4096 ? 4096 : elems;
+    if (hipMalloc(reinterpret_cast<void**>(&h.dstage), cap * sizeof(double)) != hipSuccess) return SDC_ERR_NOMEM;
+    h.dstage_cap = cap;
+    return SDC_OK;
+}
+
 inline int ensure_host(Handle& h, size_t bytes) {
     if (bytes <= h.host_size) return SDC_OK;
     if (h.host) {
@@ -141,6 +171,24 @@ template <class T> inline const T* upload(Handle& h, const std::vector<T>& v) {
 #define UPLOAD(ptr, vec)                                   \
     auto ptr = upload(h, vec);                             \
     if (!ptr) return SDC_ERR_DEVICE;
+
+// Small device results of several problems to the host with one copy:
+// gathered on the device into h.dstage, copied to h.host, synchronized.
+// `out` points at the segments, back to back in the order given.
+inline int read_back(Handle& h, const std::vector<GatherDesc>& g, double*& out) {
+    size_t total = 0;
+    for (const GatherDesc& d : g) total = std::max(total, (size_t)d.off + (size_t)d.n);
+    if (int st = ensure_dstage(h, total + 1)) return st;
+    if (int st = ensure_host(h, (total + 1) * sizeof(double) + 64)) return st;
+    const size_t mark = h.desc_off;
+    UPLOAD(dg, g);
+    gather_batch(dg, (int)g.size(), h.dstage, h.stream);
+    HIPCHK(hipMemcpyAsync(h.host, h.dstage, total * sizeof(double), hipMemcpyDeviceToHost, h.stream));
+    if (int st = sync_spin(h)) return st;
+    h.desc_off = mark;
+    out = reinterpret_cast<double*>(h.host);
+    return SDC_OK;
+}
 
 
 }  // namespace sdc

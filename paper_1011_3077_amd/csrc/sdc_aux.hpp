@@ -25,6 +25,14 @@ struct NormDesc {
     int active;
 };
 
+// Copy n doubles from src to dst + off (collecting small per-problem results
+// into one buffer for a single device-to-host copy).
+struct GatherDesc {
+    const double* src;
+    long long off;
+    int n;
+};
+
 struct SplitDesc {
     const double* Ah; int lda;
     const double* Bh; int ldb;  // null for the symmetric case
@@ -79,5 +87,7 @@ void norm1_batch(const NormDesc* d, const NormDesc* h, int count, hipStream_t s)
 void split_search_batch(const SplitDesc* d, const SplitDesc* h, int count, hipStream_t s);
 void orth_err_batch(const NormDesc* d, const NormDesc* h, int count, hipStream_t s);
 void gauss_batch(const GaussDesc* d, const GaussDesc* h, int count, hipStream_t s);
+
+void gather_batch(const GatherDesc* d, int count, double* dst, hipStream_t s);
 
 }  // namespace sdc

@@ -337,6 +337,8 @@ sdc_status_t sdc_server_destroy(sdc_server_t s) {
     if (h.host) (void)hipHostFree(h.host);
     if (h.ws2) (void)hipFree(h.ws2);
     if (h.dnorm) (void)hipFree(h.dnorm);
+    if (h.dstage) (void)hipFree(h.dstage);
+    if (h.ev_sync) (void)hipEventDestroy(h.ev_sync);
     sdc::release_streams(h);
     if (h.stream) (void)hipStreamDestroy(h.stream);
     delete s;
