@@ -102,6 +102,7 @@ sdc_status_t sdc_destroy(sdc_handle_t handle) {
     if (h.dnorm) (void)hipFree(h.dnorm);
     if (h.dstage) (void)hipFree(h.dstage);
     if (h.ev_sync) (void)hipEventDestroy(h.ev_sync);
+    if (h.ev_desc) (void)hipEventDestroy(h.ev_desc);
     sdc::release_streams(h);
     delete handle;
     return SDC_OK;

@@ -87,6 +87,18 @@ template <typename T> static QrDesc<T> qr_desc(T* W, int ld, int m, int nf, int 
     return d;
 }
 
+// Look-ahead streams for a batch of QRs, or none: below kLookaheadMinN
+// factored columns the bulk update of a panel is too small to hide the next
+// panel, and a single stream saves the host the event calls of every panel
+// (at these sizes the host's launch rate is on the critical path).
+constexpr int kLookaheadMinN = 1200;
+template <typename T> static const QrStreams* lookahead(Handle& h, const std::vector<QrDesc<T>>& q) {
+    int nf = 0;
+    for (const QrDesc<T>& d : q)
+        if (d.active) nf = std::max(nf, d.nf);
+    return nf >= kLookaheadMinN ? &h.qs : nullptr;
+}
+
 // Set-up of the sides not started yet: W <- [B0 A0 0; -A0 0 B0] from the
 // inputs and the region map; tree counters cleared.
 template <typename T> static int irs_start(Handle& h, std::vector<IrsSide<T>*>& sides) {
@@ -130,7 +142,7 @@ template <typename T> static int irs_tick(Handle& h, std::vector<IrsSide<T>*>& s
     UPLOAD(dp, pd);
     fill<double>(h.dnorm, 4 * (size_t)cnt, 0.0, h.stream);
     CHK(ensure_streams(h));
-    qr_aug_batch<T>(dq, qd.data(), cnt, h.stream, &h.qs);
+    qr_aug_batch<T>(dq, qd.data(), cnt, h.stream, lookahead(h, qd));
     irs_post_batch<T>(dp, pd.data(), cnt, 0, h.stream);
     HIPCHK(hipGetLastError());
     double* hn = reinterpret_cast<double*>(h.host);
@@ -325,7 +337,7 @@ static int run_qr(Handle& h, std::vector<JobWs*>& js, int dgi) {
     if (q.empty()) return SDC_OK;
     UPLOAD(d, q);
     CHK(ensure_streams(h));
-    qr_aug_batch<double>(d, q.data(), (int)q.size(), h.stream, &h.qs);
+    qr_aug_batch<double>(d, q.data(), (int)q.size(), h.stream, lookahead(h, q));
     return SDC_OK;
 }
 

@@ -21,11 +21,16 @@ struct Handle {
     char* ws = nullptr;
     size_t ws_size = 0;
     size_t ws_off = 0;
-    // descriptor staging: pinned host mirror + device arena, same offsets
+    // descriptor staging: pinned host mirror + device arena, same offsets.
+    // desc_dirty: end of the mirror bytes written since the last completed
+    // wait (an asynchronous copy still queued may read them); ev_desc: event
+    // recorded after the most recent copy
     char* desc_h = nullptr;
     char* desc_d = nullptr;
     size_t desc_size = 0;
     size_t desc_off = 0;
+    size_t desc_dirty = 0;
+    hipEvent_t ev_desc = nullptr;
     // pinned host buffer for small device-to-host results
     char* host = nullptr;
     size_t host_size = 0;

@@ -79,6 +79,7 @@ inline int ensure_desc(Handle& h, size_t bytes) {
     if (hipHostMalloc(&h.desc_h, bytes, hipHostMallocDefault) != hipSuccess) return SDC_ERR_NOMEM;
     h.desc_size = bytes;
     h.desc_off = 0;
+    h.desc_dirty = 0;
     return SDC_OK;
 }
 
@@ -127,6 +128,7 @@ inline int sync_spin(Handle& h) {
     while ((e = hipEventQuery(h.ev_sync)) == hipErrorNotReady) {
     }
     HIPCHK(e);
+    h.desc_dirty = 0;  // every copy issued so far has run
     return SDC_OK;
 }
 
@@ -156,15 +158,29 @@ inline int ensure_host(Handle& h, size_t bytes) {
     return SDC_OK;
 }
 
-// Copy a host array of descriptors to the device arena (pinned staging; the
-// arena is rewound only after a stream synchronization).
+// Copy a host array of descriptors to the device arena through its pinned
+// mirror.  The copy is asynchronous and reads the mirror when it runs, so the
+// arena may be rewound (desc_off lowered) at any time, but a mirror byte that
+// an earlier copy still has to read is not overwritten: writing below
+// desc_dirty first waits for the most recent copy (copies on the stream
+// complete in order, so every earlier one has then read its bytes).
 template <class T> inline const T* upload(Handle& h, const std::vector<T>& v) {
     const size_t bytes = v.size() * sizeof(T);
     size_t off = (h.desc_off + 255) & ~size_t(255);
     if (off + bytes > h.desc_size) return nullptr;
+    if (!h.ev_desc && hipEventCreateWithFlags(&h.ev_desc, hipEventDisableTiming) != hipSuccess) {
+        h.ev_desc = nullptr;
+        return nullptr;
+    }
+    if (off < h.desc_dirty) {
+        if (hipEventSynchronize(h.ev_desc) != hipSuccess) return nullptr;
+        h.desc_dirty = 0;
+    }
     std::memcpy(h.desc_h + off, v.data(), bytes);
     if (hipMemcpyAsync(h.desc_d + off, h.desc_h + off, bytes, hipMemcpyHostToDevice, h.stream) != hipSuccess)
         return nullptr;
+    if (hipEventRecord(h.ev_desc, h.stream) != hipSuccess) return nullptr;
+    h.desc_dirty = std::max(h.desc_dirty, off + bytes);
     h.desc_off = off + bytes;
     return reinterpret_cast<const T*>(h.desc_d + off);
 }

@@ -339,6 +339,7 @@ sdc_status_t sdc_server_destroy(sdc_server_t s) {
     if (h.dnorm) (void)hipFree(h.dnorm);
     if (h.dstage) (void)hipFree(h.dstage);
     if (h.ev_sync) (void)hipEventDestroy(h.ev_sync);
+    if (h.ev_desc) (void)hipEventDestroy(h.ev_desc);
     sdc::release_streams(h);
     if (h.stream) (void)hipStreamDestroy(h.stream);
     delete s;
