@@ -87,11 +87,10 @@ template <typename T> static QrDesc<T> qr_desc(T* W, int ld, int m, int nf, int 
     return d;
 }
 
-// Look-ahead streams for a batch of QRs, or none: below kLookaheadMinN
-// factored columns the bulk update of a panel is too small to hide the next
-// panel, and a single stream saves the host the event calls of every panel
-// (at these sizes the host's launch rate is on the critical path).
-constexpr int kLookaheadMinN = 1200;
+// Look-ahead streams for a batch of QRs, or none: only problems of at least
+// kLookaheadMinN factored columns are updated with look-ahead, and a single
+// stream saves the host the event calls of every panel (at smaller sizes the
+// host's launch rate is on the critical path).
 template <typename T> static const QrStreams* lookahead(Handle& h, const std::vector<QrDesc<T>>& q) {
     int nf = 0;
     for (const QrDesc<T>& d : q)

@@ -198,7 +198,8 @@ __device__ __forceinline__ bool qr_step(T (&a)[NRW][8], T (&tc)[8], T& tau_prev,
                                         T* s_P, T* s_tau, T* s_beta) {
     const int j = 8 * jw + JJ;
     if (j >= nbk) return false;
-    const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
+    const int tid = threadIdx.x, l = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: scalar branches below
     const int par = j & 1;
     const T* xs = s_x + par * 256;
     const T xn2 = s_sc[par * 2], alpha = s_sc[par * 2 + 1];
@@ -238,27 +239,36 @@ __device__ __forceinline__ bool qr_step(T (&a)[NRW][8], T (&tc)[8], T& tau_prev,
     for (int c = 0; c < 8; ++c) q[c] = fma(dj, a[0][c], q[c]);
     xh[0] = rowj ? dd : xh[0];
     const T f = wave_sum8(q, l);
-    T w[8];
+    // S_c (wave-uniform); w_c = scale S_c
+    T sc8[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) w[c] = scale * lane_read(f, 2 * c);
-    // this wave's share of T column j (tc is zero for columns >= j)
-    T pj = tc[0] * w[0];
+    for (int c = 0; c < 8; ++c) sc8[c] = lane_read(f, 2 * c);
+    // this wave's share of T column j, scale sum_c T[i][c] S_c (tc is zero
+    // for columns >= j)
+    T pj = tc[0] * sc8[0];
 #pragma unroll
-    for (int c = 1; c < 8; ++c) pj = fma(tc[c], w[c], pj);
-    if (l < 32) s_P[par * 128 + wv * 32 + l] = pj;
+    for (int c = 1; c < 8; ++c) pj = fma(tc[c], sc8[c], pj);
+    if (l < 32) s_P[par * 128 + wv * 32 + l] = scale * pj;
+    // a_c <- a_c - (tau w_c / d) xh = a_c - S_c (tau scale^2 xh) for the
+    // columns after j: all of a later wave's, those after JJ in j's own wave
+    const T g = tau * scale * scale;
+    T u[NRW];
+#pragma unroll
+    for (int i = 0; i < NRW; ++i) u[i] = g * xh[i];
+    // (selects on wave-uniform conditions: no branches, whose register
+    // copies would cost more than the products they skip)
+    const bool later = wv > jw, own = wv == jw;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        const int col = 8 * wv + c;
-        const T coef = col > j ? tau * w[c] * scale : T(0);
+        const T cf = (later || (own && c > JJ)) ? sc8[c] : T(0);
 #pragma unroll
-        for (int i = 0; i < NRW; ++i) a[i][c] = fma(-coef, xh[i], a[i][c]);
+        for (int i = 0; i < NRW; ++i) a[i][c] = fma(-cf, u[i], a[i][c]);
     }
-    if (wv == jw) {
 #pragma unroll
-        for (int i = 0; i < NRW; ++i) {
-            const int r = l + 64 * i;
-            a[i][JJ] = r > j ? xh[i] * scale : (r == j ? beta : a[i][JJ]);
-        }
+    for (int i = 0; i < NRW; ++i) {
+        const int r = l + 64 * i;
+        const T vj = r > j ? xh[i] * scale : (r == j ? beta : a[i][JJ]);
+        a[i][JJ] = own ? vj : a[i][JJ];
     }
     if (tid == 0) {
         s_tau[j] = tau;
@@ -280,7 +290,7 @@ __device__ __forceinline__ void node_qr_rows(T (&a)[NRW][8], int nbk, T* s_x, T*
                                              T* Tg) {
     constexpr int NB = QrCfg<T>::NB;
     static_assert(NB == 32 && QrCfg<T>::PT == 256, "four waves of eight columns");
-    const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
+    const int tid = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
     T tc[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) tc[c] = 0;
@@ -464,8 +474,7 @@ __global__ __launch_bounds__(QrCfg<T>::PT) void k_panel(const QrDesc<T>* __restr
 //   C^T -= Y^T V^T : Y's accumulator registers are the A operand with the
 //                 same k-slices, V^T read from LDS, C^T accumulated in place.
 template <typename T, int RB>
-__global__ __launch_bounds__(256, 2) void k_update(const QrDesc<T>* __restrict__ descs, int c0, int level,
-                                                   int mode) {
+__global__ __launch_bounds__(256, 2) void k_update(const QrDesc<T>* __restrict__ descs, int c0, int level) {
     using C = QrCfg<T>;
     using M = Mfma<T>;
     typedef typename M::v4 v4;
@@ -477,11 +486,9 @@ __global__ __launch_bounds__(256, 2) void k_update(const QrDesc<T>* __restrict__
     const QrDesc<T> d = descs[blockIdx.z];
     if (!d.active || c0 >= d.nf) return;
     const int nbk = min(NB, d.nf - c0);
-    // column range: all trailing columns (mode 0) or the columns after the
-    // next panel's (mode 2; the next panel's own columns are k_la's)
-    int cb = c0 + nbk;
+    // column range: the trailing columns after those of the row-split kernel
+    const int cb = c0 + nbk + row_split_cols(NB, d.nf, c0);
     const int ce = d.ncols;
-    if (mode != 0) cb += max(0, min(NB, d.nf - cb));
     const int col0 = cb + blockIdx.y * 64;
     if (col0 >= ce) return;
     const int par = (c0 / NB) & 1;
@@ -659,9 +666,10 @@ __global__ __launch_bounds__(256, 2) void k_update(const QrDesc<T>* __restrict__
     }
 }
 
-// Look-ahead update: the transpose of panel c0's orthogonal factor (every
-// tree level) applied to the next panel's columns, in one launch.  A
-// workgroup owns one node and one 16-column group of the next panel; its four
+// Row-split (look-ahead) update: the transpose of panel c0's orthogonal
+// factor (every tree level) applied, in one launch, to the next panel's
+// columns (row_split_cols).  A workgroup owns one node and one 16-column
+// group of them; its four
 // waves split the node's rows (row blocks [RBW w, RBW w + RBW) of wave w),
 // each forms its share of W = V^T C, the shares are summed through LDS, and
 // each wave applies C <- C - V (T^T W) to its rows.  The last workgroup to
@@ -674,7 +682,6 @@ __global__ __launch_bounds__(256) void k_la(const QrDesc<T>* __restrict__ descs,
     using M = Mfma<T>;
     typedef typename M::v4 v4;
     constexpr int NB = C::NB, VS = NB + 1, XS = 17, RBW = C::MT_MAX / 64;
-    constexpr int kCounterStride = kMaxInternal / 2;  // counters of column group 1
     __shared__ T s_V[C::MT_MAX * VS];
     __shared__ T s_X[4 * 16 * XS];  // per-wave transpose tiles, then the W / Y exchange
     __shared__ int s_rb[C::F];
@@ -685,14 +692,17 @@ __global__ __launch_bounds__(256) void k_la(const QrDesc<T>* __restrict__ descs,
     if (!d.active || c0 >= d.nf) return;
     const int nbk = min(NB, d.nf - c0);
     const int cb = c0 + nbk;
-    const int nxt = min(NB, d.nf - cb);
+    const int ce = cb + row_split_cols(NB, d.nf, c0);
     const int cgrp = blockIdx.y;
-    if (nxt <= 16 * cgrp) return;  // no columns in this group (for every node alike)
-    const int cbase = cb + 16 * cgrp, ce = cb + nxt;
+    if (ce - cb <= 16 * cgrp) return;  // no columns in this group (for every node alike)
+    const int cbase = cb + 16 * cgrp;
     const int mp = d.m - c0;
     const auto g = tree_geom<T>(mp);
     int node = blockIdx.x;
     if (node >= g.L(0)) return;
+    // arrival counters of column group cgrp: after the panel factorization's
+    // kPanelCounters, one per internal node of this panel's tree
+    const int nint = internal_index(g, g.levels, 0);
     const int par = (c0 / NB) & 1;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, gq = lane >> 4, ln = lane & 15;
     const int ld = d.ld;
@@ -875,7 +885,7 @@ __global__ __launch_bounds__(256) void k_la(const QrDesc<T>* __restrict__ descs,
         const int iidx = internal_index(g, level + 1, parent);
         const int nch = min(C::F, g.L(level) - parent * C::F);
         if (tid == 0) {
-            unsigned* cnt = d.counters + cgrp * kCounterStride + iidx;
+            unsigned* cnt = d.counters + kPanelCounters + cgrp * nint + iidx;
             const unsigned old = atomicAdd(cnt, 1u);
             s_last = (old == (unsigned)(nch - 1));
             if (s_last) *cnt = 0u;
@@ -892,29 +902,19 @@ __global__ __launch_bounds__(256) void k_la(const QrDesc<T>* __restrict__ descs,
 }
 
 template <typename T>
-static void launch_update(int rows, dim3 grid, hipStream_t s, const QrDesc<T>* d, int c0, int lev, int mode);
-template <>
-void launch_update<double>(int rows, dim3 grid, hipStream_t s, const QrDesc<double>* d, int c0, int lev,
-                           int mode) {
-    constexpr int RB = QrCfg<double>::MT_MAX / 16;
-    (void)rows;
-    hipLaunchKernelGGL((k_update<double, RB>), grid, dim3(256), 0, s, d, c0, lev, mode);
-}
-template <>
-void launch_update<float>(int rows, dim3 grid, hipStream_t s, const QrDesc<float>* d, int c0, int lev,
-                          int mode) {
-    constexpr int RB = QrCfg<float>::MT_MAX / 16;
-    (void)rows;
-    hipLaunchKernelGGL((k_update<float, RB>), grid, dim3(256), 0, s, d, c0, lev, mode);
+static void launch_update(dim3 grid, hipStream_t s, const QrDesc<T>* d, int c0, int lev) {
+    constexpr int RB = QrCfg<T>::MT_MAX / 16;
+    hipLaunchKernelGGL((k_update<T, RB>), grid, dim3(256), 0, s, d, c0, lev);
 }
 
-// Batched augmented QR, panel by panel.  Without `la` every step runs on s:
-// panel factorization, then the tree levels of the trailing update.  With
-// `la` (look-ahead, depth 1) panel k+1 is factored while the update of the
-// columns after it runs concurrently:
-//   crit: P(k), [wait rest(k-1)], LA(k) = update of panel k+1's columns
-//         (k_la, every tree level in one launch), P(k+1) ...
-//   rest: [wait LA(k)], REST(k) = update of every column after panel k+1
+// Batched augmented QR, panel by panel: panel factorization P(k), then the
+// update of the trailing columns, split per problem (row_split_cols) between
+// the row-split kernel (LA(k)) and the wide kernel's tree levels (REST(k)).
+// Without `la` every step runs on s.  With `la` (look-ahead, depth 1), when
+// every problem's next panel is in LA(k), panel k+1 is factored while REST(k)
+// runs on the second stream:
+//   crit: P(k), [wait REST(k-1)], LA(k), P(k+1) ...
+//   rest: [wait LA(k)], REST(k)
 // so P(k+1) runs beside REST(k) and LA(k) runs alone (it is short, and a
 // small grid queued behind a large one is dispatched only after it).
 // LA(k) must follow REST(k-1) (both touch panel k+1's columns); P(k+1)
@@ -934,90 +934,81 @@ void qr_aug_batch(const QrDesc<T>* d_descs, const QrDesc<T>* h, int count, hipSt
         (void)hipStreamWaitEvent(la->crit, la->evE, 0);
         sc = la->crit;
     }
+    Profiler* prof = g_prof;
     for (int c0 = 0; c0 < max_nf; c0 += C::NB) {
         int maxL[kMaxLevels] = {};
-        int maxlev = 0, maxleaf = 0, maxtrail = 0;
-        bool next = false;
+        int maxlev = 0, la_l0 = 0, la_groups = 0, rest_tiles = 0;
+        bool overlap = true;  // every next panel's columns are in LA(k)
+        // algorithmic work of this panel, per tree level: the update of level
+        // l touches R_l rows (all panel rows at the leaves, nbk per child
+        // above): 4 R nbk ntr + 2 nbk^2 ntr L_l flops, and reads + writes the
+        // R x ntr trailing slice and reads the R x nbk reflectors once; the
+        // two update kernels are charged by their share of the columns
+        double pf = 0, pb = 0, lf = 0, lb = 0, uf[kMaxLevels] = {}, ub[kMaxLevels] = {};
         for (int i = 0; i < count; ++i) {
             if (!h[i].active || c0 >= h[i].nf) continue;
             const int mp = h[i].m - c0;
             const auto g = tree_geom<T>(mp);
             for (int l = 0; l < g.levels; ++l) maxL[l] = maxL[l] > g.L(l) ? maxL[l] : g.L(l);
             maxlev = maxlev > g.levels ? maxlev : g.levels;
-            const int blocks16 = (mp + 15) / 16;
-            const int leaf = g.L(0) == 1 ? mp : min(mp, (blocks16 + g.L(0) - 1) / g.L(0) * 16);
-            maxleaf = maxleaf > leaf ? maxleaf : leaf;
             const int nbk = h[i].nf - c0 < C::NB ? h[i].nf - c0 : C::NB;
             const int trail = h[i].ncols - c0 - nbk;
-            maxtrail = maxtrail > trail ? maxtrail : trail;
-            next |= c0 + nbk < h[i].nf;
-        }
-        if (maxL[0] == 0) continue;
-        // algorithmic work of this panel, per tree level: the update of level
-        // l touches R_l rows (all panel rows at the leaves, nbk per child
-        // above): 4 R nbk ntr + 2 nbk^2 ntr L_l flops, and reads + writes the
-        // R x ntr trailing slice and reads the R x nbk reflectors once
-        double pf = 0, pb = 0, uf[kMaxLevels] = {}, ub[kMaxLevels] = {};
-        Profiler* prof = g_prof;
-        if (prof) {
-            for (int i = 0; i < count; ++i) {
-                if (!h[i].active || c0 >= h[i].nf) continue;
-                const int mp = h[i].m - c0;
-                const auto g = tree_geom<T>(mp);
-                const double nbk = h[i].nf - c0 < C::NB ? h[i].nf - c0 : C::NB;
-                const double ntr = h[i].ncols - c0 - nbk;
-                pf += 2.0 * mp * nbk * nbk;               // Householder QR of the panel
+            const int nla = row_split_cols(C::NB, h[i].nf, c0);
+            if (nla > 0) {
+                la_l0 = la_l0 > g.L(0) ? la_l0 : g.L(0);
+                la_groups = la_groups > (nla + 15) / 16 ? la_groups : (nla + 15) / 16;
+            }
+            if (trail > nla) rest_tiles = rest_tiles > (trail - nla + 63) / 64 ? rest_tiles : (trail - nla + 63) / 64;
+            const int nxt = h[i].nf - c0 - nbk < C::NB ? h[i].nf - c0 - nbk : C::NB;
+            if (nxt > 0 && nla < nxt) overlap = false;
+            if (prof) {
+                pf += 2.0 * mp * nbk * nbk;  // Householder QR of the panel
                 pb += 2.0 * mp * nbk * sizeof(T);
+                const double share = trail > 0 ? (double)nla / trail : 0.0;
                 for (int l = 0; l < g.levels; ++l) {
                     const double rows = l == 0 ? (double)mp : (double)g.L(l - 1) * nbk;
-                    uf[l] += 4.0 * rows * nbk * ntr + 2.0 * nbk * nbk * ntr * g.L(l);
-                    ub[l] += (2.0 * rows * ntr + rows * nbk) * sizeof(T);
+                    const double f = 4.0 * rows * nbk * trail + 2.0 * (double)nbk * nbk * trail * g.L(l);
+                    const double b = (2.0 * rows * trail + rows * nbk) * sizeof(T);
+                    lf += f * share;
+                    lb += b * share;
+                    uf[l] += f * (1.0 - share);
+                    ub[l] += b * (1.0 - share);
                 }
             }
         }
+        if (maxL[0] == 0) continue;
         int pid = prof ? prof->begin(sc) : -1;
         hipLaunchKernelGGL(k_panel<T>, dim3(maxL[0], count), dim3(C::PT), 0, sc, d_descs, c0);
         if (prof) prof->end(pid, sc, PROF_PANEL, pf, pb);
-        if (maxtrail <= 0) continue;
-        auto run_levels = [&](hipStream_t st, int mode, int tiles, double share) {
-            for (int lev = 0; lev < maxlev; ++lev) {
-                const int rows = lev == 0 ? maxleaf : C::MT_MAX;
-                const dim3 grid(maxL[lev], tiles, count);
-                const int uid = prof ? prof->begin(st) : -1;
-                launch_update<T>(rows, grid, st, d_descs, c0, lev, mode);
-                if (prof) prof->end(uid, st, PROF_UPDATE, uf[lev] * share, ub[lev] * share);
-            }
-        };
-        if (!la || !next) {
-            if (rest_pending) {  // the previous rest update touches these columns
-                (void)hipStreamWaitEvent(sc, la->evR, 0);
-                rest_pending = false;
-            }
-            run_levels(sc, 0, (maxtrail + 63) / 64, 1.0);
-            continue;
+        if (la_groups == 0 && rest_tiles == 0) continue;
+        if (rest_pending) {  // REST(k-1) updated columns that LA(k) and REST(k) touch
+            (void)hipStreamWaitEvent(sc, la->evR, 0);
+            rest_pending = false;
         }
-        if (rest_pending) (void)hipStreamWaitEvent(sc, la->evR, 0);
-        const double f_la = maxtrail > 0 ? (double)C::NB / maxtrail : 0.0;
-        {
-            double lf = 0, lb = 0;
-            for (int lev = 0; lev < maxlev; ++lev) {
-                lf += uf[lev] * f_la;
-                lb += ub[lev] * f_la;
-            }
+        if (la_groups > 0) {
             const int lid = prof ? prof->begin(sc) : -1;
-            hipLaunchKernelGGL(k_la<T>, dim3(maxL[0], 2, count), dim3(256), 0, sc, d_descs, c0);
+            hipLaunchKernelGGL(k_la<T>, dim3(la_l0, la_groups, count), dim3(256), 0, sc, d_descs, c0);
             if (prof) prof->end(lid, sc, PROF_LA, lf, lb);
         }
-        // REST(k) is released after LA(k): a short LA launched while the
-        // large REST grid is being dispatched would wait for all of it
-        (void)hipEventRecord(la->evP, sc);
-        (void)hipStreamWaitEvent(la->rest, la->evP, 0);
-        // the next panel may be narrower than NB, so the rest can start
-        // anywhere in [c0 + nbk, c0 + nbk + NB]: size the grid for all trailing
-        // columns (tiles past a problem's range exit at once)
-        run_levels(la->rest, 2, (maxtrail + 63) / 64, 1.0 - f_la);
-        (void)hipEventRecord(la->evR, la->rest);
-        rest_pending = true;
+        if (rest_tiles == 0) continue;
+        hipStream_t st = sc;
+        const bool side = la && la_groups > 0 && overlap;
+        if (side) {
+            // REST(k) is released after LA(k): a short LA launched while the
+            // large REST grid is being dispatched would wait for all of it
+            (void)hipEventRecord(la->evP, sc);
+            (void)hipStreamWaitEvent(la->rest, la->evP, 0);
+            st = la->rest;
+        }
+        for (int lev = 0; lev < maxlev; ++lev) {
+            const int uid = prof ? prof->begin(st) : -1;
+            launch_update<T>(dim3(maxL[lev], rest_tiles, count), st, d_descs, c0, lev);
+            if (prof) prof->end(uid, st, PROF_UPDATE, uf[lev], ub[lev]);
+        }
+        if (side) {
+            (void)hipEventRecord(la->evR, la->rest);
+            rest_pending = true;
+        }
     }
     if (la) {
         if (rest_pending) (void)hipStreamWaitEvent(sc, la->evR, 0);

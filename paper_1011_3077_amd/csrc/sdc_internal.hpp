@@ -32,10 +32,13 @@ template <> struct QrCfg<float> {
 };
 
 constexpr int kMaxLevels = 5;
-// Tree arrival counters per problem: the panel factorization counts arrivals
-// at internal nodes in the first half, the look-ahead update (two column
-// groups) in [0, kMaxInternal / 2) and [kMaxInternal / 2, kMaxInternal).
+// Tree arrival counters per problem (kMaxInternal of them, zero between
+// uses: each is reset by its last arrival): the panel factorization counts
+// arrivals at internal nodes in the first kPanelCounters, the row-split
+// update (k_la, two 16-column groups) after them, one per (column group,
+// internal node) of the panel's tree.
 constexpr int kMaxInternal = 96;
+constexpr int kPanelCounters = 32;
 constexpr int kMaxPanelRows = 2 * 16384;  // augmented matrices of order <= 16384
 
 // Tree shape of a panel with mp rows: L0 leaves, levels levels, and
@@ -88,7 +91,10 @@ template <typename T> constexpr int max_internal_nodes() {
     }
     return total;
 }
-static_assert(max_internal_nodes<double>() <= kMaxInternal / 2 && max_internal_nodes<float>() <= kMaxInternal / 2,
+static_assert(max_internal_nodes<double>() <= kPanelCounters && max_internal_nodes<float>() <= kPanelCounters,
+              "panel counters");
+static_assert(kPanelCounters + 2 * max_internal_nodes<double>() <= kMaxInternal &&
+                  kPanelCounters + 2 * max_internal_nodes<float>() <= kMaxInternal,
               "two column groups of look-ahead counters per internal node");
 
 // Index of an internal node (level >= 1) in per-problem arrays.
@@ -98,6 +104,21 @@ __host__ __device__ inline int internal_index(const TreeGeomT<T>& g, int level, 
     for (int l = 1; l < level; ++l) off += g.L(l);
     return off + node;
 }
+// Which kernel updates which trailing columns after the panel at column c0
+// of a QR with nf factored columns: columns [c0 + nbk, c0 + nbk + la) go to
+// the row-split kernel (k_la), the rest to the wide kernel (k_update).  With
+// nf >= kLookaheadMinN the row-split kernel takes the next panel's columns
+// (look-ahead: they are done first, so that the next panel can be factored
+// beside the bulk update; below that size the bulk update is too short to
+// hide a panel).  The choice depends on the problem's own shape only, so a
+// problem rounds the same alone and in any batch.
+constexpr int kLookaheadMinN = 1200;
+__host__ __device__ inline int row_split_cols(int nb, int nf, int c0) {
+    const int cb = c0 + (nf - c0 < nb ? nf - c0 : nb);
+    if (nf < kLookaheadMinN || cb >= nf) return 0;
+    return nf - cb < nb ? nf - cb : nb;
+}
+
 // Index of any node in the per-problem T-factor array (leaves first).
 template <typename T>
 __host__ __device__ inline int node_index(const TreeGeomT<T>& g, int level, int node, int tm_leaves) {
