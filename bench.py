@@ -163,6 +163,87 @@ def serve_main(args):
     print(json.dumps(out))
 
 
+def suite_main(args):
+    """The other configurations of the measurement plan, one JSON line each
+    (not the headline line): the order-128 symmetric split (latency, FP64,
+    median of 10 after 3 warm-ups), 512 symmetric problems with n
+    log-uniform in [32, 256] in one batched FP32+refine call (median of 3
+    after 1 warm-up), and the clustered order-8192 symmetric split in FP64 and
+    in FP32+refine (one warm-up, one timed run each).  Nominal flops follow
+    the cost model of the headline metric for a symmetric split,
+    (40/3 p + 16) n^3 with p repeated-squaring iterations (refinement not
+    credited).  Single calls are timed by the library (info.ms, inside the C
+    call, inputs resident in HBM); the batched call by the host clock around it."""
+    import statistics
+    import numpy as np
+    import torch
+    import sdc_synth as S
+    import paper_1011_3077_amd as P
+
+    h = P.Handle(0)
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+    half = P.region("halfplane", shift=0.0, scale=1.0)
+    sym_flops = lambda n, p: (40.0 / 3.0 * p + 16.0) * float(n) ** 3
+
+    def line(name, dtype, ms, flops, extra):
+        out = {"metric": f"{name}: split GFLOP/s (nominal split flops / time)", "value": flops / ms / 1e6,
+               "unit": "GFLOP/s", "ms": ms, "higher_is_better": True, "n_gpus": 1, "dtype": dtype,
+               "data": "synthetic", "pct_peak": flops / ms / 1e6 / (
+                   (PEAK["fp32_tflops"] if dtype.startswith("f32") else PEAK["fp64_tflops"]) * 1e3)}
+        out.update(extra)
+        print(json.dumps(out), flush=True)
+
+    # order 128, FP64: latency
+    a, d, q = S.sym_problem(128, S.family_seed(0))
+    A = dev(a)
+    runs = []
+    for i in range(13):
+        r = h.split_sym(A, half, P.opts(seed=1))
+        if i >= 3:
+            runs.append(r)
+    ms = statistics.median(r.info["ms"] for r in runs)
+    ok = all(r.status == 0 and r.info["k_lead"] == int((d > 0).sum()) for r in runs)
+    line("symmetric split, order 128", "f64", ms, sym_flops(128, runs[0].info["iters_right"]),
+         {"config": {"workload": "symmetric split of one order-128 problem at the half plane Re z < 0"},
+          "iters": runs[0].info["iters_right"], "exact_rank": ok})
+
+    # 512 batched, FP32 + refine
+    sizes = S.batch_sizes(512, S.family_seed(2))
+    probs = [S.sym_problem(n, S.family_seed(2, i)) for i, n in enumerate(sizes)]
+    As = [dev(x) for x, _, _ in probs]
+    regs = [half] * len(sizes)
+    o = P.opts(prec=P.SDC_FP32_REFINE, seed=3)
+    times = []
+    for i in range(4):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = h.split_sym_batched(As, regs, o)
+        torch.cuda.synchronize()
+        if i >= 1:
+            times.append((time.perf_counter() - t0) * 1e3)
+    ms = statistics.median(times)
+    flops = sum(sym_flops(n, r.info["iters_right"]) for n, r in zip(sizes, out))
+    ok = all(r.status == 0 and r.info["k_lead"] == int((dd > 0).sum()) for r, (_, dd, _) in zip(out, probs))
+    line("batched symmetric splits, 512 problems", "f32+f64-refine", ms, flops,
+         {"config": {"workload": "512 symmetric problems, n log-uniform in [32, 256], one batched call, "
+                                 "half plane Re z < 0", "n_min": min(sizes), "n_max": max(sizes)},
+          "exact_rank": ok, "fp64_fallbacks": sum(r.info.get("fp64_fallback", 0) for r in out)})
+
+    # order 8192 clustered, FP64 and FP32 + refine
+    a, d, q = S.clustered_sym_problem(8192, S.family_seed(3))
+    A = dev(a)
+    del q
+    for prec, dtype in ((P.SDC_FP64, "f64"), (P.SDC_FP32_REFINE, "f32+f64-refine")):
+        h.split_sym(A, half, P.opts(prec=prec, seed=1))
+        r = h.split_sym(A, half, P.opts(prec=prec, seed=1))
+        line("symmetric split, clustered order 8192", dtype, r.info["ms"], sym_flops(8192, r.info["iters_right"]),
+             {"config": {"workload": "clustered symmetric order-8192 problem (half the eigenvalues on each side "
+                                     "of 0, 5% per side within 1e-3 of +-0.01), half plane Re z < 0"},
+              "iters": r.info["iters_right"], "refine_rounds": r.info["refine_rounds"],
+              "exact_rank": r.status == 0 and r.info["k_lead"] == int((d > 0).sum())})
+    h.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -175,6 +256,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (reference kernel for HBM counters)")
     ap.add_argument("--serve", action="store_true", help="serving benchmark instead (see serve_main)")
+    ap.add_argument("--suite", action="store_true",
+                    help="the other measured configurations instead, one JSON line each (see suite_main)")
     ap.add_argument("--rate", type=float, default=4.0, help="--serve: Poisson arrival rate, requests/s")
     ap.add_argument("--duration", type=float, default=15.0, help="--serve: seconds of arrivals")
     ap.add_argument("--nmin", type=int, default=64)
@@ -182,7 +265,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(the independent subproblems would shard across GPUs, see DESIGN.md)", file=sys.stderr)
+              f"(the independent subproblems would shard across GPUs; a single large split would split its rows)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -193,6 +276,8 @@ def main():
 
     if args.serve:
         return serve_main(args)
+    if args.suite:
+        return suite_main(args)
     if args.calibrate_copy:
         x = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
         y = torch.empty_like(x)

@@ -210,6 +210,28 @@ sdc_status_t sdc_eig_dc(sdc_handle_t h, int n, const double* A, int lda, const d
                         double* S, int lds, double* QL, int ldql, double* QR, int ldqr,
                         int* nblocks, int* block_start, sdc_dc_info_t* info);
 
+/* Eigenvalues of the diagonal blocks of a block upper-triangular T (and S)
+ * as sdc_eig_dc returns them: the recursion of Sec. 3.3-3.5 stops at blocks
+ * small enough for a standard dense method, and this is that method.
+ *   symmetric != 0: each block of T of order <= 128 is symmetrized and
+ *     diagonalized by cyclic Jacobi (rotations in round-robin order, to an
+ *     off-diagonal norm of 1e-15 of the block's); its eigenvalues go to
+ *     wr[start .. start + m) in ascending order, wi = 0.  S is not read.
+ *   symmetric == 0: each block pair (T_bb, S_bb) of order 1 or 2 gives the
+ *     roots of det(T_bb - lambda S_bb) = 0 (order 2: real roots ascending; a
+ *     complex pair as (re, +im), (re, -im); an infinite eigenvalue, for a
+ *     singular S_bb, as +-inf).  Run sdc_eig_dc with leaf_max = 2 to reduce
+ *     a pencil that far.
+ *   Any other block (symmetric above order 128, pencil above order 2) gets
+ *   NaN in wr and wi.
+ * T, S, wr, wi are device pointers (column-major T and S with leading
+ * dimensions ldt, lds >= n; wr, wi hold n doubles each, caller-owned);
+ * block_start is a HOST array of nblocks + 1 increasing ints from 0 to n.
+ * Returns SDC_OK, or SDC_ERR_INVALID for inconsistent arguments (nothing
+ * written). */
+sdc_status_t sdc_block_eigvals(sdc_handle_t h, int n, const double* T, int ldt, const double* S, int lds,
+                               int nblocks, const int* block_start, int symmetric, double* wr, double* wi);
+
 /* Per-kernel timing (opt-in).  With profiling enabled every launch of the
  * hot kernels is bracketed by HIP events on the handle's stream and its
  * algorithmic work is recorded: kernel 0 = tree-level trailing update of the

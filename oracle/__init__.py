@@ -27,3 +27,4 @@ from .rurv import haar_from_gaussian, rurv, rulv, grurv2  # noqa: F401
 from .split import (premap, split_search, split_sym, split_pencil, SplitResult,  # noqa: F401
                     rank_from_rho, norm1, OK, NOT_CONVERGED, NO_SPLIT, RANK_AMBIGUOUS)
 from .philox import philox4x32_10, gaussian_matrix  # noqa: F401
+from .eig_dc import eig_dc, block_eigvals  # noqa: F401

@@ -129,3 +129,30 @@ def eig_dc(a: np.ndarray, b: np.ndarray | None = None, symmetric: bool = False, 
     leaves.sort(key=lambda x: x["s"])
     return dict(T=t, S=s, QL=None if symmetric else ql, QR=qr, blocks=[(x["s"], x["e"]) for x in leaves],
                 splits=splits, unsplit=unsplit)
+
+
+def block_eigvals(t: np.ndarray, s: np.ndarray | None, starts, symmetric: bool):
+    """Eigenvalues of the diagonal blocks of a block upper-triangular pair,
+    the dense method the recursion of Sec. 3.3-3.5 hands its small blocks to.
+    Symmetric: each block symmetrized, its eigenvalues ascending (LAPACK
+    eigvalsh, a library primitive).  Pencil: the generalized eigenvalues of
+    each block pair (LAPACK eigvals), real ones ascending, a complex pair as
+    (re, +im), (re, -im).  Returns (wr, wi), each of length n."""
+    import scipy.linalg as sla
+    n = t.shape[0]
+    wr, wi = np.empty(n), np.empty(n)
+    for a0, a1 in zip(starts[:-1], starts[1:]):
+        blk = np.asarray(t[a0:a1, a0:a1], dtype=np.float64)
+        if symmetric:
+            wr[a0:a1] = np.linalg.eigvalsh(0.5 * (blk + blk.T))
+            wi[a0:a1] = 0.0
+            continue
+        ev = sla.eigvals(blk, np.asarray(s[a0:a1, a0:a1], dtype=np.float64))
+        real = sorted(z.real for z in ev if z.imag == 0.0)
+        pairs = sorted((z.real, abs(z.imag)) for z in ev if z.imag > 0.0)
+        out = [(x, 0.0) for x in real]
+        for x, y in pairs:
+            out += [(x, y), (x, -y)]
+        wr[a0:a1] = [x for x, _ in out]
+        wi[a0:a1] = [y for _, y in out]
+    return wr, wi

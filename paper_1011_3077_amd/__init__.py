@@ -28,7 +28,8 @@ SDC_FP64, SDC_FP32_REFINE = 0, 1
 SDC_UNIT_DISK, SDC_DISK, SDC_HALFPLANE = 0, 1, 2
 
 EXPORTED = ["sdc_opts_default", "sdc_create", "sdc_destroy", "sdc_status_string", "sdc_irs",
-            "sdc_split_sym", "sdc_split_pencil", "sdc_split_sym_batched", "sdc_eig_dc", "sdc_gaussian",
+            "sdc_split_sym", "sdc_split_pencil", "sdc_split_sym_batched", "sdc_eig_dc", "sdc_block_eigvals",
+            "sdc_gaussian",
             "sdc_profile_enable", "sdc_profile_read", "sdc_server_create", "sdc_server_submit",
             "sdc_server_poll", "sdc_server_wait", "sdc_server_stats", "sdc_server_destroy"]
 SDC_REQ_SYM, SDC_REQ_PENCIL = 0, 1
@@ -117,6 +118,8 @@ lib.sdc_split_sym_batched.restype = _I
 lib.sdc_eig_dc.argtypes = [_P, _I, _P, _I, _P, _I, _I, _I, C.POINTER(Opts), _P, _I, _P, _I, _P, _I, _P, _I,
                            C.POINTER(_I), C.POINTER(_I), C.POINTER(DcInfo)]
 lib.sdc_eig_dc.restype = _I
+lib.sdc_block_eigvals.argtypes = [_P, _I, _P, _I, _P, _I, _I, C.POINTER(_I), _I, _P, _P]
+lib.sdc_block_eigvals.restype = _I
 lib.sdc_profile_enable.argtypes = [_P, _I]
 lib.sdc_profile_enable.restype = _I
 lib.sdc_profile_read.argtypes = [_P, _I, C.POINTER(KernelStats)]
@@ -281,6 +284,21 @@ class Handle:
                                    C.byref(nb), starts, C.byref(info)))
         tr = lambda x: None if x is None else x.t()
         return st, tr(t), tr(s), tr(ql), tr(qr), [starts[i] for i in range(nb.value + 1)], info.as_dict()
+
+    def block_eigvals(self, T, S, starts, symmetric: bool = False):
+        """Eigenvalues of the diagonal blocks of eig_dc's T (and S): returns
+        (wr, wi), two length-n float64 device tensors (see sdc_block_eigvals)."""
+        import torch
+        n = T.shape[0]
+        t = _cm(T)
+        s = _cm(S) if (S is not None and not symmetric) else None
+        nb = len(starts) - 1
+        st = (_I * (nb + 1))(*starts)
+        wr = torch.empty(n, dtype=torch.float64, device=T.device)
+        wi = torch.empty(n, dtype=torch.float64, device=T.device)
+        _check(lib.sdc_block_eigvals(self._h, n, t.data_ptr(), n, None if s is None else s.data_ptr(), n, nb, st,
+                                     int(symmetric), wr.data_ptr(), wi.data_ptr()))
+        return wr, wi
 
     def profile_enable(self, on: bool = True):
         _check(lib.sdc_profile_enable(self._h, int(on)))

@@ -265,4 +265,14 @@ sdc_status_t sdc_gaussian(sdc_handle_t hd, int n, uint64_t seed, int tag, double
     return (sdc_status_t)sdc::run_gaussian(h, n, seed, tag, G, ldg);
 }
 
+sdc_status_t sdc_block_eigvals(sdc_handle_t hd, int n, const double* T, int ldt, const double* S, int lds,
+                               int nblocks, const int* block_start, int symmetric, double* wr, double* wi) {
+    if (!hd || n < 1 || !T || ldt < n || (!symmetric && (!S || lds < n)) || nblocks < 1 || nblocks > n ||
+        !block_start || !wr || !wi)
+        return SDC_ERR_INVALID;
+    Handle& h = hd->h;
+    if (use_device(h) != SDC_OK) return SDC_ERR_DEVICE;
+    return (sdc_status_t)sdc::run_block_eigvals(h, n, T, ldt, S, lds, nblocks, block_start, symmetric != 0, wr, wi);
+}
+
 }  // extern "C"

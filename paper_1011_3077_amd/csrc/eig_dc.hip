@@ -359,4 +359,33 @@ int run_eig_dc(Handle& h, int n, const double* A, int lda, const double* B, int 
     return SDC_OK;
 }
 
+int run_block_eigvals(Handle& h, int n, const double* T, int ldt, const double* S, int lds, int nblocks,
+                      const int* block_start, int symmetric, double* wr, double* wi) {
+    if (nblocks < 1 || block_start[0] != 0 || block_start[nblocks] != n) return SDC_ERR_INVALID;
+    for (int b = 0; b < nblocks; ++b)
+        if (block_start[b + 1] <= block_start[b]) return SDC_ERR_INVALID;
+    CHK(ensure_desc(h, sizeof(BlockEigDesc) * (size_t)nblocks + 4096));
+    h.desc_off = 0;
+    std::vector<BlockEigDesc> v(nblocks);
+    for (int b = 0; b < nblocks; ++b) {
+        const int s0 = block_start[b];
+        BlockEigDesc& d = v[b];
+        d.T = T + s0 + (size_t)s0 * ldt;
+        d.ldt = ldt;
+        d.S = symmetric ? nullptr : S + s0 + (size_t)s0 * lds;
+        d.lds = lds;
+        d.m = block_start[b + 1] - s0;
+        d.symmetric = symmetric;
+        d.wr = wr + s0;
+        d.wi = wi + s0;
+        d.active = 1;
+    }
+    UPLOAD(dd, v);
+    block_eig_batch(dd, v.data(), nblocks, h.stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h.stream));
+    h.desc_off = 0;
+    return SDC_OK;
+}
+
 }  // namespace sdc

@@ -102,6 +102,8 @@ int run_irs_only(Handle& h, int n, const double* A, int lda, const double* B, in
                  int ldo, int* p, double* rconv);
 
 int run_gaussian(Handle& h, int n, uint64_t seed, int tag, double* G, int ldg);
+int run_block_eigvals(Handle& h, int n, const double* T, int ldt, const double* S, int lds, int nblocks,
+                      const int* block_start, int symmetric, double* wr, double* wi);
 
 // Incremental driver (continuous batching).  A JobRun holds one split job's
 // state in a caller-provided device workspace of job_run_bytes() bytes; each

@@ -60,6 +60,20 @@ struct GershDesc {
 };
 void gersh_batch(const GershDesc* d, const GershDesc* h, int count, hipStream_t s);
 
+// Eigenvalues of one diagonal block of a block upper-triangular pair
+// (leaf_kernels.hip): a symmetric block of order <= kJacobiMax by cyclic
+// Jacobi, a pencil block (T, S) of order 1 or 2 in closed form, NaN for any
+// other block.  T and S point at the block's first element (column-major).
+constexpr int kJacobiMax = 128;
+struct BlockEigDesc {
+    const double* T; int ldt;
+    const double* S; int lds;   // pencil only
+    int m, symmetric;
+    double* wr; double* wi;     // m values each
+    int active;
+};
+void block_eig_batch(const BlockEigDesc* d, const BlockEigDesc* h, int count, hipStream_t s);
+
 // Conjugate gradients on X A11 - A22 X = E (refine_kernels.hip).  X, R, P, Z
 // are m x k, contiguous (ld m); E has leading dimension lde.  rr is a ring of
 // 3 x kCgMaxBlocks partial sums (slot it % 3 holds rr_it), rr0 and pz hold

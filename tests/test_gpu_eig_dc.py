@@ -118,6 +118,78 @@ def test_eig_dc_symmetric(handle, sdc):
     assert np.linalg.norm(qr.T @ a @ qr - t, 2) <= 1e-11
 
 
+def _match_max(got, want):
+    """Largest distance after greedily pairing each computed eigenvalue with
+    the nearest unused one of the construction."""
+    want = list(want)
+    worst = 0.0
+    for z in got:
+        j = int(np.argmin([abs(z - w) for w in want]))
+        worst = max(worst, abs(z - want.pop(j)))
+    return worst
+
+
+@pytest.mark.parametrize("n,leaf", [(300, 64), (97, 16), (128, 128)])
+def test_block_eigvals_symmetric_leaves(handle, sdc, n, leaf):
+    """Cyclic Jacobi on the leaves of a symmetric recursion (even and odd
+    orders, down to the largest block the kernel takes, 128): each block's
+    eigenvalues, ascending, equal the oracle's (LAPACK) on the same T within
+    1e-13 |A|_2, and together they are the construction's spectrum."""
+    from oracle.eig_dc import block_eigvals
+    print("CASE block_eigvals symmetric", n, leaf, flush=True)
+    a, d, _ = S.sym_problem(n, S.family_seed(0, 70 + n))
+    st, t, s, ql, qr, starts, info = handle.eig_dc(dev(a), None, leaf_max=leaf, symmetric=True,
+                                                    o=sdc.opts(seed=8))
+    assert st == 0
+    wr, wi = handle.block_eigvals(t, None, starts, symmetric=True)
+    wr, wi = wr.cpu().numpy(), wi.cpu().numpy()
+    ref_r, ref_i = block_eigvals(t.cpu().numpy(), None, starts, True)
+    assert np.all(wi == 0.0)
+    assert np.abs(wr - ref_r).max() <= 1e-13 * np.abs(d).max()
+    assert np.abs(np.sort(wr) - np.sort(d)).max() <= 1e-12
+
+
+def test_block_eigvals_pencil_to_order_two(handle, sdc):
+    """A real normal matrix with complex-conjugate pairs (and one real
+    eigenvalue, order 41) as the pencil (A, I), recursed to blocks of order
+    <= 2: the closed forms give every eigenvalue (pairs as (re, +-im)) within
+    1e-9 of the construction, and match the oracle's on the same blocks."""
+    from oracle.eig_dc import block_eigvals
+    n = 41
+    print("CASE block_eigvals pencil", n, flush=True)
+    a, ev = S.normal_random_problem(n, S.family_seed(1, 41))
+    b = np.eye(n)
+    st, t, s, ql, qr, starts, info = handle.eig_dc(dev(a), dev(b), leaf_max=2, o=sdc.opts(seed=6))
+    assert st == 0
+    assert all(e - s0 <= 2 for s0, e in zip(starts[:-1], starts[1:])), info
+    wr, wi = handle.block_eigvals(t, s, starts, symmetric=False)
+    wr, wi = wr.cpu().numpy(), wi.cpu().numpy()
+    got = wr + 1j * wi
+    assert _match_max(got, ev) <= 1e-9
+    ref_r, ref_i = block_eigvals(t.cpu().numpy(), s.cpu().numpy(), starts, False)
+    assert np.abs(got - (ref_r + 1j * ref_i)).max() <= 1e-11
+
+
+def test_block_eigvals_edges(handle, sdc):
+    """A symmetric block above the Jacobi limit and a pencil block above
+    order 2 give NaN; inconsistent block starts are rejected."""
+    print("CASE block_eigvals edges", flush=True)
+    a, d, _ = S.sym_problem(129, S.family_seed(0, 129))
+    A = dev(a)
+    wr, wi = handle.block_eigvals(A, None, [0, 129], symmetric=True)
+    assert torch.isnan(wr).all() and torch.isnan(wi).all()
+    wr, wi = handle.block_eigvals(A[:5, :5].contiguous(), None, [0, 1, 5], symmetric=True)
+    ref_r, _ = __import__("oracle.eig_dc", fromlist=["block_eigvals"]).block_eigvals(a[:5, :5], None, [0, 1, 5], True)
+    assert np.abs(wr.cpu().numpy() - ref_r).max() <= 1e-14
+    p = S.pencil_problem(6, S.family_seed(1, 6))
+    wr, wi = handle.block_eigvals(dev(p["A"]), dev(p["B"]), [0, 3, 6], symmetric=False)
+    assert torch.isnan(wr).all()
+    with pytest.raises(sdc.SdcError):
+        handle.block_eigvals(A, None, [0, 100], symmetric=True)
+    with pytest.raises(sdc.SdcError):
+        handle.block_eigvals(A, None, [0, 64, 64, 129], symmetric=True)
+
+
 def test_eig_dc_benchmark_workload_full_size(handle, sdc):
     """Order-2048 pencil of the benchmark: unit circle, then blocks <= 64."""
     n, leaf = 2048, 64
