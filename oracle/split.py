@@ -223,3 +223,25 @@ def split_pencil(a: np.ndarray, b: np.ndarray, region: dict, gauss: GaussSource 
             return cand
     best.status = NOT_CONVERGED if not converged else RANK_AMBIGUOUS
     return best
+
+
+def split_svd(a: np.ndarray, region: dict, seed: int = 0, **kw):
+    """RSVD (the singular value problem, Sec. 3): one symmetric split step
+    (Alg. 6) of the embedding E = [0 A; A^T 0], whose eigenvalues are the
+    singular values of A, their negatives and |m - n| zeros, with
+    eigenvectors [u; v] / sqrt(2).  At a half plane Re z < tau (tau >= 0) the
+    leading k columns of E's Q span the pairs of the k singular values above
+    tau, so U = sqrt(2) Q[:m, :k] and V = sqrt(2) Q[m:, :k] are orthonormal
+    bases of the left and right singular subspaces and
+    S11 = Ahat[:k, :k] = U^T A V.  Returns (SplitResult of E, U, V, S11)."""
+    a = np.asarray(a, dtype=np.float64)
+    m, n = a.shape
+    e = np.zeros((m + n, m + n))
+    e[:m, m:] = a
+    e[m:, :m] = a.T
+    res = split_sym(e, region, seed=seed, **kw)
+    k = res.k
+    u = np.sqrt(2.0) * res.Q[:m, :k]
+    v = np.sqrt(2.0) * res.Q[m:, :k]
+    s11 = res.A_hat[:k, :k]
+    return res, u, v, s11

@@ -62,6 +62,28 @@ def sym_problem(n: int, seed: int, gap: float = 0.05, lo: float = -1.0, hi: floa
     return np.asfortranarray(a), d, q
 
 
+def svd_problem(m: int, n: int, seed: int, level: float = 1.0, gap: float = 0.05,
+                lo: float = 0.1, hi: float = 10.0):
+    """m x n A = P diag(sigma) Q^T with P (m x r), Q (n x r) orthonormal
+    columns of Haar matrices, r = min(m, n), and sigma log-uniform in [lo, hi]
+    excluding [level (1 - gap), level (1 + gap)], in decreasing order.
+    Returns (A, sigma, P, Q)."""
+    rng = np.random.default_rng(seed)
+    r = min(m, n)
+    p_ = haar_orthogonal(m, rng)[:, :r]
+    q_ = haar_orthogonal(n, rng)[:, :r]
+    sig = np.empty(r)
+    for i in range(r):
+        while True:
+            x = math.exp(rng.uniform(math.log(lo), math.log(hi)))
+            if abs(x - level) > gap * level:
+                break
+        sig[i] = x
+    sig = np.sort(sig)[::-1]
+    a = (p_ * sig[None, :]) @ q_.T
+    return np.asfortranarray(a), sig, p_, q_
+
+
 def clustered_sym_problem(n: int, seed: int):
     """Symmetric, eigenvalues half in [-1,-0.01] and half in [0.01,1], with
     10% of them (5% per side) within 1e-3 of +-0.01, i.e. |d| in

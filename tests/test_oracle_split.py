@@ -183,3 +183,31 @@ def test_rank_from_rho_cases():
     assert rank_from_rho(np.full(5, 0.9))[2] == "outside"
     k, gap, side = rank_from_rho(np.array([0.5, 0.1, 0.02, 1e-14, 1e-15]))
     assert side == "split" and k == 3 and gap > 1e10
+
+
+# ---------------------------------------------------------------------------
+# RSVD by the symmetric embedding, pinned to LAPACK's SVD of the construction
+# ---------------------------------------------------------------------------
+
+def _sin_theta(x, y):
+    qx, _ = np.linalg.qr(x)
+    qy, _ = np.linalg.qr(y)
+    return float(np.linalg.norm(qy - qx @ (qx.T @ qy), 2))
+
+
+@pytest.mark.parametrize("m,n", [(30, 20), (20, 30), (24, 24)])
+def test_split_svd_recovers_singular_subspaces(m, n):
+    from oracle.split import split_svd
+    import sdc_synth as S
+    a, sig, p_, q_ = S.svd_problem(m, n, S.family_seed(5, m * 100 + n), level=1.0)
+    res, u, v, s11 = split_svd(a, {"kind": "halfplane", "shift": 1.0, "scale": 1.0}, seed=2)
+    k = int((sig > 1.0).sum())
+    assert res.status == 0 and res.k == k and 0 < k < min(m, n)
+    assert np.abs(u.T @ u - np.eye(k)).max() <= 1e-12
+    assert np.abs(v.T @ v - np.eye(k)).max() <= 1e-12
+    # the subspaces of LAPACK's SVD (independent of the construction's basis)
+    pu, sv, qvt = np.linalg.svd(a)
+    assert np.allclose(sv[:len(sig)], sig, rtol=1e-12)
+    assert _sin_theta(u, pu[:, :k]) <= 1e-10 and _sin_theta(v, qvt[:k].T) <= 1e-10
+    assert np.abs(np.linalg.eigvalsh(s11) - np.sort(sig[:k])).max() <= 1e-11 * sig[0]
+    assert np.abs(u.T @ a @ v - s11).max() <= 1e-11 * sig[0]
