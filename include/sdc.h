@@ -210,6 +210,27 @@ sdc_status_t sdc_eig_dc(sdc_handle_t h, int n, const double* A, int lda, const d
                         double* S, int lds, double* QL, int ldql, double* QR, int ldqr,
                         int* nblocks, int* block_start, sdc_dc_info_t* info);
 
+/* RSVD split (the singular value problem of Sec. 3, through the symmetric
+ * embedding E = [0 A; A^T 0] of order m + n, whose eigenvalues are the
+ * singular values of A, their negatives and |m - n| zeros, with eigenvectors
+ * [u; v] / sqrt(2)).  One symmetric split step (as sdc_split_sym) of E at
+ * the half plane Re z < region.shift (kind SDC_HALFPLANE, shift >= 0; the
+ * scale as for sdc_split_sym) separates the k = info->k_lead singular values
+ * above the shift:
+ *   U (m x min(m,n), ldu >= m): columns 0..k-1 an orthonormal basis of the
+ *     left singular subspace of those values (sqrt(2) times E's Q rows 0..m-1);
+ *   V (n x min(m,n), ldv >= n): the right one (E's Q rows m..m+n-1);
+ *   S11 (min(m,n) x min(m,n), lds11 >= min(m,n)): leading k x k block
+ *     U^T A V (symmetric; its eigenvalues are the k singular values), zero
+ *     elsewhere; the columns of U and V after k are zero.
+ * A, U, V, S11 are device pointers, column-major, caller-owned; the
+ * library's workspace grows by 3 (m + n)^2 doubles.  m + n <= 16384.
+ * Statuses as for sdc_split_sym (SDC_NO_SPLIT when no singular value, or
+ * every one, lies above the shift); SDC_ERR_INVALID for bad arguments. */
+sdc_status_t sdc_split_svd(sdc_handle_t h, int m, int n, const double* A, int lda, sdc_region_t region,
+                           const sdc_opts_t* opts, double* U, int ldu, double* V, int ldv, double* S11, int lds11,
+                           sdc_info_t* info);
+
 /* Eigenvalues of the diagonal blocks of a block upper-triangular T (and S)
  * as sdc_eig_dc returns them: the recursion of Sec. 3.3-3.5 stops at blocks
  * small enough for a standard dense method, and this is that method.

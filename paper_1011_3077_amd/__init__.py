@@ -28,7 +28,8 @@ SDC_FP64, SDC_FP32_REFINE = 0, 1
 SDC_UNIT_DISK, SDC_DISK, SDC_HALFPLANE = 0, 1, 2
 
 EXPORTED = ["sdc_opts_default", "sdc_create", "sdc_destroy", "sdc_status_string", "sdc_irs",
-            "sdc_split_sym", "sdc_split_pencil", "sdc_split_sym_batched", "sdc_eig_dc", "sdc_block_eigvals",
+            "sdc_split_sym", "sdc_split_pencil", "sdc_split_sym_batched", "sdc_split_svd", "sdc_eig_dc",
+            "sdc_block_eigvals",
             "sdc_gaussian",
             "sdc_profile_enable", "sdc_profile_read", "sdc_server_create", "sdc_server_submit",
             "sdc_server_poll", "sdc_server_wait", "sdc_server_stats", "sdc_server_destroy"]
@@ -118,6 +119,8 @@ lib.sdc_split_sym_batched.restype = _I
 lib.sdc_eig_dc.argtypes = [_P, _I, _P, _I, _P, _I, _I, _I, C.POINTER(Opts), _P, _I, _P, _I, _P, _I, _P, _I,
                            C.POINTER(_I), C.POINTER(_I), C.POINTER(DcInfo)]
 lib.sdc_eig_dc.restype = _I
+lib.sdc_split_svd.argtypes = [_P, _I, _I, _P, _I, Region, C.POINTER(Opts), _P, _I, _P, _I, _P, _I, C.POINTER(Info)]
+lib.sdc_split_svd.restype = _I
 lib.sdc_block_eigvals.argtypes = [_P, _I, _P, _I, _P, _I, _I, C.POINTER(_I), _I, _P, _P]
 lib.sdc_block_eigvals.restype = _I
 lib.sdc_profile_enable.argtypes = [_P, _I]
@@ -284,6 +287,24 @@ class Handle:
                                    C.byref(nb), starts, C.byref(info)))
         tr = lambda x: None if x is None else x.t()
         return st, tr(t), tr(s), tr(ql), tr(qr), [starts[i] for i in range(nb.value + 1)], info.as_dict()
+
+    def split_svd(self, A, reg: Region | None = None, o: Opts | None = None):
+        """RSVD split of the m x n A at the half plane reg (see sdc_split_svd):
+        returns (status, info, U, V, S11) with U m x r, V n x r, S11 r x r
+        (r = min(m, n)), of which the first info["k_lead"] columns are valid."""
+        import torch
+        if not (A.is_cuda and A.dtype == torch.float64 and A.dim() == 2):
+            raise TypeError("expected a 2-D float64 tensor on a HIP device")
+        m, n = A.shape
+        r = min(m, n)
+        a = A.t().contiguous()
+        u = torch.empty((r, m), dtype=torch.float64, device=A.device)
+        v = torch.empty((r, n), dtype=torch.float64, device=A.device)
+        s11 = torch.empty((r, r), dtype=torch.float64, device=A.device)
+        info = Info()
+        st = _check(lib.sdc_split_svd(self._h, m, n, a.data_ptr(), m, reg or region("halfplane"), C.byref(o or opts()),
+                                      u.data_ptr(), m, v.data_ptr(), n, s11.data_ptr(), r, C.byref(info)))
+        return st, info.as_dict(), u.t(), v.t(), s11.t()
 
     def block_eigvals(self, T, S, starts, symmetric: bool = False):
         """Eigenvalues of the diagonal blocks of eig_dc's T (and S): returns

@@ -2,6 +2,7 @@
 // and translation to the engine's jobs.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <new>
 #include <vector>
@@ -263,6 +264,28 @@ sdc_status_t sdc_gaussian(sdc_handle_t hd, int n, uint64_t seed, int tag, double
     Handle& h = hd->h;
     if (use_device(h) != SDC_OK) return SDC_ERR_DEVICE;
     return (sdc_status_t)sdc::run_gaussian(h, n, seed, tag, G, ldg);
+}
+
+sdc_status_t sdc_split_svd(sdc_handle_t hd, int m, int n, const double* A, int lda, sdc_region_t region,
+                           const sdc_opts_t* opts, double* U, int ldu, double* V, int ldv, double* S11, int lds11,
+                           sdc_info_t* info) {
+    const int r = std::min(m, n);
+    if (!hd || m < 1 || n < 1 || m + n > kMaxN || !A || !U || !V || !S11 || lda < m || ldu < m || ldv < n ||
+        lds11 < r || !region_ok(region) || region.kind != SDC_HALFPLANE || region.shift < 0.0)
+        return SDC_ERR_INVALID;
+    sdc_info_t dummy;
+    if (!info) info = &dummy;
+    *info = sdc_info_t{};
+    Handle& h = hd->h;
+    if (use_device(h) != SDC_OK) return SDC_ERR_DEVICE;
+    const sdc_opts_t o = resolve(opts);
+    if (!prec_ok(o, false)) return SDC_ERR_INVALID;
+    int status = 0;
+    sdc::ProfScope ps(h);
+    const int rc = sdc::run_split_svd(h, m, n, A, lda, region, o, U, ldu, V, ldv, S11, lds11, info, &status);
+    resolve_profile(h);
+    if (rc < 0) return (sdc_status_t)rc;
+    return (sdc_status_t)status;
 }
 
 sdc_status_t sdc_block_eigvals(sdc_handle_t hd, int n, const double* T, int ldt, const double* S, int lds,

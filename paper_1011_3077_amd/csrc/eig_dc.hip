@@ -359,6 +359,61 @@ int run_eig_dc(Handle& h, int n, const double* A, int lda, const double* B, int 
     return SDC_OK;
 }
 
+// RSVD split: one symmetric split step of E = [0 A; A^T 0] (order m + n),
+// then U = sqrt(2) Q[:m, :k], V = sqrt(2) Q[m:, :k], S11 = Ahat[:k, :k].
+int run_split_svd(Handle& h, int m, int n, const double* A, int lda, const sdc_region_t& region,
+                  const sdc_opts_t& opts, double* U, int ldu, double* V, int ldv, double* S11, int lds11,
+                  sdc_info_t* info, int* status) {
+    const int p = m + n, r = std::min(m, n);
+    const size_t pp = (size_t)p * p;
+    CHK(ensure_ws2(h, 3 * pp * sizeof(double) + 4096));
+    CHK(ensure_desc(h, (size_t)(64 << 10)));
+    h.desc_off = 0;
+    double* E = reinterpret_cast<double*>(h.ws2);
+    double* QE = E + pp;
+    double* AE = QE + pp;
+    {
+        std::vector<EwDesc> z(1);
+        z[0] = zero_desc(p, p, E, p);
+        CHK(launch_ew(h, z));
+        std::vector<EwDesc> c(2);
+        c[0] = copy_desc(m, n, A, lda, E + (size_t)m * p, p);  // E[:m, m:] = A
+        c[1] = copy_desc(n, m, A, lda, E + m, p);              // E[m:, :m] = A^T
+        c[1].trans = 1;
+        CHK(launch_ew(h, c));
+    }
+    std::vector<SplitJob> jobs(1);
+    SplitJob& j = jobs[0];
+    j.n = p; j.pencil = false; j.A = E; j.lda = p; j.region = region; j.opts = opts;
+    j.Q = QE; j.ldq = p; j.Ahat = AE; j.ldah = p;
+    CHK(run_split_jobs(h, jobs));
+    h.desc_off = 0;
+    const int k = std::max(0, std::min(j.info.k_lead, r));
+    std::vector<EwDesc> out;
+    EwDesc cu = copy_desc(m, k, QE, p, U, ldu);
+    cu.alpha = std::sqrt(2.0);
+    EwDesc cv = copy_desc(n, k, QE + m, p, V, ldv);
+    cv.alpha = std::sqrt(2.0);
+    if (k > 0) {
+        out.push_back(cu);
+        out.push_back(cv);
+        out.push_back(copy_desc(k, k, AE, p, S11, lds11));
+    }
+    if (k < r) {
+        out.push_back(zero_desc(m, r - k, U + (size_t)k * ldu, ldu));
+        out.push_back(zero_desc(n, r - k, V + (size_t)k * ldv, ldv));
+        out.push_back(zero_desc(r, r - k, S11 + (size_t)k * lds11, lds11));
+        if (k > 0) out.push_back(zero_desc(r - k, k, S11 + k, lds11));
+    }
+    CHK(launch_ew(h, out));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h.stream));
+    h.desc_off = 0;
+    *info = j.info;
+    *status = j.status;
+    return SDC_OK;
+}
+
 int run_block_eigvals(Handle& h, int n, const double* T, int ldt, const double* S, int lds, int nblocks,
                       const int* block_start, int symmetric, double* wr, double* wi) {
     if (nblocks < 1 || block_start[0] != 0 || block_start[nblocks] != n) return SDC_ERR_INVALID;

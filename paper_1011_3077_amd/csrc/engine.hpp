@@ -102,6 +102,9 @@ int run_irs_only(Handle& h, int n, const double* A, int lda, const double* B, in
                  int ldo, int* p, double* rconv);
 
 int run_gaussian(Handle& h, int n, uint64_t seed, int tag, double* G, int ldg);
+int run_split_svd(Handle& h, int m, int n, const double* A, int lda, const sdc_region_t& region,
+                  const sdc_opts_t& opts, double* U, int ldu, double* V, int ldv, double* S11, int lds11,
+                  sdc_info_t* info, int* status);
 int run_block_eigvals(Handle& h, int n, const double* T, int ldt, const double* S, int lds, int nblocks,
                       const int* block_start, int symmetric, double* wr, double* wi);
 
