@@ -24,7 +24,8 @@ beyond what the paper's algorithms state.
 from .qr import (householder_qr_loop, qr_signed, rq_signed, ql_signed)  # noqa: F401
 from .irs import irs, IRSResult  # noqa: F401
 from .rurv import haar_from_gaussian, rurv, rulv, grurv2  # noqa: F401
-from .split import (premap, split_search, split_sym, split_pencil, split_svd, SplitResult,  # noqa: F401
+from .split import (premap, split_search, split_sym, split_pencil, split_svd, split_nonsym,
+                    SplitResult,  # noqa: F401
                     rank_from_rho, norm1, OK, NOT_CONVERGED, NO_SPLIT, RANK_AMBIGUOUS)
 from .philox import philox4x32_10, gaussian_matrix  # noqa: F401
 from .eig_dc import eig_dc, block_eigvals  # noqa: F401

@@ -245,3 +245,43 @@ def split_svd(a: np.ndarray, region: dict, seed: int = 0, **kw):
     v = np.sqrt(2.0) * res.Q[m:, :k]
     s11 = res.A_hat[:k, :k]
     return res, u, v, s11
+
+
+def split_nonsym(a: np.ndarray, region: dict, gauss: GaussSource | None = None, seed: int = 0,
+                 tau: float | None = None, maxit: int = 60, max_retries: int = 2,
+                 split_tol: float | None = None) -> SplitResult:
+    """RNEP (the non-symmetric standard problem, B = I; the paragraph after
+    Alg. 4): the right side of Alg. 4 only, since with B = I the left
+    deflating subspace equals the right one: IRS of the mapped (A, I),
+    GRURV(2, A_p + B_p, A_p, -1, 1), A_hat = Q^T A Q (not symmetrized), and
+    the split point minimizing ||E21||_1 / ||A||_1, the backward error."""
+    tau, split_tol = _defaults(tau, split_tol)
+    a = np.asarray(a, dtype=np.float64)
+    n = a.shape[0]
+    gauss = gauss or philox_source(seed)
+    a0, b0 = premap(a, np.eye(n), region)
+    res = irs(a0, b0, tau=tau, maxit=maxit)
+    ap, bp = res.A, res.B
+    norm_a = norm1(a)
+    best = None
+    for attempt in range(max_retries + 1):
+        g = gauss(n, attempt, 0)
+        q, r1, r2, _ = grurv2(ap + bp, ap, -1, 1, g)
+        rho = np.abs(np.diag(r2)) / np.abs(np.diag(r1))
+        k_rho, gap, side = rank_from_rho(rho)
+        a_hat = q.T @ a @ q
+        if side != "split":
+            k = 0 if side == "inside" else n
+            return SplitResult(NO_SPLIT if res.converged else NOT_CONVERGED, k, n - k, q, None,
+                               a_hat, None, 0.0, res.p, 0, k_rho, gap, attempt + 1, rho)
+        k, e, _ = split_search(a_hat, norm_a)
+        cand = SplitResult(OK, k, n - k, q, None, a_hat, None, e, res.p, 0, k_rho, gap,
+                           attempt + 1, rho)
+        if best is None or e < best.e:
+            best = cand
+        if k == k_rho and e <= split_tol:
+            if not res.converged:
+                cand.status = NOT_CONVERGED
+            return cand
+    best.status = NOT_CONVERGED if not res.converged else RANK_AMBIGUOUS
+    return best

@@ -62,6 +62,26 @@ def sym_problem(n: int, seed: int, gap: float = 0.05, lo: float = -1.0, hi: floa
     return np.asfortranarray(a), d, q
 
 
+def nonsym_problem(n: int, seed: int, lam_lo: float = 0.1, lam_hi: float = 10.0,
+                   circle_gap: float = 0.01, offdiag: float = 0.02):
+    """Non-symmetric A = U T U^T with U Haar and T upper triangular: real
+    eigenvalues T_ii with |lambda| log-uniform in [lam_lo, lam_hi], random
+    signs, | |lambda| - 1 | >= circle_gap; strictly upper part
+    N(0,1) offdiag / sqrt(n).  Returns (A, lam)."""
+    rng = np.random.default_rng(seed)
+    u_ = haar_orthogonal(n, rng)
+    lam = np.empty(n)
+    for i in range(n):
+        while True:
+            m = math.exp(rng.uniform(math.log(lam_lo), math.log(lam_hi)))
+            if abs(m - 1.0) >= circle_gap:
+                break
+        lam[i] = m if rng.uniform() < 0.5 else -m
+    t = np.triu(rng.standard_normal((n, n)) * (offdiag / math.sqrt(n)), 1)
+    t[np.diag_indices(n)] = lam
+    return np.asfortranarray(u_ @ t @ u_.T), lam
+
+
 def svd_problem(m: int, n: int, seed: int, level: float = 1.0, gap: float = 0.05,
                 lo: float = 0.1, hi: float = 10.0):
     """m x n A = P diag(sigma) Q^T with P (m x r), Q (n x r) orthonormal

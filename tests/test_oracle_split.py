@@ -211,3 +211,42 @@ def test_split_svd_recovers_singular_subspaces(m, n):
     assert _sin_theta(u, pu[:, :k]) <= 1e-10 and _sin_theta(v, qvt[:k].T) <= 1e-10
     assert np.abs(np.linalg.eigvalsh(s11) - np.sort(sig[:k])).max() <= 1e-11 * sig[0]
     assert np.abs(u.T @ a @ v - s11).max() <= 1e-11 * sig[0]
+
+
+# ---------------------------------------------------------------------------
+# RNEP (B = I): the right side of the pencil step alone
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [20, 45])
+def test_split_nonsym_equals_pencil_right_side_and_construction(n):
+    """With B = I the pencil step's right side is the same computation, so
+    RNEP's Q is the pencil's Q_R exactly; the split count and the block
+    eigenvalues are the construction's."""
+    from oracle.split import split_nonsym
+    a, lam = S.nonsym_problem(n, S.family_seed(6, n))
+    reg = {"kind": "unit_disk"}
+    r = split_nonsym(a, reg, seed=3)
+    p = split_pencil(a, np.eye(n), reg, seed=3)
+    k = int((np.abs(lam) > 1).sum())
+    assert r.status == OK and r.k == k == p.k
+    assert np.array_equal(r.Q, p.Q)
+    assert np.abs(r.Q.T @ r.Q - np.eye(n)).max() <= 1e-13
+    assert norm1(r.A_hat[k:, :k]) <= 1e-10 * norm1(a)
+    ev1 = np.sort_complex(np.linalg.eigvals(r.A_hat[:k, :k]))
+    ev2 = np.sort_complex(np.linalg.eigvals(r.A_hat[k:, k:]))
+    lam_out = np.sort(lam[np.abs(lam) > 1]).astype(complex)
+    lam_in = np.sort(lam[np.abs(lam) < 1]).astype(complex)
+    assert np.abs(ev1 - lam_out).max() <= 1e-8 * np.abs(lam).max()
+    assert np.abs(ev2 - lam_in).max() <= 1e-8
+
+
+def test_split_nonsym_complex_pairs_half_plane():
+    """A real normal matrix with conjugate pairs, split at Re z < 0: the
+    leading block holds the eigenvalues with positive real part."""
+    from oracle.split import split_nonsym
+    a, ev = S.normal_random_problem(40, S.family_seed(6, 40))
+    r = split_nonsym(a, {"kind": "halfplane", "shift": 0.0, "scale": 1.0}, seed=1)
+    k = int((ev.real > 0).sum())
+    assert r.status == OK and r.k == k
+    got = np.sort_complex(np.linalg.eigvals(r.A_hat[:k, :k]))
+    assert np.abs(got - np.sort_complex(ev[ev.real > 0])).max() <= 1e-9
