@@ -148,6 +148,18 @@ sdc_status_t sdc_split_sym(sdc_handle_t h, int n, const double* A, int lda, sdc_
                            const sdc_opts_t* opts, double* Q, int ldq, double* Ahat, int ldah,
                            sdc_info_t* info);
 
+/* RNEP: one split step of a non-symmetric A (B = I; the paragraph after
+ * Alg. 4).  The left deflating subspace equals the right one, so only the
+ * right side runs: IRS of the mapped (A, I), GRURV(2, A_p + B_p, A_p, -1, 1)
+ * giving Q, then Ahat = Q^T A Q (not symmetrized) and the split point that
+ * minimizes ||E21||_1 / ||A||_1 (the backward error).  Arguments, layout,
+ * ownership and statuses as for sdc_split_sym (any region kind); FP64 only
+ * (SDC_FP32_REFINE gives SDC_ERR_INVALID).  Half the work of
+ * sdc_split_pencil with B = I (whose Q_R it reproduces when both accept the
+ * same draw). */
+sdc_status_t sdc_split_nonsym(sdc_handle_t h, int n, const double* A, int lda, sdc_region_t region,
+                              const sdc_opts_t* opts, double* Q, int ldq, double* Ahat, int ldah, sdc_info_t* info);
+
 /* One split of a regular pencil (RGNEP, Alg. 4, with the map of Sec. 3.3).
  * Q_L, Q_R (n x n, orthogonal), A_hat = Q_L^T A Q_R and B_hat = Q_L^T B Q_R
  * are written; the split point minimizes ||E21||_1/||A||_1 + ||F21||_1/||B||_1. */

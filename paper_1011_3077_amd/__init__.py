@@ -28,7 +28,8 @@ SDC_FP64, SDC_FP32_REFINE = 0, 1
 SDC_UNIT_DISK, SDC_DISK, SDC_HALFPLANE = 0, 1, 2
 
 EXPORTED = ["sdc_opts_default", "sdc_create", "sdc_destroy", "sdc_status_string", "sdc_irs",
-            "sdc_split_sym", "sdc_split_pencil", "sdc_split_sym_batched", "sdc_split_svd", "sdc_eig_dc",
+            "sdc_split_sym", "sdc_split_nonsym", "sdc_split_pencil", "sdc_split_sym_batched", "sdc_split_svd",
+            "sdc_eig_dc",
             "sdc_block_eigvals",
             "sdc_gaussian",
             "sdc_profile_enable", "sdc_profile_read", "sdc_server_create", "sdc_server_submit",
@@ -119,6 +120,8 @@ lib.sdc_split_sym_batched.restype = _I
 lib.sdc_eig_dc.argtypes = [_P, _I, _P, _I, _P, _I, _I, _I, C.POINTER(Opts), _P, _I, _P, _I, _P, _I, _P, _I,
                            C.POINTER(_I), C.POINTER(_I), C.POINTER(DcInfo)]
 lib.sdc_eig_dc.restype = _I
+lib.sdc_split_nonsym.argtypes = [_P, _I, _P, _I, Region, C.POINTER(Opts), _P, _I, _P, _I, C.POINTER(Info)]
+lib.sdc_split_nonsym.restype = _I
 lib.sdc_split_svd.argtypes = [_P, _I, _I, _P, _I, Region, C.POINTER(Opts), _P, _I, _P, _I, _P, _I, C.POINTER(Info)]
 lib.sdc_split_svd.restype = _I
 lib.sdc_block_eigvals.argtypes = [_P, _I, _P, _I, _P, _I, _I, C.POINTER(_I), _I, _P, _P]
@@ -238,6 +241,15 @@ class Handle:
         info = Info()
         st = _check(lib.sdc_split_sym(self._h, n, a.data_ptr(), n, reg or region(), C.byref(o or opts()),
                                       q.data_ptr(), n, ah.data_ptr(), n, C.byref(info)))
+        return SplitResult(st, info.as_dict(), q.t(), None, ah.t(), None)
+
+    def split_nonsym(self, A, reg: Region | None = None, o: Opts | None = None) -> SplitResult:
+        n = A.shape[0]
+        a = _cm(A)
+        q, ah = _out(n, A), _out(n, A)
+        info = Info()
+        st = _check(lib.sdc_split_nonsym(self._h, n, a.data_ptr(), n, reg or region(), C.byref(o or opts()),
+                                         q.data_ptr(), n, ah.data_ptr(), n, C.byref(info)))
         return SplitResult(st, info.as_dict(), q.t(), None, ah.t(), None)
 
     def split_pencil(self, A, B, reg: Region | None = None, o: Opts | None = None) -> SplitResult:

@@ -148,6 +148,29 @@ sdc_status_t sdc_split_sym(sdc_handle_t hd, int n, const double* A, int lda, sdc
     return (sdc_status_t)j.status;
 }
 
+sdc_status_t sdc_split_nonsym(sdc_handle_t hd, int n, const double* A, int lda, sdc_region_t region,
+                              const sdc_opts_t* opts, double* Q, int ldq, double* Ahat, int ldah, sdc_info_t* info) {
+    if (!hd || n < 0 || n > kMaxN || (n > 0 && (!A || !Q || !Ahat)) || lda < n || ldq < n || ldah < n || !region_ok(region))
+        return SDC_ERR_INVALID;
+    sdc_info_t dummy;
+    if (!info) info = &dummy;
+    *info = sdc_info_t{};
+    if (n == 0) return SDC_OK;
+    Handle& h = hd->h;
+    if (use_device(h) != SDC_OK) return SDC_ERR_DEVICE;
+    std::vector<SplitJob> jobs(1);
+    SplitJob& j = jobs[0];
+    j.n = n; j.pencil = false; j.nonsym = true; j.A = A; j.lda = lda; j.region = region; j.opts = resolve(opts);
+    if (!prec_ok(j.opts, true)) return SDC_ERR_INVALID;  // FP64 only
+    j.Q = Q; j.ldq = ldq; j.Ahat = Ahat; j.ldah = ldah;
+    sdc::ProfScope ps(h);
+    const int r = sdc::run_split_jobs(h, jobs);
+    resolve_profile(h);
+    if (r < 0) return (sdc_status_t)r;
+    *info = j.info;
+    return (sdc_status_t)j.status;
+}
+
 sdc_status_t sdc_split_pencil(sdc_handle_t hd, int n, const double* A, int lda, const double* B, int ldb,
                               sdc_region_t region, const sdc_opts_t* opts, double* QL, int ldql, double* QR,
                               int ldqr, double* Ahat, int ldah, double* Bhat, int ldbh, sdc_info_t* info) {

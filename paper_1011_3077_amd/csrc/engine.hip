@@ -466,8 +466,10 @@ static int block_form(Handle& h, std::vector<JobWs*>& js) {
             g2.push_back(gemm(n, j.QL, j.ldql, 1, w->T2, n, 0, j.Bhat, j.ldbh));
         } else {
             g2.push_back(gemm(n, j.Q, j.ldq, 1, w->T1, n, 0, w->T2, n));
+            // symmetric: (A_hat + A_hat^T) / 2 (Alg. 6); RNEP keeps Q^T A Q as is
             EwDesc d{};
-            d.op = EW_SYM; d.n = n; d.rows = n; d.in = w->T2; d.ldi = n; d.out = j.Ahat; d.ldo = j.ldah;
+            d.op = j.nonsym ? EW_PERMUTE : EW_SYM; d.n = n; d.rows = n; d.in = w->T2; d.ldi = n;
+            d.out = j.Ahat; d.ldo = j.ldah;
             d.alpha = 1.0; d.active = 1;
             es.push_back(d);
         }

@@ -78,6 +78,7 @@ inline bool prec_ok(const sdc_opts_t& o, bool pencil) {
 struct SplitJob {
     int n = 0;
     bool pencil = false;
+    bool nonsym = false;  // B = I with a non-symmetric A (RNEP): A_hat not symmetrized
     const double* A = nullptr; int lda = 0;
     const double* B = nullptr; int ldb = 0;
     sdc_region_t region{};

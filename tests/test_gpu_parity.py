@@ -250,3 +250,62 @@ def test_edge_cases(handle, sdc):
     # invalid region
     with pytest.raises(sdc.SdcError, match="INVALID"):
         handle.split_sym(dev(a), sdc.region("disk", center=0.0, radius=-1.0))
+
+
+# ---------------------------------------------------------------------------
+# RNEP (sdc_split_nonsym): non-symmetric A, B = I
+# ---------------------------------------------------------------------------
+
+def _sin_theta(x, y):
+    qx, _ = np.linalg.qr(x)
+    qy, _ = np.linalg.qr(y)
+    return float(np.linalg.norm(qy - qx @ (qx.T @ qy), 2))
+
+
+@pytest.mark.parametrize("n", [40, 150])
+def test_split_nonsym_matches_oracle(handle, sdc, n):
+    from oracle.split import split_nonsym
+    a, lam = S.nonsym_problem(n, S.family_seed(6, 100 + n))
+    print_case(test="split_nonsym", n=n)
+    res = handle.split_nonsym(dev(a), sdc.region(), sdc.opts(seed=9))
+    ref = split_nonsym(a, {"kind": "unit_disk"}, seed=9)
+    k = int((np.abs(lam) > 1).sum())
+    assert res.status == sdc.SDC_OK and res.info["k_lead"] == k == ref.k
+    q, ah = host(res.Q), host(res.Ahat)
+    assert np.abs(q.T @ q - np.eye(n)).max() <= 1e-13
+    assert norm1(ah[k:, :k]) <= 1e-10 * norm1(a)
+    assert _sin_theta(q[:, :k], ref.Q[:, :k]) <= 1e-10
+    assert np.abs(q.T @ a @ q - ah).max() <= 1e-12 * norm1(a)  # not symmetrized
+    for blk, rblk in ((ah[:k, :k], ref.A_hat[:k, :k]), (ah[k:, k:], ref.A_hat[k:, k:])):
+        ev, rev = np.sort_complex(np.linalg.eigvals(blk)), np.sort_complex(np.linalg.eigvals(rblk))
+        assert np.abs(ev - rev).max() <= 1e-9 * np.abs(lam).max()
+
+
+def test_split_nonsym_equals_pencil_with_identity(handle, sdc):
+    """The pencil step with B = I runs the same right side: its Q_R is RNEP's Q."""
+    n = 64
+    a, lam = S.nonsym_problem(n, S.family_seed(6, 7))
+    print_case(test="split_nonsym_vs_pencil", n=n)
+    r1 = handle.split_nonsym(dev(a), sdc.region(), sdc.opts(seed=4))
+    r2 = handle.split_pencil(dev(a), dev(np.eye(n)), sdc.region(), sdc.opts(seed=4))
+    assert r1.status == r2.status == sdc.SDC_OK and r1.info["k_lead"] == r2.info["k_lead"]
+    assert r1.info["iters_right"] == r2.info["iters_right"]
+    assert torch.allclose(r1.Q, r2.Q, rtol=0, atol=1e-12)
+
+
+def test_split_nonsym_complex_pairs(handle, sdc):
+    from oracle.split import split_nonsym
+    n = 64
+    a, ev = S.normal_random_problem(n, S.family_seed(6, 64))
+    print_case(test="split_nonsym_pairs", n=n)
+    reg = sdc.region("halfplane", shift=0.0, scale=1.0)
+    res = handle.split_nonsym(dev(a), reg, sdc.opts(seed=2))
+    k = int((ev.real > 0).sum())
+    assert res.status == sdc.SDC_OK and res.info["k_lead"] == k
+    ah = host(res.Ahat)
+    got = np.sort_complex(np.linalg.eigvals(ah[:k, :k]))
+    assert np.abs(got - np.sort_complex(ev[ev.real > 0])).max() <= 1e-9
+    ref = split_nonsym(a, {"kind": "halfplane", "shift": 0.0, "scale": 1.0}, seed=2)
+    assert _sin_theta(host(res.Q)[:, :k], ref.Q[:, :k]) <= 1e-10
+    with pytest.raises(sdc.SdcError):
+        handle.split_nonsym(dev(a), reg, sdc.opts(prec=sdc.SDC_FP32_REFINE))
