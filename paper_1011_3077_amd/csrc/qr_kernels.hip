@@ -473,6 +473,9 @@ __global__ __launch_bounds__(QrCfg<T>::PT) void k_panel(const QrDesc<T>* __restr
 //                 {row(gq, v) : gq});
 //   C^T -= Y^T V^T : Y's accumulator registers are the A operand with the
 //                 same k-slices, V^T read from LDS, C^T accumulated in place.
+// Row blocks per group of the update phase of k_update (1, 2 and 4 were
+// measured; 2 was fastest, 1 spills)
+constexpr int kUpdGroup = 2;
 template <typename T, int RB>
 __global__ __launch_bounds__(256, 2) void k_update(const QrDesc<T>* __restrict__ descs, int c0, int level) {
     using C = QrCfg<T>;
@@ -639,30 +642,40 @@ __global__ __launch_bounds__(256, 2) void k_update(const QrDesc<T>* __restrict__
             y1 = M::mma(ta[1][kb][j], bw, y1);
         }
     }
-    // C^T -= Y^T V^T: k-steps outer, row blocks inner (RB independent
-    // accumulators); each k-step's V^T operands are read from LDS together
-    // before its MFMAs
+    // C^T -= Y^T V^T, kUpdGroup row blocks at a time (one accumulator chain
+    // each over the eight k-steps, in the same k order as a whole-slice
+    // pass, so the result does not depend on the grouping); each group is
+    // stored as soon as it is done, so its stores drain while later groups
+    // are multiplied
+    constexpr int G = kUpdGroup;
+    static_assert(RB % G == 0, "whole groups of row blocks");
+    T ya[8];
 #pragma unroll
-    for (int pb = 0; pb < 2; ++pb) {
+    for (int t = 0; t < 8; ++t) ya[t] = -((t >> 2) ? y1[t & 3] : y0[t & 3]);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const T a = -(pb ? y1[j] : y0[j]);
-            const int kcol = pb * 16 + M::row(gq, j);
-            T vb[RB];
+    for (int rb = 0; rb < RB; rb += G) {
+        if (rb < rbe) {
+            T vb[G][8];
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) vb[rb] = rb < rbe ? s_V[(rb * 16 + ln) * VS + kcol] : T(0);
+            for (int t = 0; t < 8; ++t) {
+                const int kcol = (t >> 2) * 16 + M::row(gq, t & 3);
+#pragma unroll
+                for (int g = 0; g < G; ++g) vb[g][t] = rb + g < rbe ? s_V[((rb + g) * 16 + ln) * VS + kcol] : T(0);
+            }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
-                if (rb < rbe) cr[rb] = M::mma(a, vb[rb], cr[rb]);
+            for (int t = 0; t < 8; ++t)
+#pragma unroll
+                for (int g = 0; g < G; ++g) cr[rb + g] = M::mma(ya[t], vb[g][t], cr[rb + g]);
             __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const unsigned o = c_off(rb + g);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    bc.store(cr[rb + g][q], o + (unsigned)(M::row(0, q) * ld * sizeof(T)));
+            }
         }
-    }
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-        const unsigned o = c_off(rb);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) bc.store(cr[rb][q], o + (unsigned)(M::row(0, q) * ld * sizeof(T)));
     }
 }
 
