@@ -238,7 +238,9 @@ sdc_status_t sdc_eig_dc(sdc_handle_t h, int n, const double* A, int lda, const d
  * A, U, V, S11 are device pointers, column-major, caller-owned; the
  * library's workspace grows by 3 (m + n)^2 doubles.  m + n <= 16384.
  * Statuses as for sdc_split_sym (SDC_NO_SPLIT when no singular value, or
- * every one, lies above the shift); SDC_ERR_INVALID for bad arguments. */
+ * every one, lies above the shift); SDC_ERR_INVALID for bad arguments,
+ * including a shift of 0 with m != n (E's |m - n| zero eigenvalues would lie
+ * on the line). */
 sdc_status_t sdc_split_svd(sdc_handle_t h, int m, int n, const double* A, int lda, sdc_region_t region,
                            const sdc_opts_t* opts, double* U, int ldu, double* V, int ldv, double* S11, int lds11,
                            sdc_info_t* info);

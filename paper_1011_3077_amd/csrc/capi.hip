@@ -294,7 +294,8 @@ sdc_status_t sdc_split_svd(sdc_handle_t hd, int m, int n, const double* A, int l
                            sdc_info_t* info) {
     const int r = std::min(m, n);
     if (!hd || m < 1 || n < 1 || m + n > kMaxN || !A || !U || !V || !S11 || lda < m || ldu < m || ldv < n ||
-        lds11 < r || !region_ok(region) || region.kind != SDC_HALFPLANE || region.shift < 0.0)
+        lds11 < r || !region_ok(region) || region.kind != SDC_HALFPLANE || region.shift < 0.0 ||
+        (m != n && region.shift == 0.0))  // |m - n| zero eigenvalues of the embedding on the line
         return SDC_ERR_INVALID;
     sdc_info_t dummy;
     if (!info) info = &dummy;

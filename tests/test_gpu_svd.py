@@ -85,3 +85,5 @@ def test_split_svd_edges(handle, sdc):
         handle.split_svd(A, sdc.region("halfplane", shift=-1.0, scale=1.0))
     with pytest.raises(sdc.SdcError):
         handle.split_svd(A, sdc.region("disk", center=0.0, radius=1.0))
+    with pytest.raises(sdc.SdcError):  # 30 x 20: ten zero eigenvalues of the embedding on Re z = 0
+        handle.split_svd(A, sdc.region("halfplane", shift=0.0, scale=1.0))
