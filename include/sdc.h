@@ -259,13 +259,20 @@ sdc_status_t sdc_split_svd(sdc_handle_t h, int m, int n, const double* A, int ld
  *     a pencil that far.
  *   Any other block (symmetric above order 128, pencil above order 2) gets
  *   NaN in wr and wi.
- * T, S, wr, wi are device pointers (column-major T and S with leading
+ * V (optional, symmetric only; n x n, ldv >= n): the diagonal block
+ * V[start .. start + m, start .. start + m] receives the block's orthonormal
+ * eigenvectors, column i for wr[start + i], for blocks of order <= 64 (NaN for
+ * larger ones); entries outside the diagonal blocks are not written.  With
+ * V block diagonal (zero elsewhere) and QR from sdc_eig_dc, QR V holds the
+ * eigenvectors of A.
+ * T, S, wr, wi, V are device pointers (column-major T and S with leading
  * dimensions ldt, lds >= n; wr, wi hold n doubles each, caller-owned);
  * block_start is a HOST array of nblocks + 1 increasing ints from 0 to n.
  * Returns SDC_OK, or SDC_ERR_INVALID for inconsistent arguments (nothing
  * written). */
 sdc_status_t sdc_block_eigvals(sdc_handle_t h, int n, const double* T, int ldt, const double* S, int lds,
-                               int nblocks, const int* block_start, int symmetric, double* wr, double* wi);
+                               int nblocks, const int* block_start, int symmetric, double* wr, double* wi,
+                               double* V, int ldv);
 
 /* Per-kernel timing (opt-in).  With profiling enabled every launch of the
  * hot kernels is bracketed by HIP events on the handle's stream and its

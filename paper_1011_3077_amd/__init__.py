@@ -124,7 +124,7 @@ lib.sdc_split_nonsym.argtypes = [_P, _I, _P, _I, Region, C.POINTER(Opts), _P, _I
 lib.sdc_split_nonsym.restype = _I
 lib.sdc_split_svd.argtypes = [_P, _I, _I, _P, _I, Region, C.POINTER(Opts), _P, _I, _P, _I, _P, _I, C.POINTER(Info)]
 lib.sdc_split_svd.restype = _I
-lib.sdc_block_eigvals.argtypes = [_P, _I, _P, _I, _P, _I, _I, C.POINTER(_I), _I, _P, _P]
+lib.sdc_block_eigvals.argtypes = [_P, _I, _P, _I, _P, _I, _I, C.POINTER(_I), _I, _P, _P, _P, _I]
 lib.sdc_block_eigvals.restype = _I
 lib.sdc_profile_enable.argtypes = [_P, _I]
 lib.sdc_profile_enable.restype = _I
@@ -318,9 +318,11 @@ class Handle:
                                       u.data_ptr(), m, v.data_ptr(), n, s11.data_ptr(), r, C.byref(info)))
         return st, info.as_dict(), u.t(), v.t(), s11.t()
 
-    def block_eigvals(self, T, S, starts, symmetric: bool = False):
+    def block_eigvals(self, T, S, starts, symmetric: bool = False, vectors: bool = False):
         """Eigenvalues of the diagonal blocks of eig_dc's T (and S): returns
-        (wr, wi), two length-n float64 device tensors (see sdc_block_eigvals)."""
+        (wr, wi), two length-n float64 device tensors, and with vectors=True
+        (symmetric only) also V, n x n block diagonal, the blocks'
+        eigenvectors (see sdc_block_eigvals)."""
         import torch
         n = T.shape[0]
         t = _cm(T)
@@ -329,9 +331,11 @@ class Handle:
         st = (_I * (nb + 1))(*starts)
         wr = torch.empty(n, dtype=torch.float64, device=T.device)
         wi = torch.empty(n, dtype=torch.float64, device=T.device)
+        v = torch.zeros((n, n), dtype=torch.float64, device=T.device) if vectors else None
         _check(lib.sdc_block_eigvals(self._h, n, t.data_ptr(), n, None if s is None else s.data_ptr(), n, nb, st,
-                                     int(symmetric), wr.data_ptr(), wi.data_ptr()))
-        return wr, wi
+                                     int(symmetric), wr.data_ptr(), wi.data_ptr(),
+                                     None if v is None else v.data_ptr(), n))
+        return (wr, wi) if v is None else (wr, wi, v.t())
 
     def profile_enable(self, on: bool = True):
         _check(lib.sdc_profile_enable(self._h, int(on)))

@@ -313,13 +313,15 @@ sdc_status_t sdc_split_svd(sdc_handle_t hd, int m, int n, const double* A, int l
 }
 
 sdc_status_t sdc_block_eigvals(sdc_handle_t hd, int n, const double* T, int ldt, const double* S, int lds,
-                               int nblocks, const int* block_start, int symmetric, double* wr, double* wi) {
+                               int nblocks, const int* block_start, int symmetric, double* wr, double* wi,
+                               double* V, int ldv) {
     if (!hd || n < 1 || !T || ldt < n || (!symmetric && (!S || lds < n)) || nblocks < 1 || nblocks > n ||
-        !block_start || !wr || !wi)
+        !block_start || !wr || !wi || (V && (!symmetric || ldv < n)))
         return SDC_ERR_INVALID;
     Handle& h = hd->h;
     if (use_device(h) != SDC_OK) return SDC_ERR_DEVICE;
-    return (sdc_status_t)sdc::run_block_eigvals(h, n, T, ldt, S, lds, nblocks, block_start, symmetric != 0, wr, wi);
+    return (sdc_status_t)sdc::run_block_eigvals(h, n, T, ldt, S, lds, nblocks, block_start, symmetric != 0, wr, wi,
+                                                V, ldv);
 }
 
 }  // extern "C"

@@ -415,7 +415,7 @@ int run_split_svd(Handle& h, int m, int n, const double* A, int lda, const sdc_r
 }
 
 int run_block_eigvals(Handle& h, int n, const double* T, int ldt, const double* S, int lds, int nblocks,
-                      const int* block_start, int symmetric, double* wr, double* wi) {
+                      const int* block_start, int symmetric, double* wr, double* wi, double* V, int ldv) {
     if (nblocks < 1 || block_start[0] != 0 || block_start[nblocks] != n) return SDC_ERR_INVALID;
     for (int b = 0; b < nblocks; ++b)
         if (block_start[b + 1] <= block_start[b]) return SDC_ERR_INVALID;
@@ -433,6 +433,8 @@ int run_block_eigvals(Handle& h, int n, const double* T, int ldt, const double* 
         d.symmetric = symmetric;
         d.wr = wr + s0;
         d.wi = wi + s0;
+        d.V = V ? V + s0 + (size_t)s0 * ldv : nullptr;
+        d.ldv = ldv;
         d.active = 1;
     }
     UPLOAD(dd, v);

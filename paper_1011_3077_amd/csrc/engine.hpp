@@ -107,7 +107,7 @@ int run_split_svd(Handle& h, int m, int n, const double* A, int lda, const sdc_r
                   const sdc_opts_t& opts, double* U, int ldu, double* V, int ldv, double* S11, int lds11,
                   sdc_info_t* info, int* status);
 int run_block_eigvals(Handle& h, int n, const double* T, int ldt, const double* S, int lds, int nblocks,
-                      const int* block_start, int symmetric, double* wr, double* wi);
+                      const int* block_start, int symmetric, double* wr, double* wi, double* V, int ldv);
 
 // Incremental driver (continuous batching).  A JobRun holds one split job's
 // state in a caller-provided device workspace of job_run_bytes() bytes; each

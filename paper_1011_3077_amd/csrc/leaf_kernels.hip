@@ -7,7 +7,9 @@
 //     applied together, rows first, then columns), sweeps of m - 1 rounds
 //     until the off-diagonal Frobenius norm is at most 1e-15 of the block's
 //     (at most kSweeps sweeps); the eigenvalues are the diagonal, sorted
-//     ascending, wi = 0;
+//     ascending, wi = 0; for a block of order <= kJacobiVecMax the rotations
+//     are also accumulated (V <- V J) into the eigenvectors, written in the
+//     order of the eigenvalues when the caller asks for them;
 //   * pencil block (T, S) of order 1: T/S; of order 2: the roots of
 //     det(T - lambda S) = 0, real ones ascending, a complex pair as
 //     (re, +im), (re, -im); an infinite eigenvalue (singular S) as +-inf;
@@ -92,10 +94,19 @@ __global__ __launch_bounds__(256) void k_block_eig(const BlockEigDesc* __restric
     if (m > MX) {
         const double nan = __builtin_nan("");
         for (int i = tid; i < m; i += 256) d.wr[i] = d.wi[i] = nan;
+        if (d.V)
+            for (int e = tid; e < m * m; e += 256) d.V[(e % m) + (size_t)(e / m) * d.ldv] = nan;
         return;
     }
-    // the block, symmetrized, padded to even order with an isolated zero row
+    // the block, symmetrized, padded to even order with an isolated zero row;
+    // the eigenvectors (identity at first) use the rows of s_a past MX / 2,
+    // which a block of order <= kJacobiVecMax leaves free
+    static_assert(2 * kJacobiVecMax <= MX, "eigenvector rows fit after the block's");
     const int mm = m + (m & 1), np = mm / 2;
+    const bool vec = d.V != nullptr && m <= kJacobiVecMax;
+    double* s_v = s_a + (MX / 2) * LA;  // row-major, row stride LA
+    if (vec)
+        for (int e = tid; e < mm * mm; e += 256) s_v[(e % mm) * LA + e / mm] = (e % mm) == (e / mm) ? 1.0 : 0.0;
     for (int e = tid; e < mm * mm; e += 256) {
         const int i = e % mm, j = e / mm;
         s_a[i * LA + j] = (i < m && j < m) ? 0.5 * (d.T[i + (size_t)j * d.ldt] + d.T[j + (size_t)i * d.ldt]) : 0.0;
@@ -141,13 +152,18 @@ __global__ __launch_bounds__(256) void k_block_eig(const BlockEigDesc* __restric
                 s_a[q * LA + j] = s * x + c * y;
             }
             __syncthreads();
-            for (int e = tid; e < np * mm; e += 256) {  // then columns p, q
+            for (int e = tid; e < np * mm; e += 256) {  // then columns p, q (of V too)
                 const int k = e / mm, i = e % mm;
                 const int p = s_p[k], q = s_q[k];
                 const double c = s_c[k], s = s_s[k];
                 const double x = s_a[i * LA + p], y = s_a[i * LA + q];
                 s_a[i * LA + p] = c * x - s * y;
                 s_a[i * LA + q] = s * x + c * y;
+                if (vec) {
+                    const double u = s_v[i * LA + p], w = s_v[i * LA + q];
+                    s_v[i * LA + p] = c * u - s * w;
+                    s_v[i * LA + q] = s * u + c * w;
+                }
             }
             __syncthreads();
         }
@@ -162,6 +178,10 @@ __global__ __launch_bounds__(256) void k_block_eig(const BlockEigDesc* __restric
         }
         d.wr[rank] = di;
         d.wi[rank] = 0.0;
+        if (d.V) {
+            const double nan = __builtin_nan("");
+            for (int r = 0; r < m; ++r) d.V[r + (size_t)rank * d.ldv] = vec ? s_v[r * LA + i] : nan;
+        }
     }
 }
 

@@ -65,11 +65,13 @@ void gersh_batch(const GershDesc* d, const GershDesc* h, int count, hipStream_t 
 // Jacobi, a pencil block (T, S) of order 1 or 2 in closed form, NaN for any
 // other block.  T and S point at the block's first element (column-major).
 constexpr int kJacobiMax = 128;
+constexpr int kJacobiVecMax = 64;  // blocks whose eigenvectors are accumulated too
 struct BlockEigDesc {
     const double* T; int ldt;
     const double* S; int lds;   // pencil only
     int m, symmetric;
     double* wr; double* wi;     // m values each
+    double* V; int ldv;         // optional: the block's eigenvectors (m x m, columns in the order of wr)
     int active;
 };
 void block_eig_batch(const BlockEigDesc* d, const BlockEigDesc* h, int count, hipStream_t s);

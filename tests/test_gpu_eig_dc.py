@@ -149,6 +149,29 @@ def test_block_eigvals_symmetric_leaves(handle, sdc, n, leaf):
     assert np.abs(np.sort(wr) - np.sort(d)).max() <= 1e-12
 
 
+def test_symmetric_eigendecomposition_from_leaves(handle, sdc):
+    """eig_dc to blocks <= 64, then the leaves' Jacobi eigenvectors: Z = QR V
+    has orthonormal columns, A Z = Z diag(wr) up to the dropped coupling
+    blocks, and wr is the construction's spectrum.  A block above the
+    eigenvector limit (64) gets NaN vectors but its eigenvalues."""
+    n = 300
+    print("CASE symmetric eigendecomposition", n, flush=True)
+    a, d, _ = S.sym_problem(n, S.family_seed(0, 301))
+    st, t, s, ql, qr, starts, info = handle.eig_dc(dev(a), None, leaf_max=64, symmetric=True,
+                                                    o=sdc.opts(seed=3))
+    assert st == 0
+    wr, wi, v = handle.block_eigvals(t, None, starts, symmetric=True, vectors=True)
+    z = qr.cpu().numpy() @ v.cpu().numpy()
+    wr = wr.cpu().numpy()
+    assert np.abs(z.T @ z - np.eye(n)).max() <= 1e-12
+    assert np.abs(a @ z - z * wr[None, :]).max() <= 1e-10 * np.abs(d).max()
+    assert np.abs(np.sort(wr) - np.sort(d)).max() <= 1e-12
+    a2, d2, _ = S.sym_problem(100, S.family_seed(0, 302))
+    wr2, _, v2 = handle.block_eigvals(dev(a2), None, [0, 100], symmetric=True, vectors=True)
+    assert torch.isnan(v2).all()
+    assert np.abs(np.sort(wr2.cpu().numpy()) - np.sort(d2)).max() <= 1e-12
+
+
 def test_block_eigvals_pencil_to_order_two(handle, sdc):
     """A real normal matrix with complex-conjugate pairs (and one real
     eigenvalue, order 41) as the pencil (A, I), recursed to blocks of order
