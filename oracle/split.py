@@ -173,7 +173,7 @@ def split_sym(a: np.ndarray, region: dict, gauss: GaussSource | None = None, see
                            attempt + 1, rho)
         if best is None or e < best.e:
             best = cand
-        if k == k_rho and e <= split_tol:
+        if e <= split_tol:  # the split is accepted on its backward error (Alg. 4)
             if not res.converged:
                 cand.status = NOT_CONVERGED
             return cand
@@ -217,7 +217,7 @@ def split_pencil(a: np.ndarray, b: np.ndarray, region: dict, gauss: GaussSource 
                            min(gap, gap_l), attempt + 1, rho_r)
         if best is None or e < best.e:
             best = cand
-        if k == k_rho and k == k_rho_l and e <= split_tol:
+        if e <= split_tol:  # the split is accepted on its backward error (Alg. 4)
             if not converged:
                 cand.status = NOT_CONVERGED
             return cand
@@ -279,7 +279,7 @@ def split_nonsym(a: np.ndarray, region: dict, gauss: GaussSource | None = None, 
                            attempt + 1, rho)
         if best is None or e < best.e:
             best = cand
-        if k == k_rho and e <= split_tol:
+        if e <= split_tol:  # the split is accepted on its backward error (Alg. 4)
             if not res.converged:
                 cand.status = NOT_CONVERGED
             return cand
