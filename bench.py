@@ -44,7 +44,7 @@ PEAK = {"fp64_tflops": 78.6, "fp32_tflops": 157.3, "hbm_gbs": 8000.0}
 # 256 MiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), divided by the
 # number of dispatches.  Valid only for the kernel sources it was measured
 # on (their SHA-256 below); otherwise reported as null.
-TRAFFIC = {"bytes_per_launch": 91095569, "sha256": "8da58b698a64b6f50779c27be1f16b1f1c636739e8a02126cbd01fe818b79e80", "n": 2048, "leaf": 64, "note": "rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 over 7932 update dispatches of one step"}
+TRAFFIC = {"bytes_per_launch": 104149743, "sha256": "8da58b698a64b6f50779c27be1f16b1f1c636739e8a02126cbd01fe818b79e80", "n": 2048, "leaf": 64, "note": "rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 over 6831 update dispatches of one step"}
 
 
 def log(*a):
