@@ -287,6 +287,7 @@ void ew_batch(const EwDesc* d, const EwDesc* h, int count, hipStream_t s) {
 template void ew_batch<double, double>(const EwDesc*, const EwDesc*, int, hipStream_t);
 template void ew_batch<float, double>(const EwDesc*, const EwDesc*, int, hipStream_t);
 template void ew_batch<float, float>(const EwDesc*, const EwDesc*, int, hipStream_t);
+template void ew_batch<double, float>(const EwDesc*, const EwDesc*, int, hipStream_t);
 
 // Fill a device array (used instead of memset so the calls stay capturable).
 template <typename T>

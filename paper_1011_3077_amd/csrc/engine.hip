@@ -598,10 +598,25 @@ static bool wants_refine(JobWs& w) {
     return side == SIDE_SPLIT && k == krho && k > 0 && k < j.n && !(e <= j.opts.split_tol) && e < kRefineMaxE;
 }
 
+// Element-wise conversion between FP64 and FP32 copies (rows x cols).
+static EwDesc ew_conv(int rows, int cols, const void* in, int ldi, void* out, int ldo) {
+    EwDesc d{};
+    d.op = EW_PERMUTE; d.n = cols; d.rows = rows; d.in = in; d.ldi = ldi; d.out = out; d.ldo = ldo;
+    d.alpha = 1.0; d.active = 1;
+    return d;
+}
+
+// Conjugate gradients on X A11 - A22 X = E.  The recurrences, inner
+// products and the right-hand side are FP64; the operator products
+// Z = P A11 - A22 P run on FP32 copies of A11, A22 and P (MFMA FP32 GEMMs at
+// half the bytes): a correction only has to be accurate to about the CG
+// tolerance, well above the FP32 product error, and the Newton residual
+// E is recomputed in FP64 after every round.
 static int cg_solve(Handle& h, std::vector<JobWs*>& js) {
     const int count = (int)js.size();
     std::vector<CgDesc> cg;
-    std::vector<GemmDesc<double>> g1, g2;
+    std::vector<GemmDesc<float>> g1, g2;
+    std::vector<EwDesc> prep, to32, to64;
     for (JobWs* w : js) {
         SplitJob& j = *w->job;
         const int n = j.n, k = j.info.k_lead, m = n - k;
@@ -612,21 +627,43 @@ static int cg_solve(Handle& h, std::vector<JobWs*>& js) {
         d.rr = w->cg; d.rr0 = w->cg + 3 * kCgMaxBlocks; d.pz = w->cg + 4 * kCgMaxBlocks;
         d.tol2 = kCgTol * kCgTol; d.nblk = cg_blocks(m, k); d.active = 1;
         cg.push_back(d);
+        // FP32 copies in the second half of X (n^2 doubles hold the
+        // (m + k)^2 floats of A11, A22, P and Z; the CG vectors use 4 m k <= n^2)
+        float* a11 = reinterpret_cast<float*>(w->X + (size_t)n * n);
+        float* a22 = a11 + (size_t)k * k;
+        float* pf = a22 + (size_t)m * m;
+        float* zf = pf + mk;
+        prep.push_back(ew_conv(k, k, j.Ahat, j.ldah, a11, k));
+        prep.push_back(ew_conv(m, m, j.Ahat + k + (size_t)k * j.ldah, j.ldah, a22, m));
+        to32.push_back(ew_conv(m, k, d.P, m, pf, m));
+        to64.push_back(ew_conv(m, k, zf, m, d.Z, m));
         // Z = P A11 - A22 P
-        g1.push_back(gemm_g(m, k, k, d.P, m, 0, j.Ahat, j.ldah, 0, d.Z, m, 1.0, 0.0));
-        g2.push_back(gemm_g(m, k, m, j.Ahat + k + (size_t)k * j.ldah, j.ldah, 0, d.P, m, 0, d.Z, m, -1.0, 1.0));
+        GemmDesc<float> e1{};
+        e1.A = pf; e1.lda = m; e1.B = a11; e1.ldb = k; e1.C = zf; e1.ldc = m;
+        e1.M = m; e1.N = k; e1.K = k; e1.alpha = 1.0f; e1.beta = 0.0f; e1.active = 1;
+        g1.push_back(e1);
+        GemmDesc<float> e2{};
+        e2.A = a22; e2.lda = m; e2.B = pf; e2.ldb = m; e2.C = zf; e2.ldc = m;
+        e2.M = m; e2.N = k; e2.K = m; e2.alpha = -1.0f; e2.beta = 1.0f; e2.active = 1;
+        g2.push_back(e2);
     }
     UPLOAD(dcg, cg);
     UPLOAD(dg1, g1);
     UPLOAD(dg2, g2);
+    UPLOAD(dprep, prep);
+    UPLOAD(d32, to32);
+    UPLOAD(d64, to64);
+    ew_batch<double, float>(dprep, prep.data(), (int)prep.size(), h.stream);
     size_t need = 0;
     for (const CgDesc& d : cg) need += 2 * (size_t)d.nblk;
     CHK(ensure_host(h, need * sizeof(double) + 64));
     CHK(ensure_dstage(h, need + 1));
     cg_init_batch(dcg, cg.data(), count, h.stream);
     for (int it = 0; it < kCgMaxIt; ++it) {
-        gemm_batch<double>(dg1, g1.data(), count, h.stream);
-        gemm_batch<double>(dg2, g2.data(), count, h.stream);
+        ew_batch<double, float>(d32, to32.data(), count, h.stream);
+        gemm_batch<float>(dg1, g1.data(), count, h.stream);
+        gemm_batch<float>(dg2, g2.data(), count, h.stream);
+        ew_batch<float, double>(d64, to64.data(), count, h.stream);
         for (int ph = 0; ph < 3; ++ph) cg_iter_vec(dcg, cg.data(), count, it, ph, h.stream);
         if ((it + 1) % kCgCheck != 0) continue;
         HIPCHK(hipGetLastError());
