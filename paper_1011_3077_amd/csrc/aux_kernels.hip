@@ -40,49 +40,72 @@ __device__ inline void atomic_max_nonneg(double* addr, double v) {
 
 // ---------------------------------------------------------------------------
 // Batched GEMM on the matrix cores: 64x64 output tile per 256-thread block,
-// 2x2 waves of 32x32, K staged through LDS in chunks of 16.
+// 2x2 waves of 32x32, K staged through LDS in chunks of 32.  The next chunk
+// is loaded into registers while the current one is multiplied, so the
+// global loads overlap the MFMAs; the registers go to LDS after the chunk.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm(const GemmDesc<T>* __restrict__ descs) {
     using M = Mfma<T>;
     typedef typename M::v4 v4;
+    constexpr int KC = 32, PER = 64 * KC / 256;  // elements of A (and of B) per thread per chunk
     const GemmDesc<T> d = descs[blockIdx.z];
     if (!d.active) return;
     const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
     if (m0 >= d.M || n0 >= d.N) return;
-    __shared__ T sA[16][64 + 4];
-    __shared__ T sB[16][64 + 4];
+    __shared__ T sA[KC][64 + 4];
+    __shared__ T sB[KC][64 + 4];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, gq = lane >> 4, ln = lane & 15;
     const int wm = wave >> 1, wn = wave & 1;
     v4 acc[2][2];
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = v4{0, 0, 0, 0};
-    for (int k0 = 0; k0 < d.K; k0 += 16) {
-        for (int e = tid; e < 1024; e += 256) {
-            int m, k;
-            T va = 0;
-            if (!d.ta) {
-                m = e & 63; k = e >> 6;
-                if (m0 + m < d.M && k0 + k < d.K) va = d.A[(size_t)(k0 + k) * d.lda + m0 + m];
-            } else {
-                k = e & 15; m = e >> 4;
-                if (m0 + m < d.M && k0 + k < d.K) va = d.A[(size_t)(m0 + m) * d.lda + k0 + k];
-            }
-            sA[k][m] = va;
-            int n;
-            T vb = 0;
-            if (!d.tb) {
-                k = e & 15; n = e >> 4;
-                if (n0 + n < d.N && k0 + k < d.K) vb = d.B[(size_t)(n0 + n) * d.ldb + k0 + k];
-            } else {
-                n = e & 63; k = e >> 6;
-                if (n0 + n < d.N && k0 + k < d.K) vb = d.B[(size_t)(k0 + k) * d.ldb + n0 + n];
-            }
-            sB[k][n] = vb;
-        }
-        __syncthreads();
+    T ra[PER], rb[PER];
+    // element e (< 64 KC) of a chunk: A as (m, k) with m fastest unless A is
+    // transposed, B as (k, n) with k fastest unless B is transposed, so that
+    // consecutive threads read consecutive addresses
+    auto a_mk = [&](int e, int& m, int& k) {
+        if (!d.ta) { m = e & 63; k = e >> 6; } else { k = e & (KC - 1); m = e / KC; }
+    };
+    auto b_kn = [&](int e, int& k, int& n) {
+        if (!d.tb) { k = e & (KC - 1); n = e / KC; } else { n = e & 63; k = e >> 6; }
+    };
+    auto load = [&](int k0) {
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
+        for (int t = 0; t < PER; ++t) {
+            const int e = tid + 256 * t;
+            int m, k, n;
+            a_mk(e, m, k);
+            T va = 0;
+            if (m0 + m < d.M && k0 + k < d.K)
+                va = d.ta ? d.A[(size_t)(m0 + m) * d.lda + k0 + k] : d.A[(size_t)(k0 + k) * d.lda + m0 + m];
+            ra[t] = va;
+            b_kn(e, k, n);
+            T vb = 0;
+            if (n0 + n < d.N && k0 + k < d.K)
+                vb = d.tb ? d.B[(size_t)(k0 + k) * d.ldb + n0 + n] : d.B[(size_t)(n0 + n) * d.ldb + k0 + k];
+            rb[t] = vb;
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            const int e = tid + 256 * t;
+            int m, k, n;
+            a_mk(e, m, k);
+            sA[k][m] = ra[t];
+            b_kn(e, k, n);
+            sB[k][n] = rb[t];
+        }
+    };
+    load(0);
+    stash();
+    __syncthreads();
+    for (int k0 = 0; k0 < d.K; k0 += KC) {
+        const bool more = k0 + KC < d.K;
+        if (more) load(k0 + KC);
+#pragma unroll
+        for (int kk = 0; kk < KC / 4; ++kk) {
             const T a0 = sA[kk * 4 + gq][wm * 32 + ln];
             const T a1 = sA[kk * 4 + gq][wm * 32 + 16 + ln];
             const T b0 = sB[kk * 4 + gq][wn * 32 + ln];
@@ -93,6 +116,10 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc<T>* __restrict__ de
             acc[1][1] = M::mma(a1, b1, acc[1][1]);
         }
         __syncthreads();
+        if (more) {
+            stash();
+            __syncthreads();
+        }
     }
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) {
