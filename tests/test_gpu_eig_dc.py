@@ -222,3 +222,19 @@ def test_eig_dc_benchmark_workload_full_size(handle, sdc):
     check_pencil(res, p["A"], p["B"], p["lam"], leaf, 1e-9)
     info = res[-1]
     print("full-size info", info, flush=True)
+
+
+def test_block_eigvals_all_order_one_blocks(handle, sdc):
+    """Every block of order 1: the symmetric eigenvalues are the diagonal
+    (V the identity), the pencil's are T_ii / S_ii."""
+    print("CASE block_eigvals 1x1", flush=True)
+    n = 9
+    rng = np.random.default_rng(5)
+    t = np.triu(rng.standard_normal((n, n)))
+    s = np.triu(rng.standard_normal((n, n))) + 4 * np.eye(n)
+    starts = list(range(n + 1))
+    wr, wi, v = handle.block_eigvals(dev(np.diag(np.diag(t))), None, starts, symmetric=True, vectors=True)
+    assert np.array_equal(wr.cpu().numpy(), np.diag(t)) and np.array_equal(v.cpu().numpy(), np.eye(n))
+    wr, wi = handle.block_eigvals(dev(t), dev(s), starts, symmetric=False)
+    assert np.allclose(wr.cpu().numpy(), np.diag(t) / np.diag(s), rtol=1e-15, atol=0)
+    assert not wi.cpu().numpy().any()

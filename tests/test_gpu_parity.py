@@ -309,3 +309,16 @@ def test_split_nonsym_complex_pairs(handle, sdc):
     assert _sin_theta(host(res.Q)[:, :k], ref.Q[:, :k]) <= 1e-10
     with pytest.raises(sdc.SdcError):
         handle.split_nonsym(dev(a), reg, sdc.opts(prec=sdc.SDC_FP32_REFINE))
+
+
+def test_split_nonsym_order_one_and_one_sided(handle, sdc):
+    """RNEP's degenerate cases: order 1 (no split possible) and every
+    eigenvalue on one side of the curve."""
+    print_case(test="split_nonsym_edges")
+    res = handle.split_nonsym(dev(np.array([[3.0]])), sdc.region())
+    assert res.status == sdc.SDC_NO_SPLIT and res.info["n_inside"] == 0
+    res = handle.split_nonsym(dev(np.array([[0.25]])), sdc.region())
+    assert res.status == sdc.SDC_NO_SPLIT and res.info["n_inside"] == 1
+    a, lam = S.nonsym_problem(30, S.family_seed(6, 30), lam_lo=1.5, lam_hi=8.0)
+    res = handle.split_nonsym(dev(a), sdc.region())
+    assert res.status == sdc.SDC_NO_SPLIT and res.info["n_inside"] == 0

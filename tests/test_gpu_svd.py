@@ -87,3 +87,18 @@ def test_split_svd_edges(handle, sdc):
         handle.split_svd(A, sdc.region("disk", center=0.0, radius=1.0))
     with pytest.raises(sdc.SdcError):  # 30 x 20: ten zero eigenvalues of the embedding on Re z = 0
         handle.split_svd(A, sdc.region("halfplane", shift=0.0, scale=1.0))
+
+
+def test_split_svd_tiny_shapes(handle, sdc):
+    """1 x 1 and 1 x n / n x 1 matrices: the embedding of order m + n has the
+    one singular value and its negative (and zeros); a shift below it splits
+    off exactly that value, U and V are unit vectors along A's."""
+    print("CASE split_svd tiny", flush=True)
+    reg = sdc.region("halfplane", shift=0.5, scale=1.0)
+    for a in (np.array([[2.0]]), np.array([[1.0, 2.0, 2.0]]), np.array([[3.0], [4.0]])):
+        st, info, u, v, s11 = handle.split_svd(dev(a), reg, sdc.opts(seed=2))
+        sig = np.linalg.norm(a, 2)
+        assert st == 0 and info["k_lead"] == 1
+        u1, v1 = u.cpu().numpy()[:, 0], v.cpu().numpy()[:, 0]
+        assert abs(abs(u1 @ a @ v1) - sig) <= 1e-12 * sig
+        assert abs(s11.cpu().numpy()[0, 0] - sig) <= 1e-12 * sig
