@@ -6,23 +6,47 @@ Strategy, as the paper describes it:
   [c - R, c + R] and split at a random point x uniform in [c - R/2, c + R/2];
   the two halves inherit [x, c + R] and [c - R, x]; a split that finds every
   eigenvalue on one side still shrinks the interval (progress);
-* pencils (Sec. 3.5): split at the unit circle first; if every eigenvalue is
-  inside (outside), try circles of radius 2^{-2^k} (2^{2^k}); a block whose
-  eigenvalues lie outside a circle of radius r is continued on the swapped
-  pair (B, A), whose eigenvalues are the reciprocals and lie inside 1/r;
-  inside a known disk, split by random lines through the middle half of the
-  interval of real parts (vertical lines only: the oracle keeps real
-  arithmetic, so a complex-conjugate pair is never separated).
+* pencils (Sec. 3.5): split at the unit circle first.  If every eigenvalue
+  is inside, try radii 1/2, 1/4, 1/16, ... (2^{-2^k}) until a circle splits
+  the spectrum or finds it all outside; then the smallest bounding circle is
+  the last radius that had it all inside, and the block is split by lines
+  inside that disk.  If every eigenvalue is outside, try radii 2, 4, 16, ...
+  (2^{2^k}) until a circle splits it or finds it all inside; then the largest
+  circle with the spectrum outside is the last such radius r, and the pair is
+  swapped to (B, A), whose eigenvalues are the reciprocals and lie inside
+  1/r.  Running out of exponent range ends either search the same way.  A
+  block that split at a circle of radius r continues by lines: the inside
+  part inside r, the outside part swapped, inside 1/r.  Lines are vertical
+  (real arithmetic: a complex-conjugate pair is never separated), random in
+  the middle half of the block's interval of real parts.
+* A circle or line that hits the pseudospectrum makes the split step fail
+  (no convergence, or no split meeting the tolerance); a failed circle is
+  retried at a randomly perturbed radius r 2^{u - 1/2}, a failed line at a
+  fresh random line.  After repeated failures the block is given up and
+  returned as it is, with the bound on its spectrum that the search reached
+  (Sec. 3.6: a block Schur form with a bound on each block's
+  pseudospectrum).  Repeated failures while no circle at all has worked mean
+  that every curve meets the pseudospectrum, which is what a (nearly)
+  singular pencil does (Sec. 3.5): the block is then flagged near-singular.
 The coupling blocks E21 (and F21) are set to zero after each accepted split,
 and the transformations are applied to the rest of the pair and accumulated.
+
+Each leaf block carries a bound (re_lo, re_hi, radius, inverted): the
+eigenvalues mu of the block pair satisfy re_lo <= Re mu <= re_hi and
+|mu| <= radius, where mu = 1/lambda when inverted (the block was reached
+through a swap) and mu = lambda otherwise.  Infinite entries mean no bound.
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
 from .split import split_sym, split_pencil, OK, NO_SPLIT
 
-MAX_TRIES = 8
+MAX_TRIES = 8          # consecutive failed curves before a block is given up
+MAX_CIRCLE_FAILS = 3   # consecutive failed circles before a block is given up (near-singular)
+RADIUS_MIN, RADIUS_MAX = 2.0 ** -1000, 2.0 ** 1000   # exponent range of the radius search
 
 
 def _gershgorin(a: np.ndarray):
@@ -31,9 +55,49 @@ def _gershgorin(a: np.ndarray):
     return float(np.min(c - r)), float(np.max(c + r))
 
 
+def _lines(blk, lo, hi, swap):
+    """Continue a pencil block with lines inside the disk |mu| <= hi (lo = -hi)."""
+    return dict(blk, mode="line", lo=lo, hi=hi, radius=hi, swapped=blk["swapped"] ^ swap, tries=0)
+
+
+def _circle_no_split(blk, all_inside):
+    """Next state of a block in circle mode whose circle found every
+    eigenvalue on one side (Sec. 3.5).  Returns the new block state."""
+    r, rprev, d = blk["radius"], blk["rprev"], blk["dir"]
+    if all_inside:
+        if d > 0:   # growing: rprev had it all outside -> swap, inside 1/rprev
+            return _lines(blk, -1.0 / rprev, 1.0 / rprev, True)
+        nr = 0.5 if r >= 1.0 else r * r
+        if nr < RADIUS_MIN:  # out of exponent range: bounded by r, go on with lines
+            return _lines(blk, -r, r, False)
+        return dict(blk, radius=nr, rprev=r, dir=-1, tries=0)
+    if d < 0:       # shrinking: rprev had it all inside -> lines inside rprev
+        return _lines(blk, -rprev, rprev, False)
+    nr = 2.0 if r <= 1.0 else r * r
+    if nr > RADIUS_MAX:
+        return _lines(blk, -1.0 / r, 1.0 / r, True)
+    return dict(blk, radius=nr, rprev=r, dir=1, tries=0)
+
+
+def _bound(blk, symmetric):
+    """(re_lo, re_hi, radius, inverted) of a leaf block."""
+    if symmetric:
+        return (blk["lo"], blk["hi"], max(abs(blk["lo"]), abs(blk["hi"])), 0)
+    if blk["mode"] == "line":
+        return (blk["lo"], blk["hi"], blk["radius"], int(blk["swapped"]))
+    d, rprev = blk["dir"], blk["rprev"]
+    if d < 0:   # every eigenvalue inside rprev
+        return (-rprev, rprev, rprev, int(blk["swapped"]))
+    if d > 0:   # every eigenvalue outside rprev: reciprocals inside 1/rprev
+        return (-1.0 / rprev, 1.0 / rprev, 1.0 / rprev, int(not blk["swapped"]))
+    return (-math.inf, math.inf, math.inf, int(blk["swapped"]))
+
+
 def eig_dc(a: np.ndarray, b: np.ndarray | None = None, symmetric: bool = False, leaf_max: int = 64,
            seed: int = 0):
-    """Returns dict(T, S, QL, QR, blocks=[(s, e), ...], splits, unsplit)."""
+    """Returns dict(T, S, QL, QR, blocks=[(s, e), ...], bounds=[(re_lo, re_hi,
+    radius, inverted), ...] per block, splits, unsplit, near_singular,
+    log=[(s, e, mode, curve value, status, k), ...] per split attempt)."""
     a = np.array(a, dtype=np.float64)
     n = a.shape[0]
     t = a.copy()
@@ -41,12 +105,15 @@ def eig_dc(a: np.ndarray, b: np.ndarray | None = None, symmetric: bool = False, 
     ql = np.eye(n)
     qr = np.eye(n)
     rng = np.random.default_rng(seed)
+    base = dict(s=0, e=n, swapped=False, tries=0, dir=0, rprev=1.0)
     if symmetric:
         lo, hi = _gershgorin(a)
-        work = [dict(s=0, e=n, mode="line", lo=lo, hi=hi, swapped=False, radius=1.0, tries=0)]
+        if not hi > lo:
+            hi = lo + 1.0
+        work = [dict(base, mode="line", lo=lo, hi=hi, radius=max(abs(lo), abs(hi)))]
     else:
-        work = [dict(s=0, e=n, mode="circle", lo=-1.0, hi=1.0, swapped=False, radius=1.0, tries=0)]
-    leaves, splits, unsplit = [], 0, 0
+        work = [dict(base, mode="circle", lo=-math.inf, hi=math.inf, radius=1.0)]
+    leaves, splits, unsplit, near_singular, log = [], 0, 0, 0, []
     if n <= leaf_max:
         leaves, work = work, []
     while work:
@@ -56,9 +123,11 @@ def eig_dc(a: np.ndarray, b: np.ndarray | None = None, symmetric: bool = False, 
             m = e0 - s0
             if blk["mode"] == "circle":
                 region = {"kind": "disk", "center": 0.0, "radius": blk["radius"]}
+                curve = blk["radius"]
             else:
                 c, r = 0.5 * (blk["lo"] + blk["hi"]), 0.5 * (blk["hi"] - blk["lo"])
                 region = {"kind": "halfplane", "shift": c + (rng.uniform() - 0.5) * r, "scale": r if r > 0 else 1.0}
+                curve = region["shift"]
             splits += 1
             tb = t[s0:e0, s0:e0]
             if symmetric:
@@ -70,30 +139,30 @@ def eig_dc(a: np.ndarray, b: np.ndarray | None = None, symmetric: bool = False, 
                 res = split_pencil(pa, pb, region, seed=int(rng.integers(1 << 31)))
                 qlb, qrb = res.QL, res.Q
             k = res.k
+            log.append((s0, e0, blk["mode"], curve, res.status, k))
             if res.status != OK or not (0 < k < m):
-                nb = dict(blk, tries=blk["tries"] + 1)
-                if res.status == NO_SPLIT:
+                if res.status == NO_SPLIT:   # progress: the search narrows
                     all_inside = res.n_inside == m
                     if blk["mode"] == "circle":
-                        r0 = blk["radius"]
-                        nb["radius"] = (0.5 if r0 >= 1 else r0 * r0) if all_inside else (2.0 if r0 <= 1 else r0 * r0)
-                        if nb["tries"] >= 6:
-                            nb["mode"] = "line"
-                            nb["tries"] = 0
-                            if all_inside:
-                                nb["lo"], nb["hi"] = -r0, r0
-                            else:
-                                nb["swapped"] = not blk["swapped"]
-                                nb["lo"], nb["hi"] = -1.0 / r0, 1.0 / r0
+                        nb = _circle_no_split(blk, all_inside)
                     else:
+                        nb = dict(blk, tries=0)
                         if all_inside:
                             nb["hi"] = region["shift"]
                         else:
                             nb["lo"] = region["shift"]
-                        nb["tries"] = 0 if nb["hi"] > nb["lo"] else MAX_TRIES
-                if nb["tries"] >= MAX_TRIES:
+                        if not nb["hi"] > nb["lo"]:
+                            nb["tries"] = MAX_TRIES
+                else:                        # the curve met the pseudospectrum
+                    nb = dict(blk, tries=blk["tries"] + 1)
+                    if blk["mode"] == "circle":
+                        nb["radius"] = blk["radius"] * 2.0 ** (rng.uniform() - 0.5)
+                cap = MAX_CIRCLE_FAILS if nb["mode"] == "circle" else MAX_TRIES
+                if nb["tries"] >= cap:
                     unsplit += 1
-                    leaves.append(blk)
+                    if nb["mode"] == "circle":
+                        near_singular += 1
+                    leaves.append(dict(nb, unsplit=True))
                 else:
                     nxt.append(nb)
                 continue
@@ -118,8 +187,8 @@ def eig_dc(a: np.ndarray, b: np.ndarray | None = None, symmetric: bool = False, 
             c2 = dict(blk, s=s0 + k, tries=0)
             if blk["mode"] == "circle":
                 r0 = blk["radius"]
-                c1.update(mode="line", swapped=not blk["swapped"], lo=-1.0 / r0, hi=1.0 / r0)
-                c2.update(mode="line", lo=-r0, hi=r0)
+                c1 = _lines(c1, -1.0 / r0, 1.0 / r0, True)   # outside r0: reciprocals inside 1/r0
+                c2 = _lines(c2, -r0, r0, False)
             else:
                 c1["lo"] = region["shift"]
                 c2["hi"] = region["shift"]
@@ -128,7 +197,8 @@ def eig_dc(a: np.ndarray, b: np.ndarray | None = None, symmetric: bool = False, 
         work = nxt
     leaves.sort(key=lambda x: x["s"])
     return dict(T=t, S=s, QL=None if symmetric else ql, QR=qr, blocks=[(x["s"], x["e"]) for x in leaves],
-                splits=splits, unsplit=unsplit)
+                bounds=[_bound(x, symmetric) for x in leaves], unsplit_blocks=[bool(x.get("unsplit")) for x in leaves],
+                splits=splits, unsplit=unsplit, near_singular=near_singular, log=log)
 
 
 def block_eigvals(t: np.ndarray, s: np.ndarray | None, starts, symmetric: bool):

@@ -207,11 +207,18 @@ def split_pencil(a: np.ndarray, b: np.ndarray, region: dict, gauss: GaussSource 
         k_rho_l, gap_l, side_l = rank_from_rho(rho_l)
         a_hat = ql_.T @ a @ qr_
         b_hat = ql_.T @ b @ qr_
-        if side != "split" or side_l != "split":
+        if side != "split" and side == side_l:
             k = 0 if side == "inside" else n
-            st = NO_SPLIT if (converged and side == side_l) else (NOT_CONVERGED if not converged else RANK_AMBIGUOUS)
+            st = NO_SPLIT if converged else NOT_CONVERGED
             return SplitResult(st, k, n - k, qr_, ql_, a_hat, b_hat, 0.0, right.p, left.p,
                                k_rho, gap, attempt + 1, rho_r)
+        if side != side_l:
+            # the two sides disagree about the spectrum being one-sided: a
+            # bad draw (or iterates short of convergence); try a new draw,
+            # and report the rank as unknown (-1) if none agrees
+            last = SplitResult(NOT_CONVERGED if not converged else RANK_AMBIGUOUS, -1, -1, qr_, ql_,
+                               a_hat, b_hat, np.inf, right.p, left.p, k_rho, gap, attempt + 1, rho_r)
+            continue
         k, e, _ = split_search(a_hat, norm_a, b_hat, norm_b)
         cand = SplitResult(OK, k, n - k, qr_, ql_, a_hat, b_hat, e, right.p, left.p, k_rho,
                            min(gap, gap_l), attempt + 1, rho_r)
@@ -221,6 +228,8 @@ def split_pencil(a: np.ndarray, b: np.ndarray, region: dict, gauss: GaussSource 
             if not converged:
                 cand.status = NOT_CONVERGED
             return cand
+    if best is None:
+        return last
     best.status = NOT_CONVERGED if not converged else RANK_AMBIGUOUS
     return best
 

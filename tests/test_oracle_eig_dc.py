@@ -121,3 +121,75 @@ def test_block_eigvals_after_eig_dc_give_the_spectrum():
     starts = [b[0] for b in r["blocks"]] + [48]
     wr, _ = block_eigvals(r["T"], None, starts, True)
     assert np.max(np.abs(np.sort(wr) - np.sort(d))) <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# The pencil search of Sec. 3.5: circles 2^{-+2^k} down (up) to the smallest
+# (largest) bounding circle, then lines; the reciprocal pair after a swap
+# ---------------------------------------------------------------------------
+
+def _check_bounds(r, tol=1e-9):
+    """Every block's eigenvalues (reciprocals when inverted) lie in its bound."""
+    for (a0, a1), (lo, hi, rad, inv) in zip(r["blocks"], r["bounds"]):
+        ev = sla.eigvals(r["T"][a0:a1, a0:a1], r["S"][a0:a1, a0:a1])
+        mu = 1.0 / ev if inv else ev
+        assert np.all(mu.real >= lo - tol) and np.all(mu.real <= hi + tol), ((a0, a1), (lo, hi), mu)
+        assert np.all(np.abs(mu) <= rad * (1 + tol)), ((a0, a1), rad, mu)
+
+
+@pytest.mark.parametrize("lo,hi,radii,statuses", [
+    # all inside the unit circle: 1, 1/2 (still all inside), 1/4 splits
+    (0.02, 0.4, [1.0, 0.5, 0.25], [2, 2, 0]),
+    # all outside: 1, 2 (still all outside), 4 splits
+    (2.5, 50.0, [1.0, 2.0, 4.0], [2, 2, 0]),
+    # inside 1 but outside 1/2: the smallest bounding circle is 1; lines inside it
+    (0.55, 0.95, [1.0, 0.5], [2, 2]),
+    # outside 1 but inside 2: the largest circle with all outside is 1; swap, lines
+    (1.1, 1.9, [1.0, 2.0], [2, 2]),
+])
+def test_circle_search_stops_at_the_bounding_circle(lo, hi, radii, statuses):
+    """The radius sequence of Sec. 3.5 for spectra entirely inside or outside
+    the unit circle: it runs 2^{-2^k} (2^{2^k}) only until a circle splits the
+    spectrum or finds it all on the other side, and never turns around; the
+    block spectra are the construction's and every block lies in its bound."""
+    p = S.pencil_problem(40, 91, lam_lo=lo, lam_hi=hi)
+    r = eig_dc(p["A"], p["B"], leaf_max=8, seed=5)
+    circ = [x for x in r["log"] if x[2] == "circle"]
+    assert [x[3] for x in circ] == radii
+    assert [x[4] for x in circ] == statuses
+    assert r["unsplit"] == 0 and r["near_singular"] == 0
+    got = np.sort_complex(_block_spectrum(r["T"], r["S"], r["blocks"]))
+    want = np.sort_complex(p["lam"].astype(complex))
+    assert np.max(np.abs(got - want) / np.abs(want)) <= 1e-12
+    _check_bounds(r)
+
+
+def test_singular_pencil_is_flagged_near_singular():
+    """A pencil with a common null vector of A and B (det(A - lambda B) = 0 for
+    every lambda) meets the pseudospectrum on every curve (Sec. 3.5): the
+    repeated squaring never converges, the block is given up after a few
+    circles, returned whole with no bound, and flagged."""
+    p = S.pencil_problem(24, 77)
+    t, s = p["T"].copy(), p["S"].copy()
+    t[3, 3] = s[3, 3] = 0.0
+    a, b = p["U"] @ t @ p["V"].T, p["U"] @ s @ p["V"].T
+    r = eig_dc(a, b, leaf_max=4, seed=3)
+    assert r["near_singular"] == 1 and r["unsplit"] == 1
+    assert r["blocks"] == [(0, 24)] and r["bounds"][0][2] == np.inf
+    assert all(x[2] == "circle" and x[4] == 1 for x in r["log"])  # NOT_CONVERGED on every circle
+
+
+def test_jordan_block_is_returned_unsplit_with_a_bound():
+    """E4's matrix (a 16 x 16 Jordan block at 0.1 among random eigenvalues,
+    Sec. 5): lines through the Jordan block's pseudospectrum cannot split it,
+    so it comes back as one unsplit block (Sec. 3.6) whose bound holds its
+    eigenvalues; it is not a singular pencil (B = I)."""
+    n = 32
+    a = S.jordan_problem(n, S.family_seed(7, 4))
+    r = eig_dc(a, np.eye(n), leaf_max=2, seed=3)
+    assert r["near_singular"] == 0 and r["unsplit"] >= 1
+    blk = [(b, bd) for b, bd, u in zip(r["blocks"], r["bounds"], r["unsplit_blocks"]) if u]
+    assert len(blk) == 1
+    (a0, a1), (lo, hi, rad, inv) = blk[0]
+    assert a1 - a0 >= 16 and inv == 0 and lo < 0.1 < hi
+    _check_bounds(r, tol=1e-6)
