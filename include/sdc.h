@@ -29,7 +29,8 @@
  *     solving X A11 - A22 X = E21 by conjugate gradients, Q <- Q [I -X^T; X I]
  *     re-orthonormalized, up to 3 rounds, until ||E21||_1/||A||_1 <=
  *     split_tol.  The refinement needs the two eigenvalue groups separated by
- *     a point (a half-plane split).  A problem whose FP32 attempts all fail
+ *     a point, so SDC_FP32_REFINE is accepted only with an SDC_HALFPLANE
+ *     region (other kinds: SDC_ERR_INVALID).  A problem whose FP32 attempts all fail
  *     (any status other than SDC_OK and SDC_NO_SPLIT) is split again in FP64
  *     and info->fp64_fallback is set.
  *   - Eigenvalues of the pencil A - lambda B are the roots of
@@ -100,7 +101,9 @@ typedef struct {
 
 typedef struct {
     int n;
-    int k_lead;          /* leading block size (eigenvalues outside) */
+    int k_lead;          /* leading block size (eigenvalues outside); -1 (with n_inside -1)
+                            when no draw split and a pencil's right and left sides
+                            disagreed about every eigenvalue lying on one side */
     int n_inside;        /* n - k_lead: eigenvalues inside the region */
     int iters_right;     /* IRS iterations p on (A, B) */
     int iters_left;      /* IRS iterations p on (A^T, B^T) (pencils) */
@@ -190,7 +193,11 @@ typedef struct {
     int splits;          /* split steps attempted (every call of the split step) */
     int accepted;        /* split steps that divided a block */
     int levels;          /* recursion levels run (each level is one batched call) */
-    int unsplit;         /* blocks larger than leaf_max given up on (pseudospectrum hit) */
+    int unsplit;         /* blocks larger than leaf_max given up on (every curve tried met
+                            their pseudospectrum, Sec. 3.6) */
+    int near_singular;   /* of those, blocks given up while no circle had yet split or bounded
+                            them: every curve meets the pseudospectrum, the mark of a (nearly)
+                            singular pencil (Sec. 3.5) */
     int iters_total;     /* sum of IRS iterations over all split steps and sides */
     double nominal_flops;/* sum over split steps of (40/3 (p_R + p_L) + 32) m^3 (pencil)
                             or (40/3 p + 16) m^3 (symmetric), the flop model of the
@@ -201,26 +208,49 @@ typedef struct {
                             subproblem in the 1-norm */
 } sdc_dc_info_t;
 
+/* Bound on the eigenvalues of one diagonal block of sdc_eig_dc's result: the
+ * eigenvalues mu of the block (mu = 1/lambda when `inverted`, lambda
+ * otherwise) satisfy re_lo <= Re mu <= re_hi and |mu| <= radius, up to the
+ * backward error of the splits.  Infinite entries mean no bound is known.
+ * For a block given up on (`unsplit` = 1) this is the block Schur form's
+ * bound on the block's pseudospectrum that Sec. 3.6 returns. */
+typedef struct {
+    double re_lo, re_hi, radius;
+    int inverted;
+    int unsplit;
+} sdc_block_bound_t;
+
 /* Randomized spectral divide-and-conquer to blocks of order <= leaf_max
  * (Sec. 3.3-3.5).  symmetric != 0: A symmetric, B ignored (B = I), splits at
- * a random point of the middle half of the Gershgorin interval of each block
- * (Sec. 3.4).  Otherwise the pencil is split first at the unit circle, then
- * (if every eigenvalue was on one side) at circles of radius 2^{-+2^k}, then
- * at random vertical lines through the middle half of each block's interval
- * of real parts, with A and B swapped for blocks outside a circle (their
- * reciprocal eigenvalues lie inside) (Sec. 3.5; real lines only, so a
- * complex-conjugate pair is never separated).
+ * a random point of the middle half of the current interval of each block,
+ * starting from A's Gershgorin interval (Sec. 3.4).  Otherwise the pencil is
+ * split first at the unit circle.  If every eigenvalue is inside, radii
+ * 1/2, 1/4, 1/16, ... (2^{-2^k}) follow until a circle splits the spectrum or
+ * finds it all outside; the last circle with everything inside bounds the
+ * block, which continues with random vertical lines through the middle half
+ * of that disk.  If every eigenvalue is outside, radii 2, 4, 16, ...
+ * follow the same way, and the block continues on the swapped pair (B, A),
+ * whose eigenvalues (the reciprocals) lie inside 1/r for the largest radius r
+ * with everything outside (Sec. 3.5).  A block split at a circle of radius r
+ * continues with lines inside r (its inside part) and, swapped, inside 1/r
+ * (its outside part).  Lines are real, so a complex-conjugate pair is never
+ * separated.  A circle that meets the pseudospectrum is retried at a
+ * perturbed radius; after 3 failed circles with none that worked the block is
+ * given up and counted in info->near_singular, after 8 failed lines it is
+ * given up with the bound the search reached (info->unsplit counts both).
  * Outputs (device, column-major): T = Q_L^T A Q_R and, for pencils,
  * S = Q_L^T B Q_R, block upper triangular with the strictly-lower coupling
  * blocks set to zero; QL and QR (may be NULL) accumulate the transformations
  * (QL is unused for symmetric A, where QR = Q).  block_start (HOST, n + 1
  * ints) receives the first index of each diagonal block and n at position
- * *nblocks.  A block that cannot be split after repeated draws is returned as
- * is (counted in info->unsplit).  Returns SDC_OK or a negative error. */
+ * *nblocks.  bounds (HOST, may be NULL; room for n entries) receives one
+ * sdc_block_bound_t per block.  opts->prec SDC_FP32_REFINE is accepted for
+ * symmetric A (every split is at a half plane).  Returns SDC_OK or a
+ * negative error. */
 sdc_status_t sdc_eig_dc(sdc_handle_t h, int n, const double* A, int lda, const double* B, int ldb,
                         int symmetric, int leaf_max, const sdc_opts_t* opts, double* T, int ldt,
                         double* S, int lds, double* QL, int ldql, double* QR, int ldqr,
-                        int* nblocks, int* block_start, sdc_dc_info_t* info);
+                        int* nblocks, int* block_start, sdc_block_bound_t* bounds, sdc_dc_info_t* info);
 
 /* RSVD split (the singular value problem of Sec. 3, through the symmetric
  * embedding E = [0 A; A^T 0] of order m + n, whose eigenvalues are the

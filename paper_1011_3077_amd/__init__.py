@@ -61,11 +61,16 @@ class Info(C.Structure):
 
 class DcInfo(C.Structure):
     _fields_ = [("n", C.c_int), ("nblocks", C.c_int), ("splits", C.c_int), ("accepted", C.c_int),
-                ("levels", C.c_int), ("unsplit", C.c_int), ("iters_total", C.c_int),
+                ("levels", C.c_int), ("unsplit", C.c_int), ("near_singular", C.c_int), ("iters_total", C.c_int),
                 ("nominal_flops", C.c_double), ("ms", C.c_double), ("e21_max", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class BlockBound(C.Structure):
+    _fields_ = [("re_lo", C.c_double), ("re_hi", C.c_double), ("radius", C.c_double), ("inverted", C.c_int),
+                ("unsplit", C.c_int)]
 
 
 class KernelStats(C.Structure):
@@ -118,7 +123,7 @@ lib.sdc_split_sym_batched.argtypes = [_P, _I, C.POINTER(_I), C.POINTER(_P), C.PO
                                       C.POINTER(_P), C.POINTER(_I), C.POINTER(Info), C.POINTER(_I)]
 lib.sdc_split_sym_batched.restype = _I
 lib.sdc_eig_dc.argtypes = [_P, _I, _P, _I, _P, _I, _I, _I, C.POINTER(Opts), _P, _I, _P, _I, _P, _I, _P, _I,
-                           C.POINTER(_I), C.POINTER(_I), C.POINTER(DcInfo)]
+                           C.POINTER(_I), C.POINTER(_I), C.POINTER(BlockBound), C.POINTER(DcInfo)]
 lib.sdc_eig_dc.restype = _I
 lib.sdc_split_nonsym.argtypes = [_P, _I, _P, _I, Region, C.POINTER(Opts), _P, _I, _P, _I, C.POINTER(Info)]
 lib.sdc_split_nonsym.restype = _I
@@ -282,7 +287,9 @@ class Handle:
     def eig_dc(self, A, B=None, leaf_max: int = 64, o: Opts | None = None, symmetric: bool = False,
                factors: bool = True):
         """Divide and conquer to blocks <= leaf_max.  Returns
-        (status, T, S, QL, QR, block_starts, info); S/QL are None for symmetric."""
+        (status, T, S, QL, QR, block_starts, info); S/QL are None for symmetric.
+        info["bounds"] holds one (re_lo, re_hi, radius, inverted, unsplit)
+        tuple per block (sdc_block_bound_t)."""
         n = A.shape[0]
         a = _cm(A)
         b = _cm(B) if (B is not None and not symmetric) else None
@@ -293,12 +300,15 @@ class Handle:
         nb = C.c_int()
         starts = (_I * (n + 1))()
         info = DcInfo()
+        bounds = (BlockBound * max(n, 1))()
         ptr = lambda x: None if x is None else x.data_ptr()
         st = _check(lib.sdc_eig_dc(self._h, n, a.data_ptr(), n, ptr(b), n, int(symmetric), leaf_max,
                                    C.byref(o or opts()), t.data_ptr(), n, ptr(s), n, ptr(ql), n, ptr(qr), n,
-                                   C.byref(nb), starts, C.byref(info)))
+                                   C.byref(nb), starts, bounds, C.byref(info)))
         tr = lambda x: None if x is None else x.t()
-        return st, tr(t), tr(s), tr(ql), tr(qr), [starts[i] for i in range(nb.value + 1)], info.as_dict()
+        d = info.as_dict()
+        d["bounds"] = [(x.re_lo, x.re_hi, x.radius, x.inverted, x.unsplit) for x in bounds[:nb.value]]
+        return st, tr(t), tr(s), tr(ql), tr(qr), [starts[i] for i in range(nb.value + 1)], d
 
     def split_svd(self, A, reg: Region | None = None, o: Opts | None = None):
         """RSVD split of the m x n A at the half plane reg (see sdc_split_svd):

@@ -138,7 +138,7 @@ sdc_status_t sdc_split_sym(sdc_handle_t hd, int n, const double* A, int lda, sdc
     std::vector<SplitJob> jobs(1);
     SplitJob& j = jobs[0];
     j.n = n; j.pencil = false; j.A = A; j.lda = lda; j.region = region; j.opts = resolve(opts);
-    if (!prec_ok(j.opts, false)) return SDC_ERR_INVALID;
+    if (!prec_ok(j.opts, false, region.kind)) return SDC_ERR_INVALID;
     j.Q = Q; j.ldq = ldq; j.Ahat = Ahat; j.ldah = ldah;
     sdc::ProfScope ps(h);
     const int r = sdc::run_split_jobs(h, jobs);
@@ -161,7 +161,7 @@ sdc_status_t sdc_split_nonsym(sdc_handle_t hd, int n, const double* A, int lda, 
     std::vector<SplitJob> jobs(1);
     SplitJob& j = jobs[0];
     j.n = n; j.pencil = false; j.nonsym = true; j.A = A; j.lda = lda; j.region = region; j.opts = resolve(opts);
-    if (!prec_ok(j.opts, true)) return SDC_ERR_INVALID;  // FP64 only
+    if (!prec_ok(j.opts, true, region.kind)) return SDC_ERR_INVALID;  // FP64 only
     j.Q = Q; j.ldq = ldq; j.Ahat = Ahat; j.ldah = ldah;
     sdc::ProfScope ps(h);
     const int r = sdc::run_split_jobs(h, jobs);
@@ -187,7 +187,7 @@ sdc_status_t sdc_split_pencil(sdc_handle_t hd, int n, const double* A, int lda, 
     SplitJob& j = jobs[0];
     j.n = n; j.pencil = true; j.A = A; j.lda = lda; j.B = B; j.ldb = ldb; j.region = region;
     j.opts = resolve(opts);
-    if (!prec_ok(j.opts, true)) return SDC_ERR_INVALID;
+    if (!prec_ok(j.opts, true, region.kind)) return SDC_ERR_INVALID;
     j.Q = QR; j.ldq = ldqr; j.QL = QL; j.ldql = ldql; j.Ahat = Ahat; j.ldah = ldah; j.Bhat = Bhat; j.ldbh = ldbh;
     sdc::ProfScope ps(h);
     const int r = sdc::run_split_jobs(h, jobs);
@@ -205,11 +205,12 @@ sdc_status_t sdc_split_sym_batched(sdc_handle_t hd, int count, const int* n, con
     if (count == 0) return SDC_OK;
     if (!n || !A || !lda || !regions || !Q || !ldq || !Ahat || !ldah || !statuses) return SDC_ERR_INVALID;
     const sdc_opts_t o = resolve(opts);
-    if (o.G || !prec_ok(o, false)) return SDC_ERR_INVALID;
+    if (o.G) return SDC_ERR_INVALID;
     std::vector<SplitJob> jobs;
     std::vector<int> idx;
     for (int i = 0; i < count; ++i) {
-        if (n[i] < 0 || n[i] > kMaxN || lda[i] < n[i] || ldq[i] < n[i] || ldah[i] < n[i] || !region_ok(regions[i]))
+        if (n[i] < 0 || n[i] > kMaxN || lda[i] < n[i] || ldq[i] < n[i] || ldah[i] < n[i] || !region_ok(regions[i]) ||
+            !prec_ok(o, false, regions[i].kind))
             return SDC_ERR_INVALID;
         if (n[i] > 0 && (!A[i] || !Q[i] || !Ahat[i])) return SDC_ERR_INVALID;
     }
@@ -239,7 +240,8 @@ sdc_status_t sdc_split_sym_batched(sdc_handle_t hd, int count, const int* n, con
 
 sdc_status_t sdc_eig_dc(sdc_handle_t hd, int n, const double* A, int lda, const double* B, int ldb, int symmetric,
                         int leaf_max, const sdc_opts_t* opts, double* T, int ldt, double* S, int lds, double* QL,
-                        int ldql, double* QR, int ldqr, int* nblocks, int* block_start, sdc_dc_info_t* info) {
+                        int ldql, double* QR, int ldqr, int* nblocks, int* block_start, sdc_block_bound_t* bounds,
+                        sdc_dc_info_t* info) {
     if (!hd || n < 0 || n > kMaxN || !nblocks || !block_start || leaf_max < 1) return SDC_ERR_INVALID;
     if (n > 0 && (!A || lda < n || !T || ldt < n)) return SDC_ERR_INVALID;
     if (!symmetric && n > 0 && (!B || ldb < n || !S || lds < n)) return SDC_ERR_INVALID;
@@ -253,13 +255,13 @@ sdc_status_t sdc_eig_dc(sdc_handle_t hd, int n, const double* A, int lda, const 
         return SDC_OK;
     }
     const sdc_opts_t o = resolve(opts);
-    if (o.G || !prec_ok(o, !symmetric)) return SDC_ERR_INVALID;
+    if (o.G || !prec_ok(o, !symmetric, SDC_HALFPLANE)) return SDC_ERR_INVALID;
     Handle& h = hd->h;
     if (use_device(h) != SDC_OK) return SDC_ERR_DEVICE;
     sdc::ProfScope ps(h);
     const int r = sdc::run_eig_dc(h, n, A, lda, symmetric ? nullptr : B, ldb, symmetric ? 1 : 0, leaf_max, o, T, ldt,
                                   symmetric ? nullptr : S, lds, symmetric ? nullptr : QL, ldql, QR, ldqr, nblocks,
-                                  block_start, info);
+                                  block_start, bounds, info);
     resolve_profile(h);
     return (sdc_status_t)r;
 }
@@ -303,7 +305,7 @@ sdc_status_t sdc_split_svd(sdc_handle_t hd, int m, int n, const double* A, int l
     Handle& h = hd->h;
     if (use_device(h) != SDC_OK) return SDC_ERR_DEVICE;
     const sdc_opts_t o = resolve(opts);
-    if (!prec_ok(o, false)) return SDC_ERR_INVALID;
+    if (!prec_ok(o, false, region.kind)) return SDC_ERR_INVALID;
     int status = 0;
     sdc::ProfScope ps(h);
     const int rc = sdc::run_split_svd(h, m, n, A, lda, region, o, U, ldu, V, ldv, S11, lds11, info, &status);

@@ -13,11 +13,20 @@
 //
 // Split curves: symmetric blocks use a random point of the middle half of
 // their interval (initially the Gershgorin interval, Sec. 3.4).  Pencils use
-// the unit circle first, circles of radius 2^{-2^k} (2^{2^k}) when every
-// eigenvalue was inside (outside), then random vertical lines through the
-// middle half of the block's interval of real parts; a block whose
-// eigenvalues lie outside a circle is continued on the swapped pair (B, A),
-// whose eigenvalues are the reciprocals and lie inside (Sec. 3.5).
+// the unit circle first.  When a circle finds every eigenvalue inside, the
+// radius shrinks through 2^{-2^k} until a circle splits the spectrum or finds
+// it all outside; the last radius with everything inside is then the
+// smallest bounding circle, and the block continues with random vertical
+// lines through the middle half of that disk.  When everything is outside,
+// the radius grows through 2^{2^k} the same way, and the largest circle with
+// everything outside (radius r) leads to the swapped pair (B, A), whose
+// eigenvalues are the reciprocals and lie inside 1/r (Sec. 3.5).  A circle
+// that meets the pseudospectrum (no convergence, no split within split_tol)
+// is retried at a randomly perturbed radius; a block whose circles fail
+// repeatedly while none has worked is given up and flagged near-singular
+// (every curve meets its pseudospectrum, Sec. 3.5).  A block whose lines fail
+// repeatedly is given up with the bound the search reached (a block of the
+// Schur form with a bound on its pseudospectrum, Sec. 3.6).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -40,11 +49,68 @@ struct Block {
     int swapped = 0;     // pencil split as (S_block, T_block): eigenvalues 1/lambda
     int mode = MODE_LINE;
     double lo = -1, hi = 1;  // interval of real parts (line mode)
-    double radius = 1;       // circle mode
-    int tries = 0;
+    double radius = 1;       // circle mode: the circle tried next; line mode: |mu| bound
+    double rprev = 1;        // circle mode: the previous radius of the search
+    int dir = 0;             // circle mode: 0 first circle, -1 shrinking, +1 growing
+    int tries = 0;           // consecutive failed curves
+    int unsplit = 0;
 };
 
-constexpr int kMaxTries = 8;
+constexpr int kMaxTries = 8;         // failed lines before a block is given up
+constexpr int kMaxCircleFails = 3;   // failed circles before a block is given up (near-singular)
+constexpr double kRadiusMin = 0x1p-1000, kRadiusMax = 0x1p+1000;  // exponent range of the search
+
+// Continue a pencil block with lines inside the disk |mu| <= r (swap: on the
+// reciprocal pair).
+Block to_lines(Block b, double r, bool swap) {
+    b.mode = MODE_LINE;
+    b.lo = -r;
+    b.hi = r;
+    b.radius = r;
+    b.swapped ^= swap ? 1 : 0;
+    b.tries = 0;
+    return b;
+}
+
+// Next state of a circle-mode block whose circle found every eigenvalue on
+// one side (Sec. 3.5): the search never turns around.
+Block circle_no_split(const Block& b, bool all_inside) {
+    const double r = b.radius;
+    if (all_inside) {
+        if (b.dir > 0) return to_lines(b, 1.0 / b.rprev, true);  // growing: rprev had all outside
+        const double nr = r >= 1.0 ? 0.5 : r * r;
+        if (nr < kRadiusMin) return to_lines(b, r, false);
+        Block nb = b;
+        nb.radius = nr; nb.rprev = r; nb.dir = -1; nb.tries = 0;
+        return nb;
+    }
+    if (b.dir < 0) return to_lines(b, b.rprev, false);          // shrinking: rprev had all inside
+    const double nr = r <= 1.0 ? 2.0 : r * r;
+    if (nr > kRadiusMax) return to_lines(b, 1.0 / r, true);
+    Block nb = b;
+    nb.radius = nr; nb.rprev = r; nb.dir = 1; nb.tries = 0;
+    return nb;
+}
+
+// The bound on a leaf block's eigenvalues mu (mu = 1/lambda when inverted).
+sdc_block_bound_t block_bound(const Block& b, bool symmetric) {
+    sdc_block_bound_t o{};
+    o.unsplit = b.unsplit;
+    if (symmetric) {
+        o.re_lo = b.lo; o.re_hi = b.hi; o.radius = std::max(std::fabs(b.lo), std::fabs(b.hi));
+        return o;
+    }
+    if (b.mode == MODE_LINE) {
+        o.re_lo = b.lo; o.re_hi = b.hi; o.radius = b.radius; o.inverted = b.swapped;
+    } else if (b.dir < 0) {
+        o.re_lo = -b.rprev; o.re_hi = b.rprev; o.radius = b.rprev; o.inverted = b.swapped;
+    } else if (b.dir > 0) {
+        o.re_lo = -1.0 / b.rprev; o.re_hi = 1.0 / b.rprev; o.radius = 1.0 / b.rprev; o.inverted = !b.swapped;
+    } else {
+        o.re_lo = -INFINITY; o.re_hi = INFINITY; o.radius = INFINITY; o.inverted = b.swapped;
+    }
+    return o;
+}
 
 int ensure_ws2(Handle& h, size_t bytes) {
     if (bytes <= h.ws2_size) return SDC_OK;
@@ -104,7 +170,7 @@ int launch_gemm(Handle& h, const std::vector<GemmDesc<double>>& v) {
 
 int run_eig_dc(Handle& h, int n, const double* A, int lda, const double* B, int ldb, int symmetric, int leaf_max,
                const sdc_opts_t& opts, double* T, int ldt, double* S, int lds, double* QL, int ldql, double* QR,
-               int ldqr, int* nblocks, int* block_start, sdc_dc_info_t* info) {
+               int ldqr, int* nblocks, int* block_start, sdc_block_bound_t* bounds, sdc_dc_info_t* info) {
     const auto t0 = std::chrono::steady_clock::now();
     CHK(ensure_desc(h, (size_t)(256 << 10)));
     h.desc_off = 0;
@@ -145,6 +211,7 @@ int run_eig_dc(Handle& h, int n, const double* A, int lda, const double* B, int 
         top.mode = MODE_LINE;
         top.lo = lo;
         top.hi = hi;
+        top.radius = std::max(std::fabs(lo), std::fabs(hi));
     } else {
         top.mode = MODE_CIRCLE;
         top.radius = 1.0;
@@ -231,34 +298,28 @@ int run_eig_dc(Handle& h, int n, const double* A, int lda, const double* B, int 
             const bool ok = j.status == SDC_OK && k > 0 && k < m;
             if (!ok) {
                 Block nb = b;
-                ++nb.tries;
                 if (j.status == SDC_NO_SPLIT) {
+                    // progress: the search narrows
                     const bool all_inside = j.info.n_inside == m;
                     if (b.mode == MODE_CIRCLE) {
-                        // radii 2^{-2^k} when everything is inside, 2^{2^k} when outside
-                        if (all_inside) nb.radius = b.radius >= 1.0 ? 0.5 : b.radius * b.radius;
-                        else nb.radius = b.radius <= 1.0 ? 2.0 : b.radius * b.radius;
-                        if (nb.tries >= 6) {
-                            // give up on circles: continue with lines inside the last circle
-                            nb.mode = MODE_LINE;
-                            if (all_inside) {
-                                nb.lo = -b.radius; nb.hi = b.radius;
-                            } else {
-                                nb.swapped ^= 1; nb.lo = -1.0 / b.radius; nb.hi = 1.0 / b.radius;
-                            }
-                            nb.tries = 0;
-                        }
+                        nb = circle_no_split(b, all_inside);
                     } else {
-                        // the line missed the spectrum: the interval shrinks (progress, Sec. 3.4)
+                        // the line missed the spectrum: the interval shrinks (Sec. 3.4)
                         if (all_inside) nb.hi = regs[i].shift;
                         else nb.lo = regs[i].shift;
                         nb.tries = 0;
                         if (!(nb.hi > nb.lo)) nb.tries = kMaxTries;
                     }
+                } else {
+                    // the curve met the pseudospectrum: perturb the circle, or draw a new line
+                    ++nb.tries;
+                    if (b.mode == MODE_CIRCLE) nb.radius = b.radius * std::exp2(U(rng) - 0.5);
                 }
-                if (nb.tries >= kMaxTries) {
+                if (nb.tries >= (nb.mode == MODE_CIRCLE ? kMaxCircleFails : kMaxTries)) {
                     ++st.unsplit;
-                    leaves.push_back(b);
+                    if (nb.mode == MODE_CIRCLE) ++st.near_singular;
+                    nb.unsplit = 1;
+                    leaves.push_back(nb);
                 } else {
                     next.push_back(nb);
                 }
@@ -320,11 +381,9 @@ int run_eig_dc(Handle& h, int n, const double* A, int lda, const double* B, int 
             c2.s = b.s + k;
             c1.tries = c2.tries = 0;
             if (b.mode == MODE_CIRCLE) {
-                const double r = b.radius;
-                c1.mode = c2.mode = MODE_LINE;
-                c1.swapped = b.swapped ^ 1;
-                c1.lo = -1.0 / r; c1.hi = 1.0 / r;
-                c2.lo = -r; c2.hi = r;
+                // outside the circle r: reciprocals inside 1/r; inside: lines inside r
+                c1 = to_lines(c1, 1.0 / b.radius, true);
+                c2 = to_lines(c2, b.radius, false);
             } else {
                 c1.lo = regs[i].shift;
                 c2.hi = regs[i].shift;
@@ -350,7 +409,10 @@ int run_eig_dc(Handle& h, int n, const double* A, int lda, const double* B, int 
     }
     std::sort(leaves.begin(), leaves.end(), [](const Block& a, const Block& b) { return a.s < b.s; });
     int nb = 0;
-    for (const Block& b : leaves) block_start[nb++] = b.s;
+    for (const Block& b : leaves) {
+        if (bounds) bounds[nb] = block_bound(b, symmetric != 0);
+        block_start[nb++] = b.s;
+    }
     block_start[nb] = n;
     *nblocks = nb;
     st.nblocks = nb;

@@ -809,29 +809,47 @@ static int split_pass_refined(Handle& h, std::vector<JobWs*>& js) {
     return SDC_OK;
 }
 
-// Accept / retry / classify one attempt (the oracle's rule, Alg. 4 line 5:
-// accept when the minimized norm is small, cross-checked with the rank the
-// GRURV diagonals reveal).  Returns true when the job is finished.
+// Accept / retry / classify one attempt (Alg. 4: the split point minimizes
+// the backward error e(k) and the split is accepted when e(k*) <= split_tol;
+// the rank read off the GRURV diagonals decides only whether every
+// eigenvalue lies on one side, and is reported).  A pencil whose right and
+// left sides disagree about that is retried with a new draw, as a split above
+// split_tol is.  Returns true when the job is finished.
 static bool decide(JobWs& w, bool& needs_best) {
     SplitJob& j = *w.job;
     const int n = j.n;
     double gap = 1, gapl = 1;
     int side = SIDE_SPLIT, sidel = SIDE_SPLIT;
     const int krho = rank_from_rho(w.rho_r, gap, side);
-    int krhol = krho;
-    if (j.pencil) krhol = rank_from_rho(w.rho_l, gapl, sidel);
+    if (j.pencil) rank_from_rho(w.rho_l, gapl, sidel);
+    else sidel = side;
     const bool conv = sides_converged(w);
     needs_best = false;
     j.info.k_rho = krho;
     j.info.rank_gap = j.pencil ? std::min(gap, gapl) : gap;
     j.info.attempts = w.attempt + 1;
-    if (side != SIDE_SPLIT || (j.pencil && sidel != SIDE_SPLIT)) {
+    if (side != SIDE_SPLIT && side == sidel) {
         const int k = side == SIDE_INSIDE ? 0 : n;
-        if (!j.pencil) w.status = conv ? SDC_NO_SPLIT : SDC_NOT_CONVERGED;
-        else w.status = (conv && side == sidel) ? SDC_NO_SPLIT : (conv ? SDC_RANK_AMBIGUOUS : SDC_NOT_CONVERGED);
+        w.status = conv ? SDC_NO_SPLIT : SDC_NOT_CONVERGED;
         j.info.k_lead = k;
         j.info.n_inside = n - k;
         j.info.e21_rel = 0.0;
+        return true;
+    }
+    if (side != sidel) {
+        // the two sides disagree about the spectrum being one-sided: a bad
+        // draw, or iterates short of convergence
+        if (w.attempt < j.opts.max_retries) {
+            ++w.attempt;
+            return false;
+        }
+        w.status = conv ? SDC_RANK_AMBIGUOUS : SDC_NOT_CONVERGED;
+        needs_best = w.best_attempt >= 0 && w.best_attempt != w.attempt;
+        if (!needs_best) {
+            j.info.k_lead = -1;
+            j.info.n_inside = -1;
+            j.info.e21_rel = HUGE_VAL;
+        }
         return true;
     }
     const int ks = j.info.k_lead;
@@ -841,8 +859,6 @@ static bool decide(JobWs& w, bool& needs_best) {
         w.best_e = es;
         w.best_attempt = w.attempt;
     }
-    // accepted on its backward error e(k*) (Alg. 4); the GRURV rank decides
-    // only whether every eigenvalue lies on one side, and is reported
     if (es <= j.opts.split_tol) {
         w.status = conv ? SDC_OK : SDC_NOT_CONVERGED;
         return true;

@@ -68,10 +68,12 @@ inline bool region_ok(const sdc_region_t& r) {
     if (r.kind == SDC_HALFPLANE) return std::isfinite(r.shift) && std::isfinite(r.scale) && r.scale >= 0;
     return false;
 }
-// SDC_FP32_REFINE is for symmetric problems only.
-inline bool prec_ok(const sdc_opts_t& o, bool pencil) {
+// SDC_FP32_REFINE is for symmetric problems split at a half plane only: its
+// refinement solves X A11 - A22 X = E by conjugate gradients, whose operator
+// is positive definite only when a point separates the two eigenvalue groups.
+inline bool prec_ok(const sdc_opts_t& o, bool pencil, int region_kind) {
     if (o.prec == SDC_FP64) return true;
-    return o.prec == SDC_FP32_REFINE && !pencil;
+    return o.prec == SDC_FP32_REFINE && !pencil && region_kind == SDC_HALFPLANE;
 }
 
 // One split problem (symmetric or pencil) as the drivers see it.
@@ -125,6 +127,6 @@ int job_runs_tick(Handle& h, std::vector<JobRun*>& runs, std::vector<char>& done
 // Randomized divide-and-conquer; see sdc_eig_dc.
 int run_eig_dc(Handle& h, int n, const double* A, int lda, const double* B, int ldb, int symmetric, int leaf_max,
                const sdc_opts_t& opts, double* T, int ldt, double* S, int lds, double* QL, int ldql, double* QR,
-               int ldqr, int* nblocks, int* block_start, sdc_dc_info_t* info);
+               int ldqr, int* nblocks, int* block_start, sdc_block_bound_t* bounds, sdc_dc_info_t* info);
 
 }  // namespace sdc

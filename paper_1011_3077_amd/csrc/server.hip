@@ -223,7 +223,7 @@ sdc_status_t sdc_server_submit(sdc_server_t s, const sdc_request_t* q, long long
     const int n = q->n;
     const bool pencil = q->kind == SDC_REQ_PENCIL;
     if ((q->kind != SDC_REQ_SYM && !pencil) || n < 1 || n > sdc::kMaxN || !q->A || q->lda < n || !q->Q ||
-        q->ldq < n || !q->Ahat || q->ldah < n || !sdc::region_ok(q->region) || !sdc::prec_ok(q->opts, pencil))
+        q->ldq < n || !q->Ahat || q->ldah < n || !sdc::region_ok(q->region) || !sdc::prec_ok(q->opts, pencil, q->region.kind))
         return SDC_ERR_INVALID;
     if (pencil && (!q->B || q->ldb < n || !q->QL || q->ldql < n || !q->Bhat || q->ldbh < n)) return SDC_ERR_INVALID;
     Request* r = new (std::nothrow) Request;

@@ -55,3 +55,33 @@ def test_status_strings_without_device():
     for code in (0, 1, 2, 3, -1, -2, -3, -4):
         s = lib.sdc_status_string(code)
         assert s and len(s) > 2
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsdc.so not built")
+def test_binding_structs_match_header_layout(tmp_path):
+    """Every struct the binding marshals has the size and field offsets the
+    C compiler gives the header's declaration (a field added on one side
+    only would shift every later field)."""
+    import paper_1011_3077_amd as P
+    structs = {"sdc_region_t": P.Region, "sdc_opts_t": P.Opts, "sdc_info_t": P.Info,
+               "sdc_dc_info_t": P.DcInfo, "sdc_block_bound_t": P.BlockBound,
+               "sdc_kernel_stats_t": P.KernelStats, "sdc_request_t": P.Request,
+               "sdc_server_stats_t": P.ServerStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sdc.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        c, f, v = ln.split()
+        got[(c, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
