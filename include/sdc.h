@@ -151,6 +151,28 @@ sdc_status_t sdc_split_sym(sdc_handle_t h, int n, const double* A, int lda, sdc_
                            const sdc_opts_t* opts, double* Q, int ldq, double* Ahat, int ldah,
                            sdc_info_t* info);
 
+/* Largest order and device memory of sdc_split_sym_noalloc. */
+#define SDC_NOALLOC_MAX_N 1024
+#define SDC_NOALLOC_SCRATCH_MIB 112
+
+/* sdc_split_sym without any device-memory allocation, for callers that
+ * cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Arguments, layout, ownership, statuses
+ * and results are those of sdc_split_sym (the same kernels in the same
+ * order: the outputs are bitwise equal), with n <= SDC_NOALLOC_MAX_N
+ * (SDC_ERR_INVALID beyond it).  The workspace is a static device array of
+ * SDC_NOALLOC_SCRATCH_MIB MiB per device that the library holds from the
+ * first sdc_create on that device until the process ends, and host-side
+ * staging is static too; the handle's streams and events are made by
+ * sdc_create.  Every call on one device shares that memory: calls that
+ * overlap in time on one device (from several threads or handles) race and
+ * must be serialized by the caller; consecutive calls are safe (each ends
+ * with a synchronization of the handle's stream).  Profiling
+ * (sdc_profile_enable) does not apply to this entry point. */
+sdc_status_t sdc_split_sym_noalloc(sdc_handle_t h, int n, const double* A, int lda, sdc_region_t region,
+                                   const sdc_opts_t* opts, double* Q, int ldq, double* Ahat, int ldah,
+                                   sdc_info_t* info);
+
 /* RNEP: one split step of a non-symmetric A (B = I; the paragraph after
  * Alg. 4).  The left deflating subspace equals the right one, so only the
  * right side runs: IRS of the mapped (A, I), GRURV(2, A_p + B_p, A_p, -1, 1)

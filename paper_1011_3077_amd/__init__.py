@@ -28,7 +28,7 @@ SDC_FP64, SDC_FP32_REFINE = 0, 1
 SDC_UNIT_DISK, SDC_DISK, SDC_HALFPLANE = 0, 1, 2
 
 EXPORTED = ["sdc_opts_default", "sdc_create", "sdc_destroy", "sdc_status_string", "sdc_irs",
-            "sdc_split_sym", "sdc_split_nonsym", "sdc_split_pencil", "sdc_split_sym_batched", "sdc_split_svd",
+            "sdc_split_sym", "sdc_split_sym_noalloc", "sdc_split_nonsym", "sdc_split_pencil", "sdc_split_sym_batched", "sdc_split_svd",
             "sdc_eig_dc",
             "sdc_block_eigvals",
             "sdc_gaussian",
@@ -125,6 +125,9 @@ lib.sdc_split_sym_batched.restype = _I
 lib.sdc_eig_dc.argtypes = [_P, _I, _P, _I, _P, _I, _I, _I, C.POINTER(Opts), _P, _I, _P, _I, _P, _I, _P, _I,
                            C.POINTER(_I), C.POINTER(_I), C.POINTER(BlockBound), C.POINTER(DcInfo)]
 lib.sdc_eig_dc.restype = _I
+lib.sdc_split_sym_noalloc.argtypes = [_P, _I, _P, _I, Region, C.POINTER(Opts), _P, _I, _P, _I, C.POINTER(Info)]
+lib.sdc_split_sym_noalloc.restype = _I
+NOALLOC_MAX_N = 1024
 lib.sdc_split_nonsym.argtypes = [_P, _I, _P, _I, Region, C.POINTER(Opts), _P, _I, _P, _I, C.POINTER(Info)]
 lib.sdc_split_nonsym.restype = _I
 lib.sdc_split_svd.argtypes = [_P, _I, _I, _P, _I, Region, C.POINTER(Opts), _P, _I, _P, _I, _P, _I, C.POINTER(Info)]
@@ -247,6 +250,20 @@ class Handle:
         st = _check(lib.sdc_split_sym(self._h, n, a.data_ptr(), n, reg or region(), C.byref(o or opts()),
                                       q.data_ptr(), n, ah.data_ptr(), n, C.byref(info)))
         return SplitResult(st, info.as_dict(), q.t(), None, ah.t(), None)
+
+    def split_sym_noalloc(self, A_cm, Q_cm, Ahat_cm, reg: Region | None = None, o: Opts | None = None):
+        """sdc_split_sym_noalloc on caller-owned column-major buffers (float64
+        device tensors of shape (n, n) holding the transposes, e.g. made once
+        with torch.empty and reused): nothing is allocated here or in the
+        library.  Returns (status, info)."""
+        n = A_cm.shape[0]
+        for t in (A_cm, Q_cm, Ahat_cm):
+            if not (t.is_cuda and t.is_contiguous() and tuple(t.shape) == (n, n)):
+                raise TypeError("expected contiguous (n, n) device tensors")
+        info = Info()
+        st = _check(lib.sdc_split_sym_noalloc(self._h, n, A_cm.data_ptr(), n, reg or region(), C.byref(o or opts()),
+                                              Q_cm.data_ptr(), n, Ahat_cm.data_ptr(), n, C.byref(info)))
+        return st, info.as_dict()
 
     def split_nonsym(self, A, reg: Region | None = None, o: Opts | None = None) -> SplitResult:
         n = A.shape[0]

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -17,6 +18,10 @@ using sdc::SplitJob;
 struct sdc_handle_s {
     Handle h;
 };
+
+// Preallocated device memory of sdc_split_sym_noalloc (layout and use below).
+constexpr size_t kScratchBytes = (size_t)SDC_NOALLOC_SCRATCH_MIB << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
 
 namespace {
 
@@ -39,6 +44,46 @@ sdc_opts_t resolve(const sdc_opts_t* o) {
     if (o) r = *o;
     else sdc_opts_default(&r);
     return r;
+}
+
+// ---------------------------------------------------------------------------
+// Preallocated memory of the no-allocation entry point (sdc_split_sym_noalloc).
+//
+// `scratch` is one file-scope device array; every GPU the library runs on
+// holds its own copy (at its own address) until the process ends.  In host
+// code its name is only a stand-in, so its device address is looked up once
+// per device, with that device current, when the first handle on the device
+// is created, and kept in scratch_dev[].  The array is carved into the
+// descriptor arena, the per-tick norm and result staging buffers, and the
+// split's workspace.  Host-side staging (the descriptor mirror and the small
+// result buffer) is a static host array per device.  Every call on a device
+// shares both, so calls that overlap on one device race; each call ends with
+// a stream synchronization, so calls in sequence are safe.
+// ---------------------------------------------------------------------------
+constexpr size_t kNaDescBytes = 1 << 20;      // descriptor arena
+constexpr size_t kNaNormElems = 8 << 10;      // convergence norms (doubles)
+constexpr size_t kNaStageElems = 8 << 10;     // gathered results (doubles)
+constexpr size_t kNaHostBytes = 64 << 10;     // host copy of the gathered results
+constexpr int kNaMaxDevices = 16;
+static_assert(kNaDescBytes + (kNaNormElems + kNaStageElems) * sizeof(double) < kScratchBytes, "scratch layout");
+
+char* scratch_dev[kNaMaxDevices] = {};
+std::mutex scratch_mu;
+alignas(256) char na_host_desc[kNaMaxDevices][kNaDescBytes];
+alignas(256) char na_host_res[kNaMaxDevices][kNaHostBytes];
+
+// Device address of this device's scratch (the device must be current).
+int init_scratch(int device) {
+    if (device < 0 || device >= kNaMaxDevices) return SDC_OK;  // the entry point refuses such devices
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (scratch_dev[device]) return SDC_OK;
+    char* p = nullptr;
+    if (hipGetSymbolAddress(reinterpret_cast<void**>(&p), HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return SDC_ERR_DEVICE;
+    }
+    scratch_dev[device] = p;
+    return SDC_OK;
 }
 
 
@@ -82,7 +127,15 @@ sdc_status_t sdc_create(sdc_handle_t* handle, int device, size_t budget, void* s
     p->h.device = device;
     p->h.stream = static_cast<hipStream_t>(stream);
     p->h.budget = budget;
-    if (use_device(p->h) != SDC_OK) {
+    // streams and events are made here, so the entry points that must not
+    // allocate find them ready
+    if (use_device(p->h) != SDC_OK || init_scratch(device) != SDC_OK || sdc::ensure_streams(p->h) != SDC_OK ||
+        hipEventCreateWithFlags(&p->h.ev_sync, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->h.ev_desc, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        if (p->h.ev_sync) (void)hipEventDestroy(p->h.ev_sync);
+        if (p->h.ev_desc) (void)hipEventDestroy(p->h.ev_desc);
+        sdc::release_streams(p->h);
         delete p;
         return SDC_ERR_DEVICE;
     }
@@ -143,6 +196,55 @@ sdc_status_t sdc_split_sym(sdc_handle_t hd, int n, const double* A, int lda, sdc
     sdc::ProfScope ps(h);
     const int r = sdc::run_split_jobs(h, jobs);
     resolve_profile(h);
+    if (r < 0) return (sdc_status_t)r;
+    *info = j.info;
+    return (sdc_status_t)j.status;
+}
+
+sdc_status_t sdc_split_sym_noalloc(sdc_handle_t hd, int n, const double* A, int lda, sdc_region_t region,
+                                   const sdc_opts_t* opts, double* Q, int ldq, double* Ahat, int ldah,
+                                   sdc_info_t* info) {
+    if (!hd || n < 0 || n > SDC_NOALLOC_MAX_N || (n > 0 && (!A || !Q || !Ahat)) || lda < n || ldq < n || ldah < n ||
+        !region_ok(region))
+        return SDC_ERR_INVALID;
+    Handle& h = hd->h;
+    if (h.device < 0 || h.device >= kNaMaxDevices || !scratch_dev[h.device]) return SDC_ERR_DEVICE;
+    sdc_info_t dummy;
+    if (!info) info = &dummy;
+    *info = sdc_info_t{};
+    if (n == 0) return SDC_OK;
+    if (use_device(h) != SDC_OK) return SDC_ERR_DEVICE;
+    std::vector<SplitJob> jobs(1);
+    SplitJob& j = jobs[0];
+    j.n = n; j.pencil = false; j.A = A; j.lda = lda; j.region = region; j.opts = resolve(opts);
+    if (!prec_ok(j.opts, false, region.kind)) return SDC_ERR_INVALID;
+    j.Q = Q; j.ldq = ldq; j.Ahat = Ahat; j.ldah = ldah;
+    // a handle over the preallocated buffers: the caller's stream, streams
+    // and events; nothing is allocated (the helpers refuse instead)
+    Handle nh;
+    nh.device = h.device;
+    nh.stream = h.stream;
+    nh.budget = 0;
+    nh.qs = h.qs;
+    nh.ev_sync = h.ev_sync;
+    nh.ev_desc = h.ev_desc;
+    nh.no_alloc = true;
+    char* base = scratch_dev[h.device];
+    nh.desc_d = base;
+    nh.desc_h = na_host_desc[h.device];
+    nh.desc_size = kNaDescBytes;
+    nh.dnorm = reinterpret_cast<double*>(base + kNaDescBytes);
+    nh.dnorm_cap = kNaNormElems;
+    nh.dstage = nh.dnorm + kNaNormElems;
+    nh.dstage_cap = kNaStageElems;
+    nh.host = na_host_res[h.device];
+    nh.host_size = kNaHostBytes;
+    const size_t ws_off = kNaDescBytes + (kNaNormElems + kNaStageElems) * sizeof(double);
+    nh.ws = base + ws_off;
+    nh.ws_size = kScratchBytes - ws_off;
+    sdc::ProfScope ps(nh);  // profiling off: its events would be allocations
+    const int r = sdc::run_split_jobs(nh, jobs);
+    nh.qs = sdc::QrStreams{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     if (r < 0) return (sdc_status_t)r;
     *info = j.info;
     return (sdc_status_t)j.status;

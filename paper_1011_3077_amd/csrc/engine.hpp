@@ -49,6 +49,9 @@ struct Handle {
     QrStreams qs{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     // opt-in kernel timing
     Profiler prof;
+    // every buffer above was handed in from preallocated memory: the
+    // ensure_* helpers report SDC_ERR_NOMEM instead of allocating
+    bool no_alloc = false;
 };
 
 // Installs the handle's profiler (if enabled) for the lifetime of a call.

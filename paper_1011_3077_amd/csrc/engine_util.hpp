@@ -50,6 +50,7 @@ struct Carver {
 inline int ensure_ws(Handle& h, size_t bytes) {
     if (h.budget && bytes > h.budget) return SDC_ERR_NOMEM;
     if (bytes <= h.ws_size) return SDC_OK;
+    if (h.no_alloc) return SDC_ERR_NOMEM;
     if (h.ws) {
         HIPCHK(hipStreamSynchronize(h.stream));
         HIPCHK(hipFree(h.ws));
@@ -69,6 +70,7 @@ inline int ensure_ws(Handle& h, size_t bytes) {
 
 inline int ensure_desc(Handle& h, size_t bytes) {
     if (bytes <= h.desc_size) return SDC_OK;
+    if (h.no_alloc) return SDC_ERR_NOMEM;
     if (h.desc_d) {
         HIPCHK(hipStreamSynchronize(h.stream));
         HIPCHK(hipFree(h.desc_d));
@@ -85,6 +87,7 @@ inline int ensure_desc(Handle& h, size_t bytes) {
 
 inline int ensure_streams(Handle& h) {
     if (h.qs.crit) return SDC_OK;
+    if (h.no_alloc) return SDC_ERR_DEVICE;
     if (hipStreamCreateWithFlags(&h.qs.crit, hipStreamNonBlocking) != hipSuccess) return SDC_ERR_DEVICE;
     if (hipStreamCreateWithFlags(&h.qs.rest, hipStreamNonBlocking) != hipSuccess) return SDC_ERR_DEVICE;
     hipEvent_t* ev[4] = {&h.qs.evP, &h.qs.evR, &h.qs.evE, &h.qs.evD};
@@ -105,6 +108,7 @@ inline void release_streams(Handle& h) {
 
 inline int ensure_dnorm(Handle& h, size_t elems) {
     if (elems <= h.dnorm_cap) return SDC_OK;
+    if (h.no_alloc) return SDC_ERR_NOMEM;
     if (h.dnorm) {
         HIPCHK(hipStreamSynchronize(h.stream));
         HIPCHK(hipFree(h.dnorm));
@@ -122,6 +126,7 @@ inline int ensure_dnorm(Handle& h, size_t elems) {
 // as soon as the data is there, and a blocking synchronization can put the
 // thread to sleep for tens of microseconds.
 inline int sync_spin(Handle& h) {
+    if (!h.ev_sync && h.no_alloc) return SDC_ERR_DEVICE;
     if (!h.ev_sync) HIPCHK(hipEventCreateWithFlags(&h.ev_sync, hipEventDisableTiming));
     HIPCHK(hipEventRecord(h.ev_sync, h.stream));
     hipError_t e;
@@ -134,6 +139,7 @@ inline int sync_spin(Handle& h) {
 
 inline int ensure_dstage(Handle& h, size_t elems) {
     if (elems <= h.dstage_cap) return SDC_OK;
+    if (h.no_alloc) return SDC_ERR_NOMEM;
     if (h.dstage) {
         HIPCHK(hipStreamSynchronize(h.stream));
         HIPCHK(hipFree(h.dstage));
@@ -148,6 +154,7 @@ inline int ensure_dstage(Handle& h, size_t elems) {
 
 inline int ensure_host(Handle& h, size_t bytes) {
     if (bytes <= h.host_size) return SDC_OK;
+    if (h.no_alloc) return SDC_ERR_NOMEM;
     if (h.host) {
         HIPCHK(hipStreamSynchronize(h.stream));
         HIPCHK(hipHostFree(h.host));
@@ -168,7 +175,7 @@ template <class T> inline const T* upload(Handle& h, const std::vector<T>& v) {
     const size_t bytes = v.size() * sizeof(T);
     size_t off = (h.desc_off + 255) & ~size_t(255);
     if (off + bytes > h.desc_size) return nullptr;
-    if (!h.ev_desc && hipEventCreateWithFlags(&h.ev_desc, hipEventDisableTiming) != hipSuccess) {
+    if (!h.ev_desc && (h.no_alloc || hipEventCreateWithFlags(&h.ev_desc, hipEventDisableTiming) != hipSuccess)) {
         h.ev_desc = nullptr;
         return nullptr;
     }
