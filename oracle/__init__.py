@@ -10,6 +10,7 @@ Decomposition", arXiv 1011.3077):
 * Alg. 4 (RGNEP) / Alg. 6 (RSEP) one split step, with the line-to-circle
   Moebius map of Sec. 3.3 and the split-point search of Alg. 4 line 5 -> split.py
 * the randomized divide-and-conquer strategy of Sec. 3.3-3.5       -> eig_dc.py
+* eigenvectors of an upper-triangular matrix or pencil (TREVC, Sec. 5) -> trevc.py
 * the Philox4x32-10 counter-based generator (Salmon et al., SC'11) with a
   Box-Muller transform, for the Gaussian matrix RURV draws          -> philox.py
 
@@ -29,3 +30,4 @@ from .split import (premap, split_search, split_sym, split_pencil, split_svd, sp
                     rank_from_rho, norm1, OK, NOT_CONVERGED, NO_SPLIT, RANK_AMBIGUOUS)
 from .philox import philox4x32_10, gaussian_matrix  # noqa: F401
 from .eig_dc import eig_dc, block_eigvals  # noqa: F401
+from .trevc import trevc  # noqa: F401
