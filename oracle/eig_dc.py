@@ -30,6 +30,10 @@ Strategy, as the paper describes it:
   singular pencil does (Sec. 3.5): the block is then flagged near-singular.
 The coupling blocks E21 (and F21) are set to zero after each accepted split,
 and the transformations are applied to the rest of the pair and accumulated.
+An accepted step divides its block at its split point k and also at every
+other k' whose coupling blocks are as small (e(k') <= split_tol): the paper
+notes that more than one small pair of blocks may divide the problem into
+more than two.  The pieces on either side of k inherit that side's bound.
 
 Each leaf block carries a bound (re_lo, re_hi, radius, inverted): the
 eigenvalues mu of the block pair satisfy re_lo <= Re mu <= re_hi and
@@ -42,8 +46,9 @@ import math
 
 import numpy as np
 
-from .split import split_sym, split_pencil, OK, NO_SPLIT
+from .split import split_sym, split_pencil, split_search, norm1, OK, NO_SPLIT
 
+SPLIT_TOL = 1e-10      # the split step's acceptance threshold, also for extra split points
 MAX_TRIES = 8          # consecutive failed curves before a block is given up
 MAX_CIRCLE_FAILS = 3   # consecutive failed circles before a block is given up (near-singular)
 RADIUS_MIN, RADIUS_MAX = 2.0 ** -1000, 2.0 ** 1000   # exponent range of the radius search
@@ -96,7 +101,7 @@ def _bound(blk, symmetric):
 def eig_dc(a: np.ndarray, b: np.ndarray | None = None, symmetric: bool = False, leaf_max: int = 64,
            seed: int = 0):
     """Returns dict(T, S, QL, QR, blocks=[(s, e), ...], bounds=[(re_lo, re_hi,
-    radius, inverted), ...] per block, splits, unsplit, near_singular,
+    radius, inverted), ...] per block, splits, unsplit, near_singular, extra_splits,
     log=[(s, e, mode, curve value, status, k), ...] per split attempt)."""
     a = np.array(a, dtype=np.float64)
     n = a.shape[0]
@@ -113,7 +118,7 @@ def eig_dc(a: np.ndarray, b: np.ndarray | None = None, symmetric: bool = False, 
         work = [dict(base, mode="line", lo=lo, hi=hi, radius=max(abs(lo), abs(hi)))]
     else:
         work = [dict(base, mode="circle", lo=-math.inf, hi=math.inf, radius=1.0)]
-    leaves, splits, unsplit, near_singular, log = [], 0, 0, 0, []
+    leaves, splits, unsplit, near_singular, extra, log = [], 0, 0, 0, 0, []
     if n <= leaf_max:
         leaves, work = work, []
     while work:
@@ -166,25 +171,34 @@ def eig_dc(a: np.ndarray, b: np.ndarray | None = None, symmetric: bool = False, 
                 else:
                     nxt.append(nb)
                 continue
-            # accepted: write the split pair, drop the coupling blocks, update the rest
+            # accepted: every split point with a small coupling block
+            if symmetric:
+                _, _, prof = split_search(res.A_hat, norm1(tb))
+            else:
+                _, _, prof = split_search(res.A_hat, norm1(pa), res.B_hat, norm1(pb))
+            cuts = [kk for kk in range(1, m) if kk == k or prof[kk - 1] <= SPLIT_TOL]
+            extra += len(cuts) - 1
+            # write the split pair, drop the coupling blocks, update the rest
             if symmetric:
                 t[s0:e0, s0:e0] = res.A_hat
-                t[s0 + k:e0, s0:s0 + k] = 0.0
-                t[s0:s0 + k, s0 + k:e0] = 0.0
+                for kk in cuts:
+                    t[s0 + kk:e0, s0:s0 + kk] = 0.0
+                    t[s0:s0 + kk, s0 + kk:e0] = 0.0
             else:
                 ah, bh = (res.B_hat, res.A_hat) if blk["swapped"] else (res.A_hat, res.B_hat)
                 t[s0:e0, s0:e0] = ah
                 s[s0:e0, s0:e0] = bh
-                t[s0 + k:e0, s0:s0 + k] = 0.0
-                s[s0 + k:e0, s0:s0 + k] = 0.0
+                for kk in cuts:
+                    t[s0 + kk:e0, s0:s0 + kk] = 0.0
+                    s[s0 + kk:e0, s0:s0 + kk] = 0.0
                 t[s0:e0, e0:] = qlb.T @ t[s0:e0, e0:]
                 s[s0:e0, e0:] = qlb.T @ s[s0:e0, e0:]
                 t[:s0, s0:e0] = t[:s0, s0:e0] @ qrb
                 s[:s0, s0:e0] = s[:s0, s0:e0] @ qrb
                 ql[:, s0:e0] = ql[:, s0:e0] @ qlb
             qr[:, s0:e0] = qr[:, s0:e0] @ qrb
-            c1 = dict(blk, e=s0 + k, tries=0)
-            c2 = dict(blk, s=s0 + k, tries=0)
+            c1 = dict(blk, tries=0)
+            c2 = dict(blk, tries=0)
             if blk["mode"] == "circle":
                 r0 = blk["radius"]
                 c1 = _lines(c1, -1.0 / r0, 1.0 / r0, True)   # outside r0: reciprocals inside 1/r0
@@ -192,13 +206,14 @@ def eig_dc(a: np.ndarray, b: np.ndarray | None = None, symmetric: bool = False, 
             else:
                 c1["lo"] = region["shift"]
                 c2["hi"] = region["shift"]
-            for c in (c1, c2):
+            for lo, hi in zip([0] + cuts, cuts + [m]):
+                c = dict(c1 if hi <= k else c2, s=s0 + lo, e=s0 + hi)
                 (leaves if c["e"] - c["s"] <= leaf_max else nxt).append(c)
         work = nxt
     leaves.sort(key=lambda x: x["s"])
     return dict(T=t, S=s, QL=None if symmetric else ql, QR=qr, blocks=[(x["s"], x["e"]) for x in leaves],
                 bounds=[_bound(x, symmetric) for x in leaves], unsplit_blocks=[bool(x.get("unsplit")) for x in leaves],
-                splits=splits, unsplit=unsplit, near_singular=near_singular, log=log)
+                splits=splits, unsplit=unsplit, near_singular=near_singular, extra_splits=extra, log=log)
 
 
 def block_eigvals(t: np.ndarray, s: np.ndarray | None, starts, symmetric: bool):

@@ -193,3 +193,42 @@ def test_jordan_block_is_returned_unsplit_with_a_bound():
     (a0, a1), (lo, hi, rad, inv) = blk[0]
     assert a1 - a0 >= 16 and inv == 0 and lo < 0.1 < hi
     _check_bounds(r, tol=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# Multi-way splits (the remark after Alg. 4): a step that leaves several small
+# coupling blocks divides its block at all of them
+# ---------------------------------------------------------------------------
+
+def repeated_eig_problem(n, seed, mult=5, value=0.7):
+    """Symmetric A = Q diag(d) Q^T with a `mult`-fold eigenvalue `value`
+    (no curve can separate equal eigenvalues) among n - mult others spread
+    over [-1, 1] away from it."""
+    rng = np.random.default_rng(seed)
+    others = rng.uniform(-1.0, 0.5, n - mult)
+    d = np.concatenate([np.full(mult, value), others])
+    q = S.haar_orthogonal(n, rng)
+    a = (q * d[None, :]) @ q.T
+    return 0.5 * (a + a.T), d
+
+
+def test_multiway_split_separates_a_repeated_eigenvalue_symmetric():
+    """Recursion to blocks of order 1: the five equal eigenvalues cannot be
+    split by any line, but once a split isolates their invariant subspace
+    its block is 0.7 I up to rounding, every coupling block inside it is
+    negligible, and the step divides it into blocks of order 1."""
+    a, d = repeated_eig_problem(30, 11)
+    r = eig_dc(a, symmetric=True, leaf_max=1, seed=2)
+    assert r["unsplit"] == 0 and r["extra_splits"] >= 4
+    assert all(e - s0 == 1 for s0, e in r["blocks"])
+    ev = np.sort(np.diag(r["T"]))
+    assert np.abs(ev - np.sort(d)).max() <= 1e-12
+    assert np.abs(r["QR"].T @ a @ r["QR"] - r["T"]).max() <= 1e-10
+
+
+def test_no_extra_splits_for_distinct_eigenvalues():
+    """Random bases inside each side leave no other small coupling block:
+    with distinct eigenvalues every step divides in two."""
+    a, d, _ = S.sym_problem(40, S.family_seed(0, 41))
+    r = eig_dc(a, symmetric=True, leaf_max=4, seed=1)
+    assert r["extra_splits"] == 0
