@@ -1,27 +1,28 @@
 #!/usr/bin/env python3
-"""Benchmark of the inverse-free spectral divide-and-conquer on one MI355X.
+"""Benchmark of the inverse-free spectral split on one MI355X.
 
-Workload (default, `pencil2048`): the order-2048 real pencil A = U T V^T,
-B = U S V^T (T, S upper triangular, |lambda| log-uniform in [0.1, 10],
-U, V Haar, seed 10113077 + 1000), split at the unit circle and then
-recursively to diagonal blocks of order <= 64, in FP64.  One step is one
-whole divide-and-conquer run (sdc_eig_dc) on inputs already resident in HBM.
+Workload (default): one symmetric split of the clustered order-8192 problem
+A = Q diag(d) Q^T (Q Haar; half of d in [-1, -0.01], half in [0.01, 1], 5%
+per side within 1e-3 of +-0.01; seed 10113077 + 3000) at the half plane
+Re z < 0, inputs resident in HBM.  One step is one FP64 split
+(sdc_split_sym); the FP32+refine split of the same problem is timed beside
+it (FP32 repeated squaring, FP64 convergence test, rank, block form and
+refinement).  The other configurations (order-128 symmetric split, the
+order-2048 pencil divide-and-conquer, 512 batched FP32+refine problems) are
+measured briefly and reported in `other_configs`.
 
-metric: split GFLOP/s = nominal split flops / wall time, with the nominal
-flops of every split step counted by the paper's cost model with LAPACK
-leading terms: (40/3 (p_R + p_L) + 32) m^3 for a pencil step of order m with
-p_R, p_L repeated-squaring iterations (refinement and retries not credited).
+metric: split GFLOP/s = nominal split flops / wall time, with the paper's
+cost model and LAPACK leading terms: (40/3 p + 16) n^3 for a symmetric split
+with p repeated-squaring iterations, (40/3 (p_R + p_L) + 32) m^3 per pencil
+step (refinement and retries not credited).
 
-roofline: the kernel with the largest total time in the timed region, timed
-per launch with HIP events on its stream (sdc_profile_*), against its bound:
-the tree-level trailing update is a dense contraction with 8 flop/byte in
-FP64 (4 R nb ntr flops on 2 R ntr words of 8 bytes, nb = 32), below the
-chip's 9.8 flop/byte balance, so its bound is HBM bandwidth; the panel
-factorization is vector-ALU work.
+roofline: the tree-level trailing update of the QR (the kernel with the
+largest time), timed per launch with HIP events on its stream
+(sdc_profile_*), against the roof its algorithmic intensity puts it under.
 
-cpu_baseline: the FP64 oracle (NumPy/LAPACK) on the host cores, running the
-top split of the same pencil family at order 1024 (a bounded sample; about
-1/8 of the order-2048 split's flops), in the same GFLOP/s unit.
+cpu_baseline: the FP64 oracle (NumPy/LAPACK) on the host cores, splitting a
+clustered symmetric problem of the same family at order 1536 (a bounded
+sample), in the same GFLOP/s unit.
 """
 from __future__ import annotations
 
@@ -58,26 +59,6 @@ def kernel_sources_sha():
         with open(os.path.join(ROOT, "paper_1011_3077_amd", "csrc", f), "rb") as fh:
             hsh.update(fh.read())
     return hsh.hexdigest()
-
-
-def cpu_baseline(n: int = 1024):
-    import numpy as np
-    import sdc_synth as S
-    import oracle as O
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([x.get("num_threads", 1) for x in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count() or 1
-    p = S.pencil_problem(n, S.family_seed(1, 500))
-    t0 = time.perf_counter()
-    r = O.split_pencil(p["A"], p["B"], {"kind": "unit_disk"}, seed=1)
-    dt = time.perf_counter() - t0
-    flops = (40.0 / 3.0 * (r.p_right + r.p_left) + 32.0) * n ** 3
-    return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"oracle split_pencil (unit circle) of one order-{n} pencil of the same family, "
-                      f"p_R={r.p_right}, p_L={r.p_left}, {dt:.1f} s, nominal {flops:.3e} flops",
-            "seconds": dt}
 
 
 def serve_main(args):
@@ -244,15 +225,184 @@ def suite_main(args):
     h.close()
 
 
+def _roofline(P, stats, k, names, peak_tflops, traffic=None):
+    """Roofline object of kernel k from its event-timed launches.  The bound
+    is the lower of the two roofs at the kernel's algorithmic intensity
+    (flops per byte of its minimum traffic): HBM below the machine balance,
+    MFMA above it; the fraction of the MFMA peak is given either way.  The
+    panel factorization is a sequential column loop in few workgroups and is
+    set against the vector peak of its precision."""
+    sd = stats[k]
+    if sd["ms"] <= 0:
+        return None
+    secs = sd["ms"] / 1e3
+    fl = sd["flops"] / secs / 1e12
+    if k == P.KERNEL_PANEL:
+        r = {"bound": "alu", "achieved": fl, "peak": peak_tflops, "unit": "TFLOP/s", "frac": fl / peak_tflops,
+             "traffic": None}
+    else:
+        inten = sd["flops"] / max(sd["bytes"], 1.0)
+        if inten < peak_tflops * 1e12 / (PEAK["hbm_gbs"] * 1e9):
+            ach = sd["bytes"] / secs / 1e9
+            r = {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+                 "frac": ach / PEAK["hbm_gbs"], "traffic": None}
+        else:
+            r = {"bound": "mfma", "achieved": fl, "peak": peak_tflops, "unit": "TFLOP/s", "frac": fl / peak_tflops,
+                 "traffic": None}
+        r["intensity_flop_per_byte"] = inten
+        r["mfma_achieved_tflops"] = fl
+        r["mfma_frac"] = fl / peak_tflops
+    if traffic is not None:
+        r["traffic"] = traffic["bytes_per_launch"]
+        r["traffic_note"] = traffic["note"]
+    r["kernel"] = names[k]
+    r["launches"] = sd["launches"]
+    r["avg_launch_us"] = sd["ms"] * 1e3 / max(sd["launches"], 1)
+    r["algorithmic_flops_per_launch"] = sd["flops"] / max(sd["launches"], 1)
+    r["algorithmic_bytes_per_launch"] = sd["bytes"] / max(sd["launches"], 1)
+    return r
+
+
+def kernel_names(P, prec):
+    t = "f32" if prec == "f32" else "f64"
+    return {P.KERNEL_UPDATE: f"k_update (tree-level trailing update, MFMA {t})",
+            P.KERNEL_PANEL: "k_panel (TSQR panel Householder)",
+            P.KERNEL_GEMM: "k_gemm (MFMA)",
+            P.KERNEL_LA: f"k_la (look-ahead update of the next panel, MFMA {t})"}
+
+
+def sym_flops(n, p):
+    """Nominal flops of one symmetric split with p repeated-squaring iterations."""
+    return (40.0 / 3.0 * p + 16.0) * float(n) ** 3
+
+
+def cpu_baseline_sym(n: int = 1536):
+    """The FP64 oracle on the host's cores: split_sym of one clustered
+    symmetric problem of the headline family at order n (a bounded sample)."""
+    import sdc_synth as S
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([x.get("num_threads", 1) for x in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    a, d, _ = S.clustered_sym_problem(n, S.family_seed(3, 1))
+    t0 = time.perf_counter()
+    r = O.split_sym(a, {"kind": "halfplane", "shift": 0.0, "scale": 1.0}, seed=1)
+    dt = time.perf_counter() - t0
+    flops = sym_flops(n, r.p_right)
+    return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"oracle split_sym (half plane Re z < 0) of one clustered symmetric order-{n} problem of "
+                      f"the same family, p={r.p_right}, {dt:.1f} s, nominal {flops:.3e} flops",
+            "seconds": dt}
+
+
+def other_configs(P, h):
+    """The other configurations, measured briefly beside the headline line:
+    the order-128 symmetric split (latency, FP64; median of 10 after 3
+    warm-ups, checked against the oracle), the order-2048 pencil
+    divide-and-conquer to blocks <= 64 (FP64; mean of 3 after 1 warm-up), and
+    512 symmetric problems with n log-uniform in [32, 256] in one batched
+    FP32+refine call (median of 3 after 1 warm-up).  Inputs resident in HBM;
+    host clock around each call after a device synchronization."""
+    import statistics
+    import numpy as np
+    import scipy.linalg as sla
+    import torch
+    import sdc_synth as S
+    import oracle as O
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+    half = P.region("halfplane", shift=0.0, scale=1.0)
+    out = {}
+
+    def timed(fn, reps, warm):
+        res, ts = None, []
+        for i in range(warm + reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = fn()
+            torch.cuda.synchronize()
+            if i >= warm:
+                ts.append((time.perf_counter() - t0) * 1e3)
+        return res, ts
+
+    # order 128 symmetric, FP64 (latency)
+    a, d, _ = S.sym_problem(128, S.family_seed(0))
+    A = dev(a)
+    r, ts = timed(lambda: h.split_sym(A, half, P.opts(seed=1)), 10, 3)
+    k = r.info["k_lead"]
+    ref = O.split_sym(a, {"kind": "halfplane", "shift": 0.0, "scale": 1.0}, seed=1)
+    ah = r.Ahat.cpu().numpy()
+    ev = np.sort(np.concatenate([np.linalg.eigvalsh(ah[:k, :k]), np.linalg.eigvalsh(ah[k:, k:])]))
+    ev_ref = np.sort(np.concatenate([np.linalg.eigvalsh(ref.A_hat[:k, :k]), np.linalg.eigvalsh(ref.A_hat[k:, k:])]))
+    qs, qo = r.Q.cpu().numpy()[:, :k], ref.Q[:, :k]
+    ms = statistics.median(ts)
+    fl = sym_flops(128, r.info["iters_right"])
+    out["sym128_fp64"] = {
+        "workload": "symmetric split of one order-128 problem at Re z < 0 (FP64)", "ms": ms,
+        "gflops": fl / ms / 1e6, "pct_fp64_peak": fl / ms / 1e6 / (PEAK["fp64_tflops"] * 1e3),
+        "iters": r.info["iters_right"], "k": k, "exact_rank": r.status == 0 and k == int((d > 0).sum()) == ref.k,
+        "e21_rel": r.info["e21_rel"],
+        "eig_abs_err_vs_oracle": float(np.abs(ev - ev_ref).max()),
+        "subspace_sin_vs_oracle": float(np.linalg.norm(qo - qs @ (qs.T @ qo), 2)),
+        "runs": len(ts)}
+    log(f"[bench] order 128: {ms:.2f} ms")
+
+    # order-2048 pencil divide-and-conquer to blocks <= 64, FP64
+    pb = S.pencil_problem(2048, S.family_seed(1))
+    A, B = dev(pb["A"]), dev(pb["B"])
+    r, ts = timed(lambda: h.eig_dc(A, B, leaf_max=64, o=P.opts(seed=1)), 3, 1)
+    st, t, s_, ql, qr, starts, info = r
+    t, s_ = t.cpu().numpy(), s_.cpu().numpy()
+    got = np.sort_complex(np.concatenate([sla.eigvals(t[a0:a1, a0:a1], s_[a0:a1, a0:a1])
+                                          for a0, a1 in zip(starts[:-1], starts[1:])]))
+    want = np.sort_complex(pb["lam"].astype(complex))
+    ms = statistics.mean(ts)
+    out["pencil2048_dc_fp64"] = {
+        "workload": "divide-and-conquer of the order-2048 real pencil (unit circle, then blocks <= 64), FP64",
+        "ms": ms, "gflops": info["nominal_flops"] / ms / 1e6,
+        "pct_fp64_peak": info["nominal_flops"] / ms / 1e6 / (PEAK["fp64_tflops"] * 1e3),
+        "nominal_flops": info["nominal_flops"], "splits": info["splits"], "accepted": info["accepted"],
+        "blocks": info["nblocks"], "unsplit": info["unsplit"],
+        "nominal_flops_note": "every split attempt counted, including those that divided nothing",
+        "eig_rel_err_vs_construction": float(np.max(np.abs(got - want) / np.abs(want))), "runs": len(ts)}
+    log(f"[bench] order-2048 pencil recursion: {ms:.1f} ms")
+    del A, B
+
+    # 512 batched symmetric problems, FP32 + refine
+    sizes = S.batch_sizes(512, S.family_seed(2))
+    probs = [S.sym_problem(n, S.family_seed(2, i)) for i, n in enumerate(sizes)]
+    As = [dev(x) for x, _, _ in probs]
+    o = P.opts(prec=P.SDC_FP32_REFINE, seed=3)
+    res, ts = timed(lambda: h.split_sym_batched(As, [half] * len(sizes), o), 3, 1)
+    ms = statistics.median(ts)
+    fl = sum(sym_flops(n, r.info["iters_right"]) for n, r in zip(sizes, res))
+    worst = 0.0
+    for r, (_, dd, _) in zip(res, probs):
+        k = r.info["k_lead"]
+        ah = r.Ahat.cpu().numpy()
+        ev = np.sort(np.concatenate([np.linalg.eigvalsh(ah[:k, :k]), np.linalg.eigvalsh(ah[k:, k:])]))
+        worst = max(worst, float(np.abs(ev - np.sort(dd)).max()))
+    out["batched512_fp32_refine"] = {
+        "workload": "512 symmetric problems, n log-uniform in [32, 256], one batched FP32+refine call",
+        "ms": ms, "gflops": fl / ms / 1e6, "pct_fp32_peak": fl / ms / 1e6 / (PEAK["fp32_tflops"] * 1e3),
+        "exact_rank": all(r.status == 0 and r.info["k_lead"] == int((dd > 0).sum()) for r, (_, dd, _) in zip(res, probs)),
+        "fp64_fallbacks": sum(r.info.get("fp64_fallback", 0) for r in res),
+        "eig_abs_err_vs_construction": worst, "runs": len(ts)}
+    log(f"[bench] 512 batched: {ms:.1f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=2048)
-    ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--fp32-steps", type=int, default=3, help="timed FP32+refine splits (at most --steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-launch events")
+    ap.add_argument("--no-extras", action="store_true", help="skip the other configurations")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (reference kernel for HBM counters)")
     ap.add_argument("--serve", action="store_true", help="serving benchmark instead (see serve_main)")
@@ -269,7 +419,6 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import scipy.linalg as sla
     import torch
     import sdc_synth as S
     import paper_1011_3077_amd as P
@@ -284,112 +433,91 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         del x, y
-    n, leaf = args.n, args.leaf
-    log(f"[bench] generating order-{n} pencil")
-    pb = S.pencil_problem(n, S.family_seed(1))
-    A = torch.from_numpy(pb["A"]).to("cuda:0")
-    B = torch.from_numpy(pb["B"]).to("cuda:0")
+    n = args.n
+    log(f"[bench] generating clustered symmetric order-{n} problem")
+    a, d, q = S.clustered_sym_problem(n, S.family_seed(3))
+    del q
+    kexp = int((d > 0).sum())
+    A = torch.from_numpy(a).to("cuda:0")
+    del a
+    half = P.region("halfplane", shift=0.0, scale=1.0)
     h = P.Handle(0)
-    o = P.opts(seed=1)
 
-    def step():
-        return h.eig_dc(A, B, leaf_max=leaf, o=o)
+    def step(prec):
+        return h.split_sym(A, half, P.opts(prec=prec, seed=1))
 
     for i in range(args.warmup):
-        r = step()
-        log(f"[bench] warmup {i}: {r[-1]['ms']:.1f} ms, splits {r[-1]['splits']}")
+        r = step(P.SDC_FP64)
+        log(f"[bench] warmup {i}: {r.info['ms']:.1f} ms, p {r.info['iters_right']}")
     torch.cuda.synchronize()
-    # throughput: the timed steps without per-launch events
+    # the headline: K FP64 splits, without per-launch events
     flops = 0.0
     t0 = time.perf_counter()
     for i in range(args.steps):
-        r = step()
-        flops += r[-1]["nominal_flops"]
+        r = step(P.SDC_FP64)
+        flops += sym_flops(n, r.info["iters_right"])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    log(f"[bench] timed {args.steps} steps: {dt:.3f} s")
-    # per-kernel times: the same steps again with HIP events around every
-    # launch of the hot kernels (on the launch's stream); the events add
-    # host calls and GPU packets to every launch (about a fifth of the step
-    # time), so they stay out of the throughput pass above
-    stats = {}
-    dt_prof = None
+    r64 = r
+    log(f"[bench] timed {args.steps} FP64 splits: {dt:.3f} s")
+    # FP32 repeated squaring + FP64 refinement of the same problem
+    k32 = max(1, min(args.fp32_steps, args.steps))
+    step(P.SDC_FP32_REFINE)
+    torch.cuda.synchronize()
+    flops32 = 0.0
+    t1 = time.perf_counter()
+    for i in range(k32):
+        r = step(P.SDC_FP32_REFINE)
+        flops32 += sym_flops(n, r.info["iters_right"])
+    torch.cuda.synchronize()
+    dt32 = time.perf_counter() - t1
+    r32 = r
+    log(f"[bench] timed {k32} FP32+refine splits: {dt32:.3f} s")
+
+    def accuracy(res):
+        k = res.info["k_lead"]
+        e21 = res.Ahat[k:, :k].abs().sum(dim=0).max().item() / A.abs().sum(dim=0).max().item()
+        ah = res.Ahat.cpu().numpy()
+        ev = np.sort(np.concatenate([np.linalg.eigvalsh(ah[:k, :k]), np.linalg.eigvalsh(ah[k:, k:])]))
+        return {"exact_rank": res.status == 0 and k == kexp, "k": k, "iters": res.info["iters_right"],
+                "e21_rel": e21, "eig_rel_err_vs_construction": float(np.abs(ev - np.sort(d)).max() / np.abs(d).max()),
+                "refine_rounds": res.info["refine_rounds"], "fp64_fallback": res.info["fp64_fallback"]}
+
+    acc64, acc32 = accuracy(r64), accuracy(r32)
+    # per-kernel times: one more split of each precision with HIP events
+    # around every launch of the hot kernels (on the launch's stream)
+    stats64 = stats32 = None
     if not args.no_profile:
         h.profile_enable(True)
-        t1 = time.perf_counter()
-        for i in range(args.steps):
-            step()
+        step(P.SDC_FP64)
         torch.cuda.synchronize()
-        dt_prof = time.perf_counter() - t1
-        log(f"[bench] profiled {args.steps} steps: {dt_prof:.3f} s")
-        stats = {k: h.profile_read(k) for k in (P.KERNEL_UPDATE, P.KERNEL_PANEL, P.KERNEL_GEMM, P.KERNEL_LA)}
+        stats64 = {k: h.profile_read(k) for k in (P.KERNEL_UPDATE, P.KERNEL_PANEL, P.KERNEL_GEMM, P.KERNEL_LA)}
+        h.profile_enable(True)
+        step(P.SDC_FP32_REFINE)
+        torch.cuda.synchronize()
+        stats32 = {k: h.profile_read(k) for k in (P.KERNEL_UPDATE, P.KERNEL_PANEL, P.KERNEL_GEMM, P.KERNEL_LA)}
         h.profile_enable(False)
-
-    # accuracy of the last step against the construction (outside the timed region)
-    st, t, s, ql, qr, starts, info = r
-    t, s = t.cpu().numpy(), s.cpu().numpy()
-    ev = []
-    for a0, a1 in zip(starts[:-1], starts[1:]):
-        ev.append(sla.eigvals(t[a0:a1, a0:a1], s[a0:a1, a0:a1]))
-    got = np.sort_complex(np.concatenate(ev))
-    want = np.sort_complex(pb["lam"].astype(complex))
-    eig_err = float(np.max(np.abs(got - want) / np.abs(want)))
+    extras = None
+    if not args.no_extras:
+        del A
+        torch.cuda.empty_cache()
+        extras = other_configs(P, h)
     h.close()
 
     value = flops / dt / 1e9
-    names = {P.KERNEL_UPDATE: "k_update (tree-level trailing update, MFMA f64)",
-             P.KERNEL_PANEL: "k_panel (TSQR panel Householder)",
-             P.KERNEL_GEMM: "k_gemm (MFMA f64)",
-             P.KERNEL_LA: "k_la (look-ahead update of the next panel, MFMA f64)"}
-    def roofline(k):
-        """Roofline object of kernel k from its event-timed launches: the
-        panel factorization against the FP64 vector peak (it is a sequential
-        column loop in few workgroups), the MFMA kernels against HBM or FP64
-        MFMA by their algorithmic intensity."""
-        sd = stats[k]
-        if sd["ms"] <= 0:
-            return None
-        secs = sd["ms"] / 1e3
-        if k == P.KERNEL_PANEL:
-            ach = sd["flops"] / secs / 1e12
-            r = {"bound": "alu", "achieved": ach, "peak": PEAK["fp64_tflops"], "unit": "TFLOP/s",
-                 "frac": ach / PEAK["fp64_tflops"], "traffic": None}
-        else:
-            inten = sd["flops"] / max(sd["bytes"], 1.0)
-            if inten < PEAK["fp64_tflops"] * 1e12 / (PEAK["hbm_gbs"] * 1e9):
-                ach = sd["bytes"] / secs / 1e9
-                r = {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
-                     "frac": ach / PEAK["hbm_gbs"], "traffic": None}
-            else:
-                ach = sd["flops"] / secs / 1e12
-                r = {"bound": "mfma", "achieved": ach, "peak": PEAK["fp64_tflops"], "unit": "TFLOP/s",
-                     "frac": ach / PEAK["fp64_tflops"], "traffic": None}
-        if k == P.KERNEL_UPDATE and TRAFFIC and TRAFFIC.get("sha256") == kernel_sources_sha() \
-                and TRAFFIC.get("n") == n and TRAFFIC.get("leaf") == leaf:
-            r["traffic"] = TRAFFIC["bytes_per_launch"]
-            r["traffic_note"] = TRAFFIC["note"]
-        r["kernel"] = names[k]
-        r["launches"] = sd["launches"]
-        r["avg_launch_us"] = sd["ms"] * 1e3 / max(sd["launches"], 1)
-        r["algorithmic_flops_per_launch"] = sd["flops"] / max(sd["launches"], 1)
-        r["algorithmic_bytes_per_launch"] = sd["bytes"] / max(sd["launches"], 1)
-        return r
-
-    roof = roof_upd = None
-    if not args.no_profile:
-        # dominant = largest summed launch time (the panel and the update
-        # kernels run on two streams, so their times overlap); the bulk
-        # HBM-bound update is reported beside it when it is not the dominant
-        dom = max(stats, key=lambda k: stats[k]["ms"])
-        roof = roofline(dom)
-        if dom != P.KERNEL_UPDATE:
-            roof_upd = roofline(P.KERNEL_UPDATE)
+    value32 = flops32 / dt32 / 1e9
+    roof = roof32 = None
+    if stats64 is not None:
+        names = kernel_names(P, "f64")
+        tr = TRAFFIC if (TRAFFIC and TRAFFIC.get("sha256") == kernel_sources_sha() and TRAFFIC.get("n") == n) else None
+        roof = _roofline(P, stats64, P.KERNEL_UPDATE, names, PEAK["fp64_tflops"], tr)
+        roof32 = _roofline(P, stats32, P.KERNEL_UPDATE, kernel_names(P, "f32"), PEAK["fp32_tflops"])
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
-        cpu = cpu_baseline()
+        cpu = cpu_baseline_sym()
     out = {
-        "metric": "split GFLOP/s (nominal split flops / wall time), FP64",
+        "metric": "split GFLOP/s (nominal split flops / wall time), FP64; FP32+refine beside it",
         "value": value,
         "unit": "GFLOP/s",
         "n_gpus": 1,
@@ -401,19 +529,25 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"divide-and-conquer of an order-{n} real pencil (unit circle, then recursion "
-                               f"to blocks <= {leaf}), FP64", "n": n, "leaf_max": leaf,
-                   "generator": "sdc_synth.pencil_problem seed 10113077+1000"},
+        "config": {"workload": f"symmetric split of one clustered order-{n} problem at Re z < 0 (half the eigenvalues "
+                               f"on each side, 5% per side within 1e-3 of +-0.01), FP64", "n": n,
+                   "generator": "sdc_synth.clustered_sym_problem seed 10113077+3000"},
         "pct_fp64_peak": value / (PEAK["fp64_tflops"] * 1e3),
         "nominal_flops_per_step": flops / args.steps,
-        "splits_per_step": info["splits"],
-        "blocks": info["nblocks"],
-        "eig_rel_err_vs_construction": eig_err,
-        "kernels": {names[k]: v for k, v in stats.items()},
-        "kernel_timing": "HIP events around every launch, in a second pass of the same steps "
-                         "(ms_per_step of that pass: %s)" % (None if dt_prof is None else round(dt_prof / args.steps * 1e3, 1)),
+        "accuracy": acc64,
+        "fp32_refine": {"value": value32, "unit": "GFLOP/s", "steps": k32, "ms_per_step": dt32 / k32 * 1e3,
+                        "pct_fp32_peak": value32 / (PEAK["fp32_tflops"] * 1e3),
+                        "pct_fp64_peak": value32 / (PEAK["fp64_tflops"] * 1e3),
+                        "speedup_vs_fp64": (dt / args.steps) / (dt32 / k32),
+                        "dtype": "f32 squaring + f64 test, rank, block form and refinement",
+                        "nominal_flops_note": "refinement flops not credited", "accuracy": acc32,
+                        "roofline_update": roof32},
+        "accuracy_note": "eigenvalues of the two diagonal blocks against the construction's (the FP64 oracle "
+                         "at this order is the construction up to its own rounding); order 128 against the oracle",
+        "kernels_fp64": None if stats64 is None else {kernel_names(P, "f64")[k]: v for k, v in stats64.items()},
+        "kernel_timing": "HIP events around every launch of the hot kernels, in one extra split per precision",
         "roofline": roof,
-        "roofline_update": roof_upd,
+        "other_configs": extras,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -214,6 +214,9 @@ typedef struct {
     int nblocks;         /* diagonal blocks of the final block-triangular pair */
     int splits;          /* split steps attempted (every call of the split step) */
     int accepted;        /* split steps that divided a block */
+    int extra_splits;    /* additional split points taken from accepted steps: every k'
+                            besides the step's k with e(k') <= split_tol also divides the
+                            block (more than two pieces, the remark after Alg. 4) */
     int levels;          /* recursion levels run (each level is one batched call) */
     int unsplit;         /* blocks larger than leaf_max given up on (every curve tried met
                             their pseudospectrum, Sec. 3.6) */
@@ -260,6 +263,10 @@ typedef struct {
  * perturbed radius; after 3 failed circles with none that worked the block is
  * given up and counted in info->near_singular, after 8 failed lines it is
  * given up with the bound the search reached (info->unsplit counts both).
+ * An accepted step divides its block at its split point k and at every other
+ * k' whose coupling blocks are as small (e(k') <= opts->split_tol), so a
+ * cluster of equal eigenvalues, which no curve separates, still falls apart
+ * into blocks of order 1 once it is split off (info->extra_splits).
  * Outputs (device, column-major): T = Q_L^T A Q_R and, for pencils,
  * S = Q_L^T B Q_R, block upper triangular with the strictly-lower coupling
  * blocks set to zero; QL and QR (may be NULL) accumulate the transformations
@@ -325,6 +332,23 @@ sdc_status_t sdc_split_svd(sdc_handle_t h, int m, int n, const double* A, int ld
 sdc_status_t sdc_block_eigvals(sdc_handle_t h, int n, const double* T, int ldt, const double* S, int lds,
                                int nblocks, const int* block_start, int symmetric, double* wr, double* wi,
                                double* V, int ldv);
+
+/* Eigenvectors of an upper-triangular matrix or pencil (TREVC, Sec. 5),
+ * blocked as Alg. 8 with 32 x 32 blocks.  For upper-triangular T (and S;
+ * S == NULL means S = I) with eigenvalues lambda_j = T_jj / S_jj, X (n x n)
+ * receives the upper-triangular eigenvector matrix with unit diagonal:
+ * T X = S X diag(lambda), i.e. column j solves (T - lambda_j S) x = 0 with
+ * x_j = 1 and zeros below; X is written in full.  Only the upper triangles
+ * of T and S are read.  The eigenvalues are assumed distinct (a real
+ * spectrum: sdc_eig_dc with leaf_max = 1 on a pencil with real eigenvalues
+ * gives such T and S, and Q_R X then holds the pencil's right
+ * eigenvectors); a denominator T_ii - lambda_j S_ii smaller than
+ * eps (|T_ii| + |lambda_j S_ii|) is replaced by that bound, as LAPACK's
+ * TREVC guards it.  No scaling against overflow is done.  T, S, X are
+ * device pointers, column-major, leading dimensions >= n, caller-owned.
+ * Returns SDC_OK, or SDC_ERR_INVALID for bad arguments. */
+sdc_status_t sdc_trevc(sdc_handle_t h, int n, const double* T, int ldt, const double* S, int lds, double* X,
+                       int ldx);
 
 /* Per-kernel timing (opt-in).  With profiling enabled every launch of the
  * hot kernels is bracketed by HIP events on the handle's stream and its

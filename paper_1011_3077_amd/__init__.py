@@ -30,7 +30,7 @@ SDC_UNIT_DISK, SDC_DISK, SDC_HALFPLANE = 0, 1, 2
 EXPORTED = ["sdc_opts_default", "sdc_create", "sdc_destroy", "sdc_status_string", "sdc_irs",
             "sdc_split_sym", "sdc_split_sym_noalloc", "sdc_split_nonsym", "sdc_split_pencil", "sdc_split_sym_batched", "sdc_split_svd",
             "sdc_eig_dc",
-            "sdc_block_eigvals",
+            "sdc_block_eigvals", "sdc_trevc",
             "sdc_gaussian",
             "sdc_profile_enable", "sdc_profile_read", "sdc_server_create", "sdc_server_submit",
             "sdc_server_poll", "sdc_server_wait", "sdc_server_stats", "sdc_server_destroy"]
@@ -61,7 +61,8 @@ class Info(C.Structure):
 
 class DcInfo(C.Structure):
     _fields_ = [("n", C.c_int), ("nblocks", C.c_int), ("splits", C.c_int), ("accepted", C.c_int),
-                ("levels", C.c_int), ("unsplit", C.c_int), ("near_singular", C.c_int), ("iters_total", C.c_int),
+                ("extra_splits", C.c_int), ("levels", C.c_int), ("unsplit", C.c_int), ("near_singular", C.c_int),
+                ("iters_total", C.c_int),
                 ("nominal_flops", C.c_double), ("ms", C.c_double), ("e21_max", C.c_double)]
 
     def as_dict(self):
@@ -134,6 +135,8 @@ lib.sdc_split_svd.argtypes = [_P, _I, _I, _P, _I, Region, C.POINTER(Opts), _P, _
 lib.sdc_split_svd.restype = _I
 lib.sdc_block_eigvals.argtypes = [_P, _I, _P, _I, _P, _I, _I, C.POINTER(_I), _I, _P, _P, _P, _I]
 lib.sdc_block_eigvals.restype = _I
+lib.sdc_trevc.argtypes = [_P, _I, _P, _I, _P, _I, _P, _I]
+lib.sdc_trevc.restype = _I
 lib.sdc_profile_enable.argtypes = [_P, _I]
 lib.sdc_profile_enable.restype = _I
 lib.sdc_profile_read.argtypes = [_P, _I, C.POINTER(KernelStats)]
@@ -192,6 +195,15 @@ def _cm(t):
     return t.t().contiguous()
 
 
+def _cm_sym(t):
+    """Column-major buffer of a symmetric matrix: its own memory when it is
+    contiguous (a symmetric matrix equals its transpose), else a copy."""
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.dim() == 2):
+        raise TypeError("expected a 2-D float64 tensor on a HIP device")
+    return t if t.is_contiguous() else t.t().contiguous()
+
+
 def _out(n, like):
     import torch
     return torch.empty((n, n), dtype=torch.float64, device=like.device)
@@ -244,7 +256,7 @@ class Handle:
 
     def split_sym(self, A, reg: Region | None = None, o: Opts | None = None) -> SplitResult:
         n = A.shape[0]
-        a = _cm(A)
+        a = _cm_sym(A)
         q, ah = _out(n, A), _out(n, A)
         info = Info()
         st = _check(lib.sdc_split_sym(self._h, n, a.data_ptr(), n, reg or region(), C.byref(o or opts()),
@@ -286,7 +298,7 @@ class Handle:
 
     def split_sym_batched(self, As, regs, o: Opts | None = None):
         cnt = len(As)
-        cms = [_cm(a) for a in As]
+        cms = [_cm_sym(a) for a in As]
         outs_q = [_out(a.shape[0], a) for a in As]
         outs_a = [_out(a.shape[0], a) for a in As]
         ns = (_I * cnt)(*[a.shape[0] for a in As])
@@ -363,6 +375,16 @@ class Handle:
                                      int(symmetric), wr.data_ptr(), wi.data_ptr(),
                                      None if v is None else v.data_ptr(), n))
         return (wr, wi) if v is None else (wr, wi, v.t())
+
+    def trevc(self, T, S=None):
+        """Eigenvectors of the upper-triangular T (pencil (T, S)): X upper
+        triangular with unit diagonal, T X = S X diag(T_jj / S_jj)."""
+        n = T.shape[0]
+        t = _cm(T)
+        s = _cm(S) if S is not None else None
+        x = _out(n, T)
+        _check(lib.sdc_trevc(self._h, n, t.data_ptr(), n, None if s is None else s.data_ptr(), n, x.data_ptr(), n))
+        return x.t()
 
     def profile_enable(self, on: bool = True):
         _check(lib.sdc_profile_enable(self._h, int(on)))

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsdc.so")
 SOURCES = ["qr_kernels.hip", "aux_kernels.hip", "engine.hip", "eig_dc.hip", "refine_kernels.hip", "leaf_kernels.hip",
-           "capi.hip", "server.hip"]
+           "trevc_kernels.hip", "capi.hip", "server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SDC_OFFLOAD_ARCH", "gfx950")

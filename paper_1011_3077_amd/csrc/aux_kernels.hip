@@ -333,6 +333,15 @@ template void fill<double>(double*, size_t, double, hipStream_t);
 template void fill<float>(float*, size_t, float, hipStream_t);
 template void fill<unsigned>(unsigned*, size_t, unsigned, hipStream_t);
 
+// Zero many small device arrays in one launch (one block per array).
+__global__ __launch_bounds__(256) void k_zero(const ZeroDesc* __restrict__ descs) {
+    const ZeroDesc d = descs[blockIdx.x];
+    for (unsigned i = threadIdx.x; i < d.words; i += 256) d.p[i] = 0u;
+}
+void zero_batch(const ZeroDesc* d, int count, hipStream_t s) {
+    if (count > 0) hipLaunchKernelGGL(k_zero, dim3(count), dim3(256), 0, s, d);
+}
+
 // ---------------------------------------------------------------------------
 // Norms and the split-point search (Alg. 4 line 5; the prefix-sum plus max
 // reduction of Sec. 4.2).

@@ -250,6 +250,19 @@ sdc_status_t sdc_split_sym_noalloc(sdc_handle_t hd, int n, const double* A, int 
     return (sdc_status_t)j.status;
 }
 
+sdc_status_t sdc_trevc(sdc_handle_t hd, int n, const double* T, int ldt, const double* S, int lds, double* X,
+                       int ldx) {
+    if (!hd || n < 0 || n > kMaxN || (n > 0 && (!T || !X)) || ldt < n || ldx < n || (S && lds < n))
+        return SDC_ERR_INVALID;
+    if (n == 0) return SDC_OK;
+    Handle& h = hd->h;
+    if (use_device(h) != SDC_OK) return SDC_ERR_DEVICE;
+    sdc::TrevcArgs a{T, ldt, S, S ? lds : n, X, ldx, n};
+    sdc::trevc_launch(a, h.stream);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h.stream) != hipSuccess) return SDC_ERR_DEVICE;
+    return SDC_OK;
+}
+
 sdc_status_t sdc_split_nonsym(sdc_handle_t hd, int n, const double* A, int lda, sdc_region_t region,
                               const sdc_opts_t* opts, double* Q, int ldq, double* Ahat, int ldah, sdc_info_t* info) {
     if (!hd || n < 0 || n > kMaxN || (n > 0 && (!A || !Q || !Ahat)) || lda < n || ldq < n || ldah < n || !region_ok(region))

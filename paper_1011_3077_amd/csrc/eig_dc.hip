@@ -238,8 +238,18 @@ int run_eig_dc(Handle& h, int n, const double* A, int lda, const double* B, int 
             need += 4 * m * m + 2 * m * (size_t)(n - work[i].e) + 2 * (size_t)work[i].s * m + 2 * (size_t)n * m;
             need = (need + 31) & ~size_t(31);
         }
+        // e(k) profiles of the split steps, back to back (for multi-way splits)
+        std::vector<size_t> poff(cnt);
+        const size_t prof0 = need;
+        for (int i = 0; i < cnt; ++i) {
+            poff[i] = need - prof0;
+            need += (size_t)(work[i].e - work[i].s);
+        }
+        const size_t prof_len = need - prof0;
+        need = (need + 31) & ~size_t(31);
         CHK(ensure_ws2(h, need * sizeof(double) + 4096));
         double* base = reinterpret_cast<double*>(h.ws2);
+        double* prof = base + prof0;
 
         std::vector<SplitJob> jobs(cnt);
         std::vector<sdc_region_t> regs(cnt);
@@ -275,10 +285,16 @@ int run_eig_dc(Handle& h, int n, const double* A, int lda, const double* B, int 
             j.QL = o + (size_t)m * m; j.ldql = m;
             j.Ahat = o + 2 * (size_t)m * m; j.ldah = m;
             j.Bhat = o + 3 * (size_t)m * m; j.ldbh = m;
+            j.eprof = prof + poff[i];
             if (symmetric) j.QL = nullptr;
         }
         CHK(run_split_jobs(h, jobs));
         h.desc_off = 0;
+        CHK(ensure_host(h, prof_len * sizeof(double) + 64));
+        HIPCHK(hipMemcpyAsync(h.host, prof, prof_len * sizeof(double), hipMemcpyDeviceToHost, h.stream));
+        HIPCHK(hipStreamSynchronize(h.stream));
+        const std::vector<double> hprof(reinterpret_cast<const double*>(h.host),
+                                        reinterpret_cast<const double*>(h.host) + prof_len);
 
         // ---- classify, and collect the global updates of accepted splits
         std::vector<EwDesc> put, zero, back1, back2;
@@ -335,14 +351,21 @@ int run_eig_dc(Handle& h, int n, const double* A, int lda, const double* B, int 
             double* rowt = o + 4 * (size_t)m * m;
             double* colt = rowt + 2 * (size_t)m * (n - b.e);
             double* fact = colt + 2 * (size_t)b.s * m;
+            // split points: k, and every other k' whose coupling blocks are as
+            // small (e(k') <= split_tol): the step may divide the block into
+            // more than two (the remark after Alg. 4)
+            std::vector<int> cuts;
+            const double* ep = hprof.data() + poff[i];
+            for (int kk = 1; kk < m; ++kk)
+                if (kk == k || ep[kk] <= j.opts.split_tol) cuts.push_back(kk);
+            st.extra_splits += (int)cuts.size() - 1;
             put.push_back(copy_desc(m, m, Ah, m, T + b.s + (size_t)b.s * ldt, ldt));
-            zero.push_back(zero_desc(m - k, k, T + (b.s + k) + (size_t)b.s * ldt, ldt));
-            if (!symmetric) {
-                put.push_back(copy_desc(m, m, Bh, m, S + b.s + (size_t)b.s * lds, lds));
-                zero.push_back(zero_desc(m - k, k, S + (b.s + k) + (size_t)b.s * lds, lds));
-            } else {
+            if (!symmetric) put.push_back(copy_desc(m, m, Bh, m, S + b.s + (size_t)b.s * lds, lds));
+            for (int kk : cuts) {
+                zero.push_back(zero_desc(m - kk, kk, T + (b.s + kk) + (size_t)b.s * ldt, ldt));
+                if (!symmetric) zero.push_back(zero_desc(m - kk, kk, S + (b.s + kk) + (size_t)b.s * lds, lds));
                 // symmetric: the dropped coupling block is E21 and E21^T
-                zero.push_back(zero_desc(k, m - k, T + b.s + (size_t)(b.s + k) * ldt, ldt));
+                else zero.push_back(zero_desc(kk, m - kk, T + b.s + (size_t)(b.s + kk) * ldt, ldt));
             }
             // For symmetric A both coupling blocks are dropped at every split,
             // so T stays block diagonal and the row/column updates would
@@ -375,10 +398,10 @@ int run_eig_dc(Handle& h, int n, const double* A, int lda, const double* B, int 
                                          fact + (size_t)n * m, n));
                 back2.push_back(copy_desc(n, m, fact + (size_t)n * m, n, QL + (size_t)b.s * ldql, ldql));
             }
-            // children: leading block = eigenvalues outside the curve
+            // children: leading block(s) = eigenvalues outside the curve, the
+            // trailing one(s) inside; the pieces of a multi-way split inherit
+            // the bound of their side
             Block c1 = b, c2 = b;
-            c1.e = b.s + k;
-            c2.s = b.s + k;
             c1.tries = c2.tries = 0;
             if (b.mode == MODE_CIRCLE) {
                 // outside the circle r: reciprocals inside 1/r; inside: lines inside r
@@ -388,9 +411,15 @@ int run_eig_dc(Handle& h, int n, const double* A, int lda, const double* B, int 
                 c1.lo = regs[i].shift;
                 c2.hi = regs[i].shift;
             }
-            for (const Block& c : {c1, c2}) {
+            int lo = 0;
+            cuts.push_back(m);
+            for (int hi : cuts) {
+                Block c = hi <= k ? c1 : c2;
+                c.s = b.s + lo;
+                c.e = b.s + hi;
                 if (c.e - c.s <= leaf_max) leaves.push_back(c);
                 else next.push_back(c);
+                lo = hi;
             }
         }
         // order matters only between the phases: row updates, then column

@@ -102,14 +102,17 @@ template <typename T> static const QrStreams* lookahead(Handle& h, const std::ve
 // inputs and the region map; tree counters cleared.
 template <typename T> static int irs_start(Handle& h, std::vector<IrsSide<T>*>& sides) {
     std::vector<IrsInit<T>> ini;
+    std::vector<ZeroDesc> zd;
     for (IrsSide<T>* sp : sides) {
         IrsSide<T>& s = *sp;
         if (s.started) continue;
         ini.push_back(IrsInit<T>{s.W, s.n, s.ld, s.A, s.lda, s.B, s.ldb, s.a1, s.a2, s.b1, s.b2, s.trans});
-        fill<unsigned>(s.counters, kMaxInternal, 0u, h.stream);
+        zd.push_back(ZeroDesc{s.counters, (unsigned)kMaxInternal});
         s.p = 0; s.converged = 0; s.nonfinite = 0; s.rconv = NAN; s.done = 0; s.started = 1;
     }
     if (ini.empty()) return SDC_OK;
+    UPLOAD(dzd, zd);
+    zero_batch(dzd, (int)zd.size(), h.stream);
     UPLOAD(dini, ini);
     irs_init_batch<T>(dini, ini.data(), (int)ini.size(), h.stream);
     return SDC_OK;
@@ -995,6 +998,7 @@ static int finish_jobs(Handle& h, std::vector<JobWs*>& wsp) {
     // views of (A_p, B_p) in FP64; norms of the inputs
     std::vector<EwDesc> conv;
     std::vector<NormDesc> nrm;
+    std::vector<ZeroDesc> zd;
     std::vector<JobWs*> live;
     for (JobWs* wp : wsp) {
         JobWs& w = *wp;
@@ -1029,12 +1033,16 @@ static int finish_jobs(Handle& h, std::vector<JobWs*>& wsp) {
             w.status = SDC_ERR_NONFINITE;
             continue;
         }
-        fill<double>(w.nrm, 2, 0.0, h.stream);
-        fill<double>(w.orth, 1, 0.0, h.stream);
-        fill<unsigned>(w.qcnt, kMaxInternal, 0u, h.stream);
+        zd.push_back(ZeroDesc{reinterpret_cast<unsigned*>(w.nrm), 4u});
+        zd.push_back(ZeroDesc{reinterpret_cast<unsigned*>(w.orth), 2u});
+        zd.push_back(ZeroDesc{w.qcnt, (unsigned)kMaxInternal});
         nrm.push_back(NormDesc{j.A, j.lda, n, n, w.nrm, 1});
         if (j.pencil) nrm.push_back(NormDesc{j.B, j.ldb, n, n, w.nrm + 1, 1});
         live.push_back(&w);
+    }
+    if (!zd.empty()) {
+        UPLOAD(dzd, zd);
+        zero_batch(dzd, (int)zd.size(), h.stream);
     }
     if (!conv.empty()) {
         UPLOAD(dc, conv);
@@ -1078,6 +1086,23 @@ static int finish_jobs(Handle& h, std::vector<JobWs*>& wsp) {
             j.info.n_inside = j.n - k;
         }
         h.desc_off = 0;
+    }
+
+    // the e(k) profile of the returned split, where the caller wants it
+    {
+        std::vector<EwDesc> ep;
+        for (JobWs* w : wsp) {
+            SplitJob& j = *w->job;
+            if (!j.eprof || w->status != SDC_OK || j.n < 2) continue;
+            EwDesc d{};
+            d.op = EW_PERMUTE; d.n = 1; d.rows = j.n; d.in = w->e; d.ldi = j.n; d.out = j.eprof; d.ldo = j.n;
+            d.alpha = 1.0; d.active = 1;
+            ep.push_back(d);
+        }
+        if (!ep.empty()) {
+            UPLOAD(dep, ep);
+            ew_batch<double, double>(dep, ep.data(), (int)ep.size(), h.stream);
+        }
     }
 
     // diagnostics: ||Q^T Q - I||_F

@@ -92,6 +92,8 @@ struct SplitJob {
     double* QL = nullptr; int ldql = 0;
     double* Ahat = nullptr; int ldah = 0;
     double* Bhat = nullptr; int ldbh = 0;
+    double* eprof = nullptr;  // optional device output (n doubles): e(k) for k = 1 .. n-1 of the
+                              // returned split, at index k (the multi-way splits of the recursion)
     sdc_info_t info{};
     int status = 0;
 };

@@ -99,11 +99,26 @@ template <typename Tin, typename Tout>
 void ew_batch(const EwDesc* d, const EwDesc* h, int count, hipStream_t s);
 template <typename T>
 void fill(T* p, size_t n, T v, hipStream_t s);
+// Zeroing of many small arrays (counters, norm accumulators) in one launch.
+struct ZeroDesc {
+    unsigned* p;
+    unsigned words;  // 4-byte words
+};
+void zero_batch(const ZeroDesc* d, int count, hipStream_t s);
 void norm1_batch(const NormDesc* d, const NormDesc* h, int count, hipStream_t s);
 void split_search_batch(const SplitDesc* d, const SplitDesc* h, int count, hipStream_t s);
 void orth_err_batch(const NormDesc* d, const NormDesc* h, int count, hipStream_t s);
 void gauss_batch(const GaussDesc* d, const GaussDesc* h, int count, hipStream_t s);
 
 void gather_batch(const GatherDesc* d, int count, double* dst, hipStream_t s);
+
+// Eigenvectors of an upper-triangular matrix or pencil (TREVC, Alg. 8).
+struct TrevcArgs {
+    const double* T; int ldt;
+    const double* S; int lds;   // nullptr: S = I
+    double* X; int ldx;
+    int n;
+};
+void trevc_launch(const TrevcArgs& a, hipStream_t s);
 
 }  // namespace sdc

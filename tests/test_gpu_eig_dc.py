@@ -238,3 +238,24 @@ def test_block_eigvals_all_order_one_blocks(handle, sdc):
     wr, wi = handle.block_eigvals(dev(t), dev(s), starts, symmetric=False)
     assert np.allclose(wr.cpu().numpy(), np.diag(t) / np.diag(s), rtol=1e-15, atol=0)
     assert not wi.cpu().numpy().any()
+
+
+def test_multiway_split_separates_a_repeated_eigenvalue(handle, sdc):
+    """A five-fold eigenvalue of a symmetric matrix: no line separates equal
+    eigenvalues, but the step that isolates their invariant subspace leaves
+    every coupling block inside it negligible, and the library (like the
+    oracle) divides there too, down to blocks of order 1."""
+    import sys, os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from test_oracle_eig_dc import repeated_eig_problem
+    from oracle.eig_dc import eig_dc
+    print("CASE multiway", flush=True)
+    a, d = repeated_eig_problem(30, 11)
+    st, t, s, ql, qr, starts, info = handle.eig_dc(dev(a), None, leaf_max=1, symmetric=True, o=sdc.opts(seed=2))
+    assert st == 0 and info["unsplit"] == 0 and info["extra_splits"] >= 4, info
+    assert starts == list(range(31))
+    t, qr = t.cpu().numpy(), qr.cpu().numpy()
+    assert np.abs(np.sort(np.diag(t)) - np.sort(d)).max() <= 1e-12
+    assert np.abs(qr.T @ a @ qr - t).max() <= 1e-10
+    ref = eig_dc(a, symmetric=True, leaf_max=1, seed=2)
+    assert ref["extra_splits"] >= 4 and np.abs(np.sort(np.diag(ref["T"])) - np.sort(np.diag(t))).max() <= 1e-12
