@@ -12,7 +12,9 @@
 //     order of the eigenvalues when the caller asks for them;
 //   * pencil block (T, S) of order 1: T/S; of order 2: the roots of
 //     det(T - lambda S) = 0, real ones ascending, a complex pair as
-//     (re, +im), (re, -im); an infinite eigenvalue (singular S) as +-inf;
+//     (re, +im), (re, -im), from the 2 x 2 matrix S'^{-1} T' after a rotation
+//     that makes S upper triangular (the shape LAPACK's QZ hands its 2 x 2
+//     solver); an infinite eigenvalue (singular S) as +-inf;
 //   * any other block: NaN (the recursion can be run to blocks of order <= 2
 //     for a pencil; a symmetric block above kJacobiMax is left to the caller).
 #include <cmath>
@@ -49,28 +51,43 @@ __device__ void pencil_small(const BlockEigDesc& d) {
     }
     const double t11 = d.T[0], t21 = d.T[1], t12 = d.T[d.ldt], t22 = d.T[d.ldt + 1];
     const double s11 = d.S[0], s21 = d.S[1], s12 = d.S[d.lds], s22 = d.S[d.lds + 1];
-    // det(T - l S) = a l^2 + b l + c
-    const double a = s11 * s22 - s12 * s21;
-    const double b = -(t11 * s22 + t22 * s11 - t12 * s21 - t21 * s12);
-    const double c = t11 * t22 - t12 * t21;
+    // a rotation from the left makes S upper triangular: (T', S') = G (T, S)
+    const double h = hypot(s11, s21);
+    const double gc = h > 0.0 ? s11 / h : 1.0, gs = h > 0.0 ? s21 / h : 0.0;
+    const double u11 = h, u12 = gc * s12 + gs * s22, u22 = gc * s22 - gs * s12;
+    const double v11 = gc * t11 + gs * t21, v12 = gc * t12 + gs * t22;
+    const double v21 = gc * t21 - gs * t11, v22 = gc * t22 - gs * t12;
     double r0, r1, i0 = 0.0, i1 = 0.0;
-    if (a == 0.0) {  // one infinite eigenvalue
+    if (u11 == 0.0 || u22 == 0.0) {
+        // singular S: det(T' - l S') = a l^2 + b l + c with a = 0, one
+        // infinite eigenvalue and the root of the linear part
+        const double b = -(v11 * u22 + v22 * u11 - v12 * 0.0 - v21 * u12);
+        const double c = v11 * v22 - v12 * v21;
         r0 = b != 0.0 ? -c / b : nan;
         r1 = (b >= 0.0 ? 1.0 : -1.0) * INFINITY;
+        if (u11 == 0.0 && u22 == 0.0) r0 = nan;
     } else {
-        const double disc = b * b - 4.0 * a * c;
+        // M = S'^{-1} T', whose eigenvalues m22 + p +- sqrt(p^2 + m12 m21),
+        // p = (m11 - m22) / 2, are formed without the cancellation of the
+        // determinant's coefficients (the larger root first, the other from
+        // the product of the two)
+        const double m21 = v21 / u22, m22 = v22 / u22;
+        const double m11 = (v11 - u12 * m21) / u11, m12 = (v12 - u12 * m22) / u11;
+        const double pp = 0.5 * (m11 - m22);
+        const double bc = m12 * m21;
+        const double disc = pp * pp + bc;
         if (disc >= 0.0) {
-            const double q = -0.5 * (b + copysign(sqrt(disc), b));
-            r0 = q != 0.0 ? q / a : 0.0;
-            r1 = q != 0.0 ? c / q : 0.0;
+            const double z = pp + copysign(sqrt(disc), pp);
+            r0 = m22 + z;
+            r1 = z != 0.0 ? m22 - bc / z : m22;
             if (r1 < r0) {
                 const double t = r0;
                 r0 = r1;
                 r1 = t;
             }
         } else {
-            r0 = r1 = -b / (2.0 * a);
-            i0 = sqrt(-disc) / (2.0 * fabs(a));
+            r0 = r1 = m22 + pp;
+            i0 = sqrt(-disc);
             i1 = -i0;
         }
     }

@@ -259,3 +259,21 @@ def test_multiway_split_separates_a_repeated_eigenvalue(handle, sdc):
     assert np.abs(qr.T @ a @ qr - t).max() <= 1e-10
     ref = eig_dc(a, symmetric=True, leaf_max=1, seed=2)
     assert ref["extra_splits"] >= 4 and np.abs(np.sort(np.diag(ref["T"])) - np.sort(np.diag(t))).max() <= 1e-12
+
+
+def test_pencil_benchmark_workload_to_order_two_leaves(handle, sdc):
+    """The order-2048 benchmark pencil recursed to blocks of order <= 2 and
+    every eigenvalue taken from the leaves (closed forms): the construction's
+    spectrum within 1e-10 relative, no block left unsplit."""
+    n = 2048
+    print("CASE eig_dc to order-2 leaves", n, flush=True)
+    p = S.pencil_problem(n, S.family_seed(1))
+    st, t, s, ql, qr, starts, info = handle.eig_dc(dev(p["A"]), dev(p["B"]), leaf_max=2, o=sdc.opts(seed=1),
+                                                    factors=False)
+    print("info", {k: v for k, v in info.items() if k != "bounds"}, flush=True)
+    assert st == 0 and info["unsplit"] == 0 and info["near_singular"] == 0
+    assert all(e - s0 <= 2 for s0, e in zip(starts[:-1], starts[1:]))
+    wr, wi = handle.block_eigvals(t, s, starts, symmetric=False)
+    got = np.sort_complex((wr + 1j * wi).cpu().numpy())
+    want = np.sort_complex(p["lam"].astype(complex))
+    assert np.max(np.abs(got - want) / np.abs(want)) <= 1e-10
