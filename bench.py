@@ -39,13 +39,13 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp64_tflops": 78.6, "fp32_tflops": 157.3, "hbm_gbs": 8000.0}
 
 # HBM traffic of the dominant kernel (the tree-level trailing update), from
-# two rocprofv3 --pmc runs of `bench.py --steps 1 --warmup 0 --calibrate-copy`
-# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch): summed over the update's
-# dispatches in the step, each counter scaled by what it reads for a plain
-# 256 MiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), divided by the
-# number of dispatches.  Valid only for the kernel sources it was measured
+# two rocprofv3 --pmc runs of `bench.py --steps 1 --warmup 0 --calibrate-copy
+# --no-profile --no-extras --fp32-steps 1` (FETCH_SIZE, then WRITE_SIZE, KiB
+# per dispatch): summed over the update's dispatches in the FP64 split, each
+# counter scaled by what it reads for a plain 256 MiB device copy
+# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), divided by the number of dispatches.  Valid only for the kernel sources it was measured
 # on (their SHA-256 below); otherwise reported as null.
-TRAFFIC = {"bytes_per_launch": 104149743, "sha256": "8da58b698a64b6f50779c27be1f16b1f1c636739e8a02126cbd01fe818b79e80", "n": 2048, "leaf": 64, "note": "rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 over 6831 update dispatches of one step"}
+TRAFFIC = {"bytes_per_launch": 1579156800, "sha256": "8da58b698a64b6f50779c27be1f16b1f1c636739e8a02126cbd01fe818b79e80", "n": 8192, "note": "rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 over the 10536 update dispatches of one FP64 split"}
 
 
 def log(*a):
@@ -65,7 +65,10 @@ def serve_main(args):
     """Serving benchmark: Poisson arrivals of split requests (sizes
     log-uniform in [nmin, nmax]; 70% symmetric, half of them FP32+refine; 30%
     nonsymmetric pencils, FP64) into the continuous-batching server, inputs
-    resident in HBM; reports p50/p99 latency and throughput.  Requests reuse a
+    resident in HBM; one JSON line per offered rate (--rate takes a
+    comma-separated list) with p50/p99 latency, throughput, the queue at the
+    end of the arrivals, and a check that sampled requests' results are
+    bitwise those of single calls with the same arguments.  Requests reuse a
     pool of distinct problems (each request draws its own Gaussian seed)."""
     import numpy as np
     import torch
@@ -90,58 +93,77 @@ def serve_main(args):
                              B=torch.from_numpy(pb["B"]).to("cuda:0"), reg=P.region(), prec=P.SDC_FP64,
                              k=int((np.abs(pb["lam"]) > 1).sum())))
     torch.cuda.synchronize()
-    arrivals = []
-    t = 0.0
-    while True:
-        t += rng.exponential(1.0 / args.rate)
-        if t > args.duration:
-            break
-        arrivals.append(t)
-    log(f"[serve] {len(arrivals)} arrivals over {args.duration} s at {args.rate}/s")
-    srv = P.Server(0)
-    tickets = []
-    t0 = time.perf_counter()
-    for i, ta in enumerate(arrivals):
-        dt = ta - (time.perf_counter() - t0)
-        if dt > 0:
-            time.sleep(dt)
-        q = pool[i % pool_size]
-        tickets.append((srv.submit(q["A"], q["B"], q["reg"], P.opts(prec=q["prec"], seed=1000 + i)), q))
-    bad = 0
-    statuses = {}
-    for tk, q in tickets:
-        r = srv.wait(tk)
-        statuses[r.status] = statuses.get(r.status, 0) + 1
-        if r.status != 0 or r.info["k_lead"] != q["k"]:
-            bad += 1
-    st = srv.stats()
-    srv.close()
-    wall = st["wall_ms"] / 1e3
-    out = {
-        "metric": "served split requests: p99 latency (submission to completion)",
-        "value": st["p99_ms"],
-        "unit": "ms",
-        "higher_is_better": False,
-        "n_gpus": 1,
-        "p50_ms": st["p50_ms"],
-        "mean_ms": st["mean_ms"],
-        "max_ms": st["max_ms"],
-        "throughput_req_s": st["completed"] / wall if wall > 0 else None,
-        "nominal_gflops": st["nominal_flops"] / wall / 1e9 if wall > 0 else None,
-        "offered_rate_req_s": args.rate,
-        "requests": st["completed"],
-        "wrong_or_failed": bad,
-        "statuses": {str(k): v for k, v in statuses.items()},
-        "peak_active": st["peak_active"],
-        "peak_bytes": st["peak_bytes"],
-        "budget_bytes": st["budget_bytes"],
-        "dtype": "f64 / f32+f64-refine",
-        "data": "synthetic",
-        "config": {"workload": f"Poisson {args.rate}/s for {args.duration} s, n log-uniform in "
-                               f"[{args.nmin}, {args.nmax}], 70% symmetric (half FP32+refine), 30% pencils",
-                   "pool": pool_size},
-    }
-    print(json.dumps(out))
+    for rate in [float(x) for x in str(args.rate).split(",")]:
+        arrivals = []
+        t = 0.0
+        while True:
+            t += rng.exponential(1.0 / rate)
+            if t > args.duration:
+                break
+            arrivals.append(t)
+        log(f"[serve] {len(arrivals)} arrivals over {args.duration} s at {rate}/s")
+        srv = P.Server(0, max_active=args.max_active)
+        tickets = []
+        t0 = time.perf_counter()
+        for i, ta in enumerate(arrivals):
+            dt = ta - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            q = pool[i % pool_size]
+            tickets.append((srv.submit(q["A"], q["B"], q["reg"], P.opts(prec=q["prec"], seed=1000 + i)), q, i))
+        queued_at_end = srv.stats()["pending"]
+        bad = 0
+        statuses = {}
+        sample = {}
+        for cnt, (tk, q, i) in enumerate(tickets):
+            r = srv.wait(tk)
+            if cnt % 50 == 49:
+                log(f"[serve] {cnt + 1} of {len(tickets)} done")
+            statuses[r.status] = statuses.get(r.status, 0) + 1
+            if r.status != 0 or r.info["k_lead"] != q["k"]:
+                bad += 1
+            if i < 4 or i == len(tickets) - 1:
+                sample[i] = r
+        st = srv.stats()
+        srv.close()
+        # the sampled requests alone, through the single-problem entry points
+        h = P.Handle(0)
+        same = True
+        for i, r in sample.items():
+            q = pool[i % pool_size]
+            o = P.opts(prec=q["prec"], seed=1000 + i)
+            a = h.split_sym(q["A"], q["reg"], o) if q["kind"] == "sym" else h.split_pencil(q["A"], q["B"], q["reg"], o)
+            same &= a.status == r.status and torch.equal(a.Q, r.Q) and torch.equal(a.Ahat, r.Ahat)
+        h.close()
+        wall = st["wall_ms"] / 1e3
+        out = {
+            "metric": "served split requests: p99 latency (submission to completion)",
+            "value": st["p99_ms"],
+            "unit": "ms",
+            "higher_is_better": False,
+            "n_gpus": 1,
+            "p50_ms": st["p50_ms"],
+            "mean_ms": st["mean_ms"],
+            "max_ms": st["max_ms"],
+            "throughput_req_s": st["completed"] / wall if wall > 0 else None,
+            "nominal_gflops": st["nominal_flops"] / wall / 1e9 if wall > 0 else None,
+            "offered_rate_req_s": rate,
+            "requests": st["completed"],
+            "queued_when_arrivals_ended": queued_at_end,
+            "wrong_or_failed": bad,
+            "statuses": {str(k): v for k, v in statuses.items()},
+            "sampled_results_equal_single_calls": bool(same),
+            "peak_active": st["peak_active"],
+            "max_active": args.max_active or 64,
+            "peak_bytes": st["peak_bytes"],
+            "budget_bytes": st["budget_bytes"],
+            "dtype": "f64 / f32+f64-refine",
+            "data": "synthetic",
+            "config": {"workload": f"Poisson {rate}/s for {args.duration} s, n log-uniform in "
+                                   f"[{args.nmin}, {args.nmax}], 70% symmetric (half FP32+refine), 30% pencils",
+                       "pool": pool_size},
+        }
+        print(json.dumps(out), flush=True)
 
 
 def suite_main(args):
@@ -408,8 +430,9 @@ def main():
     ap.add_argument("--serve", action="store_true", help="serving benchmark instead (see serve_main)")
     ap.add_argument("--suite", action="store_true",
                     help="the other measured configurations instead, one JSON line each (see suite_main)")
-    ap.add_argument("--rate", type=float, default=4.0, help="--serve: Poisson arrival rate, requests/s")
+    ap.add_argument("--rate", type=str, default="4", help="--serve: Poisson arrival rate(s), requests/s, comma-separated")
     ap.add_argument("--duration", type=float, default=15.0, help="--serve: seconds of arrivals")
+    ap.add_argument("--max-active", type=int, default=0, help="--serve: requests run at once (0: the server's default, 64)")
     ap.add_argument("--nmin", type=int, default=64)
     ap.add_argument("--nmax", type=int, default=2048)
     args = ap.parse_args()

@@ -437,7 +437,9 @@ sdc_status_t sdc_server_submit(sdc_server_t server, const sdc_request_t* req, lo
  * hold its result and the ticket is released.  SDC_ERR_INVALID for an unknown
  * or released ticket. */
 sdc_status_t sdc_server_poll(sdc_server_t server, long long ticket, int* done, int* status, sdc_info_t* info);
-/* Block until the request finished, then as sdc_server_poll with *done = 1. */
+/* Block until the request finished, then as sdc_server_poll with *done = 1.
+ * A ticket's result goes to one caller: a second thread waiting on the same
+ * ticket returns SDC_ERR_INVALID once the first has taken it. */
 sdc_status_t sdc_server_wait(sdc_server_t server, long long ticket, int* status, sdc_info_t* info);
 /* Latency percentiles, throughput counters, admission state. */
 sdc_status_t sdc_server_stats(sdc_server_t server, sdc_server_stats_t* out);

@@ -434,7 +434,7 @@ class Server:
         q, ah = _out(n, A), _out(n, A)
         ql = _out(n, A) if b is not None else None
         bh = _out(n, A) if b is not None else None
-        torch.cuda.synchronize(A.device)  # inputs complete before the worker reads them
+        torch.cuda.current_stream(A.device).synchronize()  # the input copies complete before the worker reads them
         r = Request()
         r.kind = SDC_REQ_PENCIL if b is not None else SDC_REQ_SYM
         r.n = n

@@ -30,7 +30,7 @@ struct Profiler {
     hipEvent_t next_event() {
         if (used == pool.size()) {
             hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
             pool.push_back(e);
         }
         return pool[used++];

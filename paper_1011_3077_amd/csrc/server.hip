@@ -262,6 +262,7 @@ static sdc_status_t take_result(sdc_server_s* s, long long ticket, int* status, 
     if (status) *status = it->second.status;
     if (info) *info = it->second.info;
     s->results.erase(it);
+    s->cv_done.notify_all();  // another waiter on this ticket now sees it released
     return SDC_OK;
 }
 
@@ -280,10 +281,13 @@ sdc_status_t sdc_server_wait(sdc_server_t s, long long ticket, int* status, sdc_
     std::unique_lock<std::mutex> lk(s->mu);
     auto it = s->results.find(ticket);
     if (it == s->results.end()) return SDC_ERR_INVALID;
+    // a second waiter on the same ticket wakes when the first takes the
+    // result and then reports the ticket as released
     s->cv_done.wait(lk, [&] {
         auto jt = s->results.find(ticket);
-        return jt != s->results.end() && jt->second.done;
+        return jt == s->results.end() || jt->second.done;
     });
+    if (s->results.find(ticket) == s->results.end()) return SDC_ERR_INVALID;
     return take_result(s, ticket, status, info);
 }
 

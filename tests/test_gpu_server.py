@@ -160,3 +160,30 @@ def test_server_poll_and_threads(handle, sdc):
         srv.close()
     for (a, d, q), r in zip(probs, res):
         assert r is not None and r.status == 0 and r.info["k_lead"] == int((d > 0).sum())
+
+
+def test_server_two_waiters_on_one_ticket(handle, sdc):
+    """Two threads wait on the same ticket: one receives the result, the
+    other returns SDC_ERR_INVALID instead of blocking."""
+    import ctypes as C
+    print("CASE server two waiters", flush=True)
+    a, d, q = S.sym_problem(90, S.family_seed(4, 91))
+    srv = sdc.Server(0)
+    try:
+        t = srv.submit(dev(a), None, sdc.region("halfplane", shift=0.0, scale=1.0), sdc.opts(seed=3))
+        out = [None, None]
+
+        def waiter(i):
+            st, info = C.c_int(), sdc.Info()
+            out[i] = sdc.lib.sdc_server_wait(srv._s, t, C.byref(st), C.byref(info))
+
+        th = [threading.Thread(target=waiter, args=(i,)) for i in range(2)]
+        for x in th:
+            x.start()
+        for x in th:
+            x.join(timeout=60)
+        assert not any(x.is_alive() for x in th)
+        assert sorted(out) == [sdc.SDC_ERR_INVALID, sdc.SDC_OK]
+        srv._live.pop(t, None)
+    finally:
+        srv.close()
