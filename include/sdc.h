@@ -97,6 +97,9 @@ typedef struct {
                             n x n Gaussian matrices, index [attempt*2 + side]
                             (side 0 right, 1 left); NULL -> Philox4x32-10 draws */
     int diagnostics;     /* nonzero: also compute info->orth_err (one more GEMM) */
+    int panel_width;     /* QR panel width, 32 or 64 columns; 0 -> the handle's table
+                            (sdc_tune_set / sdc_autotune), which chooses per problem from its
+                            own order, so a problem gives the same bits alone and in a batch */
 } sdc_opts_t;
 
 typedef struct {
@@ -374,6 +377,51 @@ sdc_status_t sdc_profile_read(sdc_handle_t h, int kernel, sdc_kernel_stats_t* ou
  * Philox4x32-10 keyed by `seed`, counter (e mod 2^32, e div 2^32, tag, 0) for
  * the column-major element index e, then Box-Muller.  G is a device pointer. */
 sdc_status_t sdc_gaussian(sdc_handle_t h, int n, uint64_t seed, int tag, double* G, int ldg);
+
+/* ------------------------------------------------------------------------
+ * Panel-width tuning of the repeated squaring's QR (the batched blocked
+ * Householder QR of Alg. 3, costed with the communication-avoiding QR of
+ * Sec. 4.2).  Panels are 32 or 64 columns wide; a problem with at least
+ * nb64_min factored columns takes 64-column panels (per precision of the
+ * iterates: FP64, and the FP32 iterates of SDC_FP32_REFINE).  The choice is
+ * per problem, from its own order, so a problem gives the same bits alone
+ * and in any batch on handles with the same table; opts->panel_width
+ * overrides it for one call.
+ * ---------------------------------------------------------------------- */
+#define SDC_PANEL64_NEVER (-1)
+
+/* Set the table: the smallest order that takes 64-column panels, for FP64
+ * and for FP32 iterates; SDC_PANEL64_NEVER (any negative value) for none.
+ * The default is SDC_PANEL64_NEVER for both (measured on MI355X: the
+ * 32-column panels are faster at every order up to 8192). */
+sdc_status_t sdc_tune_set(sdc_handle_t h, int nb64_min_fp64, int nb64_min_fp32);
+sdc_status_t sdc_tune_get(sdc_handle_t h, int* nb64_min_fp64, int* nb64_min_fp32);
+
+typedef struct {
+    int n;               /* order timed */
+    int prec;            /* SDC_FP64 or SDC_FP32_REFINE (FP32 iterates) */
+    double ms_nb32;      /* one repeated-squaring iteration, 32-column panels (best of reps) */
+    double ms_nb64;      /* the same with 64-column panels */
+} sdc_tune_result_t;
+
+/* Autotuner: for each of the `count` orders (1 .. 16384) and both iterate
+ * precisions, time one repeated-squaring iteration (Alg. 3: the QR of the
+ * stacked pair and the updates) of a Gaussian matrix with each panel width,
+ * best of `reps` (>= 1) runs, and set the table: per precision, the
+ * smallest timed order from which the 64-column panels win at every larger
+ * timed order (SDC_PANEL64_NEVER if they do not win at the largest).
+ * results (device-independent host memory, 2 * count entries, FP64 rows
+ * first) receives the timings, or may be NULL.  Allocates device memory
+ * for the test matrices (SDC_ERR_NOMEM if it cannot); results are
+ * undefined on error.  Minutes at orders of several thousand. */
+sdc_status_t sdc_autotune(sdc_handle_t h, const int* orders, int count, int reps, sdc_tune_result_t* results);
+
+/* Write the table as JSON to `path` ({"nb64_min_fp64": .., "nb64_min_fp32": ..,
+ * "arch": ..}), or read it back (keys missing from the file leave the table
+ * as it is).  SDC_ERR_INVALID if the file cannot be written, read or
+ * parsed. */
+sdc_status_t sdc_tune_save(sdc_handle_t h, const char* path);
+sdc_status_t sdc_tune_load(sdc_handle_t h, const char* path);
 
 /* ------------------------------------------------------------------------
  * Served form: a request loop with continuous batching.

@@ -31,7 +31,7 @@ EXPORTED = ["sdc_opts_default", "sdc_create", "sdc_destroy", "sdc_status_string"
             "sdc_split_sym", "sdc_split_sym_noalloc", "sdc_split_nonsym", "sdc_split_pencil", "sdc_split_sym_batched", "sdc_split_svd",
             "sdc_eig_dc",
             "sdc_block_eigvals", "sdc_trevc",
-            "sdc_gaussian",
+            "sdc_gaussian", "sdc_tune_set", "sdc_tune_get", "sdc_autotune", "sdc_tune_save", "sdc_tune_load",
             "sdc_profile_enable", "sdc_profile_read", "sdc_server_create", "sdc_server_submit",
             "sdc_server_poll", "sdc_server_wait", "sdc_server_stats", "sdc_server_destroy"]
 SDC_REQ_SYM, SDC_REQ_PENCIL = 0, 1
@@ -45,7 +45,7 @@ class Region(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("prec", C.c_int), ("tau", C.c_double), ("maxit", C.c_int), ("seed", C.c_uint64),
                 ("max_retries", C.c_int), ("split_tol", C.c_double), ("G", C.c_void_p),
-                ("diagnostics", C.c_int)]
+                ("diagnostics", C.c_int), ("panel_width", C.c_int)]
 
 
 class Info(C.Structure):
@@ -82,6 +82,14 @@ class KernelStats(C.Structure):
 
 
 KERNEL_UPDATE, KERNEL_PANEL, KERNEL_GEMM, KERNEL_LA = 0, 1, 2, 3
+SDC_PANEL64_NEVER = -1
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("n", C.c_int), ("prec", C.c_int), ("ms_nb32", C.c_double), ("ms_nb64", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class Request(C.Structure):
@@ -143,6 +151,16 @@ lib.sdc_profile_read.argtypes = [_P, _I, C.POINTER(KernelStats)]
 lib.sdc_profile_read.restype = _I
 lib.sdc_gaussian.argtypes = [_P, _I, C.c_uint64, _I, _P, _I]
 lib.sdc_gaussian.restype = _I
+lib.sdc_tune_set.argtypes = [_P, _I, _I]
+lib.sdc_tune_set.restype = _I
+lib.sdc_tune_get.argtypes = [_P, C.POINTER(_I), C.POINTER(_I)]
+lib.sdc_tune_get.restype = _I
+lib.sdc_autotune.argtypes = [_P, C.POINTER(_I), _I, _I, C.POINTER(TuneResult)]
+lib.sdc_autotune.restype = _I
+lib.sdc_tune_save.argtypes = [_P, C.c_char_p]
+lib.sdc_tune_save.restype = _I
+lib.sdc_tune_load.argtypes = [_P, C.c_char_p]
+lib.sdc_tune_load.restype = _I
 lib.sdc_server_create.argtypes = [C.POINTER(_P), _I, C.c_size_t, _I]
 lib.sdc_server_create.restype = _I
 lib.sdc_server_submit.argtypes = [_P, C.POINTER(Request), C.POINTER(C.c_longlong)]
@@ -178,11 +196,12 @@ def region(kind: str = "unit_disk", center: float = 0.0, radius: float = 1.0, sh
 
 
 def opts(prec: int = SDC_FP64, tau: float = 0.0, maxit: int = 60, seed: int = 0, max_retries: int = 2,
-         split_tol: float = 1e-10, G=None, diagnostics: int = 0) -> Opts:
+         split_tol: float = 1e-10, G=None, diagnostics: int = 0, panel_width: int = 0) -> Opts:
     o = Opts()
     lib.sdc_opts_default(C.byref(o))
     o.prec, o.tau, o.maxit, o.seed = prec, tau, maxit, seed
     o.max_retries, o.split_tol, o.diagnostics = max_retries, split_tol, diagnostics
+    o.panel_width = panel_width
     o.G = None if G is None else G.data_ptr()
     return o
 
@@ -399,6 +418,30 @@ class Handle:
         g = torch.empty((n, n), dtype=torch.float64, device=f"cuda:{self.device}")
         _check(lib.sdc_gaussian(self._h, n, seed, tag, g.data_ptr(), n))
         return g.t()
+
+    def tune_set(self, nb64_min_fp64: int, nb64_min_fp32: int):
+        _check(lib.sdc_tune_set(self._h, nb64_min_fp64, nb64_min_fp32))
+
+    def tune_get(self):
+        a, b = _I(), _I()
+        _check(lib.sdc_tune_get(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def autotune(self, orders, reps: int = 2, cache: str | None = None):
+        """sdc_autotune over `orders`; returns the timings (FP64 rows first)
+        and, with `cache`, writes the resulting table there as JSON."""
+        arr = (_I * len(orders))(*orders)
+        res = (TuneResult * (2 * len(orders)))()
+        _check(lib.sdc_autotune(self._h, arr, len(orders), reps, res))
+        if cache is not None:
+            _check(lib.sdc_tune_save(self._h, cache.encode()))
+        return [r.as_dict() for r in res]
+
+    def tune_save(self, path: str):
+        _check(lib.sdc_tune_save(self._h, path.encode()))
+
+    def tune_load(self, path: str):
+        _check(lib.sdc_tune_load(self._h, path.encode()))
 
 
 class Server:

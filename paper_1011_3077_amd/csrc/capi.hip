@@ -3,6 +3,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cstdio>
+#include <cstdlib>
+#include <string>
 #include <cmath>
 #include <mutex>
 #include <new>
@@ -101,6 +106,7 @@ void sdc_opts_default(sdc_opts_t* o) {
     o->split_tol = 1e-10;
     o->G = nullptr;
     o->diagnostics = 0;
+    o->panel_width = 0;
 }
 
 const char* sdc_status_string(int s) {
@@ -404,6 +410,129 @@ sdc_status_t sdc_gaussian(sdc_handle_t hd, int n, uint64_t seed, int tag, double
     Handle& h = hd->h;
     if (use_device(h) != SDC_OK) return SDC_ERR_DEVICE;
     return (sdc_status_t)sdc::run_gaussian(h, n, seed, tag, G, ldg);
+}
+
+// ---------------------------------------------------------------------------
+// Panel-width table and its autotuner
+// ---------------------------------------------------------------------------
+static int tune_to_api(int v) { return v >= sdc::kNb64Never ? SDC_PANEL64_NEVER : v; }
+static int tune_from_api(int v) { return v < 0 ? sdc::kNb64Never : v; }
+
+sdc_status_t sdc_tune_set(sdc_handle_t hd, int nb64_min_fp64, int nb64_min_fp32) {
+    if (!hd) return SDC_ERR_INVALID;
+    hd->h.nb64_min[0] = tune_from_api(nb64_min_fp64);
+    hd->h.nb64_min[1] = tune_from_api(nb64_min_fp32);
+    return SDC_OK;
+}
+
+sdc_status_t sdc_tune_get(sdc_handle_t hd, int* nb64_min_fp64, int* nb64_min_fp32) {
+    if (!hd || !nb64_min_fp64 || !nb64_min_fp32) return SDC_ERR_INVALID;
+    *nb64_min_fp64 = tune_to_api(hd->h.nb64_min[0]);
+    *nb64_min_fp32 = tune_to_api(hd->h.nb64_min[1]);
+    return SDC_OK;
+}
+
+sdc_status_t sdc_autotune(sdc_handle_t hd, const int* orders, int count, int reps, sdc_tune_result_t* results) {
+    if (!hd || !orders || count < 1 || reps < 1) return SDC_ERR_INVALID;
+    for (int i = 0; i < count; ++i)
+        if (orders[i] < 1 || orders[i] > kMaxN) return SDC_ERR_INVALID;
+    Handle& h = hd->h;
+    if (h.no_alloc) return SDC_ERR_INVALID;
+    if (use_device(h) != SDC_OK) return SDC_ERR_DEVICE;
+    const int nmax = *std::max_element(orders, orders + count);
+    const size_t nn = (size_t)nmax * nmax;
+    double* buf = nullptr;  // A, then A_p, B_p, R of the timed iteration
+    if (hipMalloc(reinterpret_cast<void**>(&buf), 4 * nn * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return SDC_ERR_NOMEM;
+    }
+    std::vector<sdc_tune_result_t> res;
+    int rc = SDC_OK;
+    for (int pi = 0; pi < 2 && rc == SDC_OK; ++pi) {
+        for (int i = 0; i < count && rc == SDC_OK; ++i) {
+            const int n = orders[i];
+            sdc_tune_result_t r{n, pi ? SDC_FP32_REFINE : SDC_FP64, INFINITY, INFINITY};
+            rc = sdc::run_gaussian(h, n, 0x5dc7u, 0, buf, n);
+            for (int w = 0; w < 2 && rc == SDC_OK; ++w) {
+                sdc_opts_t o;
+                sdc_opts_default(&o);
+                o.prec = r.prec;
+                o.maxit = 1;  // one iteration: the work of every later one
+                o.panel_width = w ? 64 : 32;
+                sdc_region_t reg{SDC_HALFPLANE, 0.0, 0.0, 0.0, 1.0};
+                for (int k = 0; k <= reps && rc == SDC_OK; ++k) {  // the first run warms up
+                    int p = 0;
+                    double rconv = 0.0;
+                    if (hipStreamSynchronize(h.stream) != hipSuccess) rc = SDC_ERR_DEVICE;
+                    const auto t0 = std::chrono::steady_clock::now();
+                    const int st = sdc::run_irs_only(h, n, buf, n, nullptr, 0, 0, reg, o, buf + nn, buf + 2 * nn,
+                                                     buf + 3 * nn, n, &p, &rconv);
+                    if (st < 0) rc = st;
+                    if (rc == SDC_OK && hipStreamSynchronize(h.stream) != hipSuccess) rc = SDC_ERR_DEVICE;
+                    const double ms =
+                        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                    if (k > 0) (w ? r.ms_nb64 : r.ms_nb32) = std::min(w ? r.ms_nb64 : r.ms_nb32, ms);
+                }
+            }
+            res.push_back(r);
+        }
+    }
+    (void)hipFree(buf);
+    if (rc != SDC_OK) return (sdc_status_t)rc;
+    // per precision: the smallest order from which 64 wins at every larger timed order
+    for (int pi = 0; pi < 2; ++pi) {
+        std::vector<sdc_tune_result_t> v(res.begin() + pi * count, res.begin() + (pi + 1) * count);
+        std::sort(v.begin(), v.end(), [](const sdc_tune_result_t& a, const sdc_tune_result_t& b) { return a.n < b.n; });
+        int lim = sdc::kNb64Never;
+        for (int i = (int)v.size() - 1; i >= 0 && v[i].ms_nb64 < v[i].ms_nb32; --i) lim = v[i].n;
+        h.nb64_min[pi] = lim;
+    }
+    if (results) std::copy(res.begin(), res.end(), results);
+    return SDC_OK;
+}
+
+sdc_status_t sdc_tune_save(sdc_handle_t hd, const char* path) {
+    if (!hd || !path) return SDC_ERR_INVALID;
+    hipDeviceProp_t prop{};
+    const bool have = hipGetDeviceProperties(&prop, hd->h.device) == hipSuccess;
+    FILE* f = std::fopen(path, "w");
+    if (!f) return SDC_ERR_INVALID;
+    const int ok = std::fprintf(f, "{\"nb64_min_fp64\": %d, \"nb64_min_fp32\": %d, \"arch\": \"%s\"}\n",
+                                tune_to_api(hd->h.nb64_min[0]), tune_to_api(hd->h.nb64_min[1]),
+                                have ? prop.gcnArchName : "unknown");
+    return (std::fclose(f) == 0 && ok > 0) ? SDC_OK : SDC_ERR_INVALID;
+}
+
+// Integer value of "key" in a small JSON object (found: 1, absent: 0, malformed: -1).
+static int json_int(const std::string& text, const char* key, int* out) {
+    const std::string k = std::string("\"") + key + "\"";
+    const size_t at = text.find(k);
+    if (at == std::string::npos) return 0;
+    size_t i = text.find(':', at + k.size());
+    if (i == std::string::npos) return -1;
+    const char* b = text.c_str() + i + 1;
+    char* e = nullptr;
+    const long v = std::strtol(b, &e, 10);
+    if (e == b || v < INT_MIN || v > INT_MAX) return -1;
+    *out = (int)v;
+    return 1;
+}
+
+sdc_status_t sdc_tune_load(sdc_handle_t hd, const char* path) {
+    if (!hd || !path) return SDC_ERR_INVALID;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return SDC_ERR_INVALID;
+    std::string text;
+    char chunk[512];
+    size_t got;
+    while ((got = std::fread(chunk, 1, sizeof chunk, f)) > 0 && text.size() < (1u << 16)) text.append(chunk, got);
+    std::fclose(f);
+    int v64 = 0, v32 = 0;
+    const int a = json_int(text, "nb64_min_fp64", &v64), b = json_int(text, "nb64_min_fp32", &v32);
+    if (a < 0 || b < 0 || text.find('{') == std::string::npos) return SDC_ERR_INVALID;
+    if (a > 0) hd->h.nb64_min[0] = tune_from_api(v64);
+    if (b > 0) hd->h.nb64_min[1] = tune_from_api(v32);
+    return SDC_OK;
 }
 
 sdc_status_t sdc_split_svd(sdc_handle_t hd, int m, int n, const double* A, int lda, sdc_region_t region,

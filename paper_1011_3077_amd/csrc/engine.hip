@@ -51,6 +51,7 @@ template <typename T> struct IrsSide {
     int maxit = 60;
     T* W = nullptr; double* Rprev = nullptr; T* diag = nullptr; double* norms = nullptr;
     T* Tm = nullptr; unsigned* counters = nullptr;
+    int nb = 32;  // QR panel width of this side (panel_width)
     int p = 0, converged = 0, nonfinite = 0;
     int started = 0, done = 0;
     double rconv = NAN;
@@ -67,22 +68,28 @@ template <typename T> static void irs_layout(Carver& c, IrsSide<T>& s) {
     s.counters = c.take<unsigned>(kMaxInternal);
 }
 
-// aux holds 2 * qr_aux_elems<T>(m) elements (one set per panel parity).
-template <typename T> static QrDesc<T> qr_desc(T* W, int ld, int m, int nf, int ncols, T* aux, T* diag,
-                                               unsigned* counters) {
-    using C = QrCfg<T>;
-    const auto g = tree_geom<T>(m);
+// aux holds 2 * qr_aux_elems<T>(m) elements (one set per panel parity, at
+// the same offsets for either panel width).
+template <typename T, int NBW> static void qr_desc_aux(QrDesc<T>& d, int m, T* aux) {
+    using C = QrCfg<T, NBW>;
+    const auto g = tree_geom<T, NBW>(m);
     size_t internal = 0;
     for (int l = 1; l < g.levels; ++l) internal += (size_t)g.L(l);
     const size_t tm = ((size_t)g.L(0) + internal) * C::NB * C::NB;
     const size_t per = qr_aux_elems<T>(m);
-    QrDesc<T> d;
-    d.W = W; d.ld = ld; d.m = m; d.nf = nf; d.ncols = ncols;
     for (int p = 0; p < 2; ++p) {
         d.Tm[p] = aux + p * per;
         d.Vint[p] = aux + p * per + tm;
     }
     d.tm_leaves = g.L(0);
+}
+template <typename T> static QrDesc<T> qr_desc(T* W, int ld, int m, int nf, int ncols, T* aux, T* diag,
+                                               unsigned* counters, int nb) {
+    QrDesc<T> d;
+    d.W = W; d.ld = ld; d.m = m; d.nf = nf; d.ncols = ncols;
+    d.nb = nb == 64 ? 64 : 32;
+    if (d.nb == 64) qr_desc_aux<T, 64>(d, m, aux);
+    else qr_desc_aux<T, 32>(d, m, aux);
     d.diag = diag; d.counters = counters; d.active = 1;
     return d;
 }
@@ -96,6 +103,21 @@ template <typename T> static const QrStreams* lookahead(Handle& h, const std::ve
     for (const QrDesc<T>& d : q)
         if (d.active) nf = std::max(nf, d.nf);
     return nf >= kLookaheadMinN ? &h.qs : nullptr;
+}
+
+// The QRs of a batch, one batched call per panel width (32 first): every
+// problem is factored by the kernels of its own width, whatever else is in
+// the batch, so it rounds the same alone and in any batch.
+template <typename T> static int run_qr_grouped(Handle& h, const std::vector<QrDesc<T>>& qd) {
+    for (int nb : {32, 64}) {
+        std::vector<QrDesc<T>> g;
+        for (const QrDesc<T>& d : qd)
+            if (d.nb == nb) g.push_back(d);
+        if (g.empty()) continue;
+        UPLOAD(dg, g);
+        qr_aug_batch<T>(dg, g.data(), (int)g.size(), h.stream, lookahead(h, g));
+    }
+    return SDC_OK;
 }
 
 // Set-up of the sides not started yet: W <- [B0 A0 0; -A0 0 B0] from the
@@ -136,15 +158,14 @@ template <typename T> static int irs_tick(Handle& h, std::vector<IrsSide<T>*>& s
     for (int i = 0; i < cnt; ++i) {
         IrsSide<T>& s = *act[i];
         s.norms = h.dnorm + 4 * i;
-        qd[i] = qr_desc<T>(s.W, s.ld, 2 * s.n, s.n, 3 * s.n, s.Tm, s.diag, s.counters);
+        qd[i] = qr_desc<T>(s.W, s.ld, 2 * s.n, s.n, 3 * s.n, s.Tm, s.diag, s.counters, s.nb);
         pd[i] = IrsDesc<T>{s.W, s.n, s.ld, s.Rprev, s.diag, s.norms, 1};
     }
     const size_t mark = h.desc_off;
-    UPLOAD(dq, qd);
     UPLOAD(dp, pd);
     fill<double>(h.dnorm, 4 * (size_t)cnt, 0.0, h.stream);
     CHK(ensure_streams(h));
-    qr_aug_batch<T>(dq, qd.data(), cnt, h.stream, lookahead(h, qd));
+    CHK(run_qr_grouped<T>(h, qd));
     irs_post_batch<T>(dp, pd.data(), cnt, 0, h.stream);
     HIPCHK(hipGetLastError());
     double* hn = reinterpret_cast<double*>(h.host);
@@ -238,6 +259,7 @@ struct JobWs {
     double* qaux = nullptr;
     double* dg[4] = {nullptr, nullptr, nullptr, nullptr};
     unsigned* qcnt = nullptr;
+    int qnb = 32;  // panel width of the GRURV / rank-revealing QRs (FP64, n columns)
     double *SA = nullptr, *SB = nullptr, *e = nullptr, *out = nullptr, *nrm = nullptr, *orth = nullptr;
     double* cg = nullptr;  // CG partial sums of the FP64 refinement (5 x kCgMaxBlocks)
     std::vector<double> rho_r, rho_l;
@@ -247,13 +269,16 @@ struct JobWs {
     double tau = 0;
 };
 
-static void job_layout(Carver& c, JobWs& w) {
+static void job_layout(Carver& c, JobWs& w, const Handle* h) {
     const SplitJob& j = *w.job;
     const size_t n = (size_t)j.n;
     const int nsides = j.pencil ? 2 : 1;
+    w.qnb = panel_width(h, j.n, false, j.opts.panel_width);
     for (int s = 0; s < nsides; ++s) {
         w.sf[s].n = j.n;
         w.sd[s].n = j.n;
+        w.sf[s].nb = panel_width(h, j.n, true, j.opts.panel_width);
+        w.sd[s].nb = panel_width(h, j.n, false, j.opts.panel_width);
         if (w.fp32) {
             irs_layout(c, w.sf[s]);
             w.Apd[s] = c.take<double>(n * n);
@@ -334,13 +359,11 @@ static int run_qr(Handle& h, std::vector<JobWs*>& js, int dgi) {
     std::vector<QrDesc<double>> q;
     for (JobWs* w : js) {
         const int n = w->job->n;
-        q.push_back(qr_desc<double>(w->X, n, n, n, 2 * n, w->qaux, w->dg[dgi], w->qcnt));
+        q.push_back(qr_desc<double>(w->X, n, n, n, 2 * n, w->qaux, w->dg[dgi], w->qcnt, w->qnb));
     }
     if (q.empty()) return SDC_OK;
-    UPLOAD(d, q);
     CHK(ensure_streams(h));
-    qr_aug_batch<double>(d, q.data(), (int)q.size(), h.stream, lookahead(h, q));
-    return SDC_OK;
+    return run_qr_grouped<double>(h, q);
 }
 
 // X[:, 0:n] <- the Gaussian of (attempt, side); X[:, n:2n] <- I.
@@ -935,7 +958,7 @@ int run_split_jobs(Handle& h, std::vector<SplitJob>& jobs) {
     }
     // workspace: size pass, then carve
     auto layout = [&](Carver& c) {
-        for (JobWs& w : ws) job_layout(c, w);
+        for (JobWs& w : ws) job_layout(c, w, &h);
     };
     {
         Carver c0(nullptr);
@@ -1148,18 +1171,18 @@ size_t job_run_bytes(const SplitJob& j0) {
     w.job = &j;
     w.fp32 = j.opts.prec == SDC_FP32_REFINE;
     Carver c(nullptr);
-    job_layout(c, w);
+    job_layout(c, w, nullptr);  // the size does not depend on the panel widths
     return c.off + 256;
 }
 
-JobRun* job_run_create(SplitJob* j, char* ws, size_t bytes) {
+JobRun* job_run_create(const Handle& h, SplitJob* j, char* ws, size_t bytes) {
     fill_defaults(j->opts);
     JobRun* r = new (std::nothrow) JobRun;
     if (!r) return nullptr;
     r->w.job = j;
     r->w.fp32 = j->opts.prec == SDC_FP32_REFINE;
     Carver c(ws, bytes);
-    job_layout(c, r->w);
+    job_layout(c, r->w, &h);
     if (c.overflow) {
         delete r;
         return nullptr;
@@ -1222,6 +1245,8 @@ int run_irs_only(Handle& h, int n, const double* A, int lda, const double* B, in
     };
     sdd.n = n;
     sff.n = n;
+    sdd.nb = panel_width(&h, n, false, opts.panel_width);
+    sff.nb = panel_width(&h, n, true, opts.panel_width);
     auto layout = [&](Carver& c) {
         if (fp32) irs_layout(c, sff);
         else irs_layout(c, sdd);

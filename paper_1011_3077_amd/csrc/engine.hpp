@@ -13,6 +13,17 @@
 
 namespace sdc {
 
+// Default panel-width table (the smallest number of factored columns that
+// takes 64-column panels; kNb64Never: none).  Measured on one MI355X, the
+// 64-column panels lose at every order up to 8192 in both precisions: the
+// fan-in of their reduction tree drops from 8 to 4, which adds a third more
+// rows to the trailing update (a seventh with 32-column panels), and their
+// panel and look-ahead kernels each take a CU's whole LDS beside the bulk
+// update.  sdc_autotune measures the choice for the device at hand.
+constexpr int kNb64Never = 1 << 30;
+constexpr int kNb64MinFp64 = kNb64Never;
+constexpr int kNb64MinFp32 = kNb64Never;
+
 struct Handle {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -52,7 +63,21 @@ struct Handle {
     // every buffer above was handed in from preallocated memory: the
     // ensure_* helpers report SDC_ERR_NOMEM instead of allocating
     bool no_alloc = false;
+    // QR panel width table: problems with at least nb64_min[p] factored
+    // columns use 64-column panels ([0] FP64 iterates, [1] FP32 iterates);
+    // set by sdc_tune_set / sdc_autotune
+    int nb64_min[2] = {kNb64MinFp64, kNb64MinFp32};
 };
+
+// Panel width (32 or 64) of a QR with nf factored columns: `forced` (the
+// caller's opts.panel_width) if it is 32 or 64, else the handle's table
+// (the defaults without a handle).  It depends on the problem alone, never
+// on the rest of a batch.
+inline int panel_width(const Handle* h, int nf, bool fp32, int forced) {
+    if (forced == 32 || forced == 64) return forced;
+    const int lim = h ? h->nb64_min[fp32 ? 1 : 0] : (fp32 ? kNb64MinFp32 : kNb64MinFp64);
+    return nf >= lim ? 64 : 32;
+}
 
 // Installs the handle's profiler (if enabled) for the lifetime of a call.
 struct ProfScope {
@@ -125,7 +150,7 @@ int run_block_eigvals(Handle& h, int n, const double* T, int ldt, const double* 
 // other runs share its ticks.
 struct JobRun;
 size_t job_run_bytes(const SplitJob& j);
-JobRun* job_run_create(SplitJob* j, char* ws, size_t bytes);
+JobRun* job_run_create(const Handle& h, SplitJob* j, char* ws, size_t bytes);
 void job_run_destroy(JobRun* r);
 int job_runs_tick(Handle& h, std::vector<JobRun*>& runs, std::vector<char>& done);
 

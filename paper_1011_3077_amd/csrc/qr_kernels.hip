@@ -166,8 +166,8 @@ template <typename T> __device__ __forceinline__ T wave_sum8(const T (&q)[8], in
 // the w_l it already has, leaves it in LDS, and the owner of column j
 // finishes that column after the next barrier.
 // ---------------------------------------------------------------------------
-template <typename T, int NRW, int CC>
-__device__ __forceinline__ void qr_publish(const T (&a)[NRW][8], int jn, T* xs, T* sc) {
+template <typename T, int NRW, int CW, int CC>
+__device__ __forceinline__ void qr_publish(const T (&a)[NRW][CW], int jn, T* xs, T* sc) {
     const int l = threadIdx.x & 63;
     T nsq = 0;
 #pragma unroll
@@ -185,18 +185,20 @@ __device__ __forceinline__ void qr_publish(const T (&a)[NRW][8], int jn, T* xs, 
     }
 }
 
-// T column j of the node from the waves' partial sums p[4][32] (lanes i < NB).
-template <typename T>
+// T column j of the node from the waves' partial sums p[4][NB] (lanes i < NB).
+template <typename T, int NB>
 __device__ __forceinline__ T qr_tcol(const T* p, int j, T tauj) {
-    const int i = threadIdx.x & 31, l = threadIdx.x & 63;
-    const T s = (p[i] + p[32 + i]) + (p[64 + i] + p[96 + i]);
+    const int i = threadIdx.x & (NB - 1), l = threadIdx.x & 63;
+    const T s = (p[i] + p[NB + i]) + (p[2 * NB + i] + p[3 * NB + i]);
     return l < j ? -tauj * s : (l == j ? tauj : T(0));
 }
 
-template <typename T, int NRW, int JJ>
-__device__ __forceinline__ bool qr_step(T (&a)[NRW][8], T (&tc)[8], T& tau_prev, int jw, int nbk, T* s_x, T* s_sc,
+// One column step; CW = NB / 4 columns per wave (8 or 16).
+template <typename T, int NRW, int CW, int JJ>
+__device__ __forceinline__ bool qr_step(T (&a)[NRW][CW], T (&tc)[CW], T& tau_prev, int jw, int nbk, T* s_x, T* s_sc,
                                         T* s_P, T* s_tau, T* s_beta) {
-    const int j = 8 * jw + JJ;
+    constexpr int NB = 4 * CW;
+    const int j = CW * jw + JJ;
     if (j >= nbk) return false;
     const int tid = threadIdx.x, l = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: scalar branches below
@@ -210,8 +212,8 @@ __device__ __forceinline__ bool qr_step(T (&a)[NRW][8], T (&tc)[8], T& tau_prev,
         const T x = xs[r];
         xh[i] = r > j ? x : T(0);
     }
-    // finish T column j - 1 (its owner, register (JJ + 7) % 8)
-    if (j > 0 && wv == ((j - 1) >> 3)) tc[(JJ + 7) & 7] = qr_tcol(s_P + (par ^ 1) * 128, j - 1, tau_prev);
+    // finish T column j - 1 (its owner, register (JJ + CW - 1) % CW)
+    if (j > 0 && wv == (j - 1) / CW) tc[(JJ + CW - 1) % CW] = qr_tcol<T, NB>(s_P + (par ^ 1) * 4 * NB, j - 1, tau_prev);
     // reflector scalars, without branches (the zero-norm case selected at the end)
     const T nrm = sqrt(alpha * alpha + xn2);
     const T b0 = alpha >= T(0) ? -nrm : nrm;
@@ -225,9 +227,9 @@ __device__ __forceinline__ bool qr_step(T (&a)[NRW][8], T (&tc)[8], T& tau_prev,
     const T dd = zero ? T(0) : d0;
     // products over the rows below the diagonal, then row j's term (row j < 64:
     // register 0 of lane j) once d is known
-    T q[8];
+    T q[CW];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
+    for (int c = 0; c < CW; ++c) {
         T s = xh[0] * a[0][c];
 #pragma unroll
         for (int i = 1; i < NRW; ++i) s = fma(xh[i], a[i][c], s);
@@ -236,19 +238,25 @@ __device__ __forceinline__ bool qr_step(T (&a)[NRW][8], T (&tc)[8], T& tau_prev,
     const bool rowj = l == j;
     const T dj = rowj ? dd : T(0);
 #pragma unroll
-    for (int c = 0; c < 8; ++c) q[c] = fma(dj, a[0][c], q[c]);
+    for (int c = 0; c < CW; ++c) q[c] = fma(dj, a[0][c], q[c]);
     xh[0] = rowj ? dd : xh[0];
-    const T f = wave_sum8(q, l);
-    // S_c (wave-uniform); w_c = scale S_c
-    T sc8[8];
+    // S_c (wave-uniform), eight columns per wave sum; w_c = scale S_c
+    T sc8[CW];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) sc8[c] = lane_read(f, 2 * c);
+    for (int h = 0; h < CW / 8; ++h) {
+        T q8[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) q8[c] = q[8 * h + c];
+        const T f = wave_sum8(q8, l);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) sc8[8 * h + c] = lane_read(f, 2 * c);
+    }
     // this wave's share of T column j, scale sum_c T[i][c] S_c (tc is zero
     // for columns >= j)
     T pj = tc[0] * sc8[0];
 #pragma unroll
-    for (int c = 1; c < 8; ++c) pj = fma(tc[c], sc8[c], pj);
-    if (l < 32) s_P[par * 128 + wv * 32 + l] = scale * pj;
+    for (int c = 1; c < CW; ++c) pj = fma(tc[c], sc8[c], pj);
+    if (l < NB) s_P[par * 4 * NB + wv * NB + l] = scale * pj;
     // a_c <- a_c - (tau w_c / d) xh = a_c - S_c (tau scale^2 xh) for the
     // columns after j: all of a later wave's, those after JJ in j's own wave
     const T g = tau * scale * scale;
@@ -259,7 +267,7 @@ __device__ __forceinline__ bool qr_step(T (&a)[NRW][8], T (&tc)[8], T& tau_prev,
     // copies would cost more than the products they skip)
     const bool later = wv > jw, own = wv == jw;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
+    for (int c = 0; c < CW; ++c) {
         const T cf = (later || (own && c > JJ)) ? sc8[c] : T(0);
 #pragma unroll
         for (int i = 0; i < NRW; ++i) a[i][c] = fma(-cf, u[i], a[i][c]);
@@ -276,49 +284,53 @@ __device__ __forceinline__ bool qr_step(T (&a)[NRW][8], T (&tc)[8], T& tau_prev,
     }
     tau_prev = tau;
     if (j + 1 < nbk) {
-        if (wv == (j + 1) >> 3)
-            qr_publish<T, NRW, (JJ + 1) & 7>(a, j + 1, s_x + ((j + 1) & 1) * 256, s_sc + ((j + 1) & 1) * 2);
+        if (wv == (j + 1) / CW)
+            qr_publish<T, NRW, CW, (JJ + 1) % CW>(a, j + 1, s_x + ((j + 1) & 1) * 256, s_sc + ((j + 1) & 1) * 2);
         __syncthreads();
     }
     return true;
 }
 
-// Factor the node; T (NB x NB, column-major) goes to Tg.  s_P holds 256
-// elements of scratch.
-template <typename T, int NRW>
-__device__ __forceinline__ void node_qr_rows(T (&a)[NRW][8], int nbk, T* s_x, T* s_sc, T* s_P, T* s_tau, T* s_beta,
-                                             T* Tg) {
-    constexpr int NB = QrCfg<T>::NB;
-    static_assert(NB == 32 && QrCfg<T>::PT == 256, "four waves of eight columns");
-    const int tid = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
-    T tc[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) tc[c] = 0;
-    T tau_prev = 0;
-    if (tid < 64) qr_publish<T, NRW, 0>(a, 0, s_x, s_sc);
-    __syncthreads();
-    for (int jw = 0; jw < 4; ++jw) {
-        if (!qr_step<T, NRW, 0>(a, tc, tau_prev, jw, nbk, s_x, s_sc, s_P, s_tau, s_beta)) break;
-        if (!qr_step<T, NRW, 1>(a, tc, tau_prev, jw, nbk, s_x, s_sc, s_P, s_tau, s_beta)) break;
-        if (!qr_step<T, NRW, 2>(a, tc, tau_prev, jw, nbk, s_x, s_sc, s_P, s_tau, s_beta)) break;
-        if (!qr_step<T, NRW, 3>(a, tc, tau_prev, jw, nbk, s_x, s_sc, s_P, s_tau, s_beta)) break;
-        if (!qr_step<T, NRW, 4>(a, tc, tau_prev, jw, nbk, s_x, s_sc, s_P, s_tau, s_beta)) break;
-        if (!qr_step<T, NRW, 5>(a, tc, tau_prev, jw, nbk, s_x, s_sc, s_P, s_tau, s_beta)) break;
-        if (!qr_step<T, NRW, 6>(a, tc, tau_prev, jw, nbk, s_x, s_sc, s_P, s_tau, s_beta)) break;
-        if (!qr_step<T, NRW, 7>(a, tc, tau_prev, jw, nbk, s_x, s_sc, s_P, s_tau, s_beta)) break;
+// The CW column steps of wave-block jw, JJ = J0 .. CW - 1 (false once past nbk).
+template <typename T, int NRW, int CW, int J0>
+__device__ __forceinline__ bool qr_steps(T (&a)[NRW][CW], T (&tc)[CW], T& tau_prev, int jw, int nbk, T* s_x,
+                                         T* s_sc, T* s_P, T* s_tau, T* s_beta) {
+    if constexpr (J0 >= CW) {
+        return true;
+    } else {
+        if (!qr_step<T, NRW, CW, J0>(a, tc, tau_prev, jw, nbk, s_x, s_sc, s_P, s_tau, s_beta)) return false;
+        return qr_steps<T, NRW, CW, J0 + 1>(a, tc, tau_prev, jw, nbk, s_x, s_sc, s_P, s_tau, s_beta);
     }
+}
+
+// Factor the node; T (NB x NB, column-major) goes to Tg.  s_P holds 8 NB
+// elements of scratch.
+template <typename T, int NRW, int CW>
+__device__ __forceinline__ void node_qr_rows(T (&a)[NRW][CW], int nbk, T* s_x, T* s_sc, T* s_P, T* s_tau, T* s_beta,
+                                             T* Tg) {
+    constexpr int NB = 4 * CW;
+    static_assert(QrCfg<T, NB>::PT == 256, "four waves of NB / 4 columns");
+    const int tid = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
+    T tc[CW];
+#pragma unroll
+    for (int c = 0; c < CW; ++c) tc[c] = 0;
+    T tau_prev = 0;
+    if (tid < 64) qr_publish<T, NRW, CW, 0>(a, 0, s_x, s_sc);
+    __syncthreads();
+    for (int jw = 0; jw < 4; ++jw)
+        if (!qr_steps<T, NRW, CW, 0>(a, tc, tau_prev, jw, nbk, s_x, s_sc, s_P, s_tau, s_beta)) break;
     __syncthreads();
     // last column of T
     const int jl = nbk - 1;
-    if (wv == (jl >> 3)) {
-        const T t = qr_tcol(s_P + (jl & 1) * 128, jl, tau_prev);
+    if (wv == jl / CW) {
+        const T t = qr_tcol<T, NB>(s_P + (jl & 1) * 4 * NB, jl, tau_prev);
 #pragma unroll
-        for (int c = 0; c < 8; ++c) tc[c] = c == (jl & 7) ? t : tc[c];
+        for (int c = 0; c < CW; ++c) tc[c] = c == (jl % CW) ? t : tc[c];
     }
     if (l < NB) {
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const int col = 8 * wv + c;
+        for (int c = 0; c < CW; ++c) {
+            const int col = CW * wv + c;
             Tg[col * NB + l] = (l <= col && col < nbk) ? tc[c] : T(0);
         }
     }
@@ -328,39 +340,39 @@ __device__ __forceinline__ void node_qr_rows(T (&a)[NRW][8], int nbk, T* s_x, T*
 // NRW register rows per lane (64 NRW >= mt): load, QR, write T (NB x NB,
 // column-major) to Tg, and put R/V back into s_tile.  The start of s_tile
 // serves as scratch while the node is in registers.
-template <typename T, int NRW>
+template <typename T, int NRW, int NB>
 __device__ __forceinline__ void factor_tile_rows(T* s_tile, int mt, int nbk, T* s_x, T* s_sc, T* s_tau, T* s_beta,
                                                  T* Tg) {
-    constexpr int LDT = QrCfg<T>::MT_MAX + 1;
+    constexpr int LDT = QrCfg<T, NB>::MT_MAX + 1, CW = NB / 4;
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
-    T a[NRW][8];
+    T a[NRW][CW];
 #pragma unroll
     for (int i = 0; i < NRW; ++i)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
+        for (int c = 0; c < CW; ++c) {
             const int r = l + 64 * i;
-            a[i][c] = r < mt ? s_tile[(8 * wv + c) * LDT + r] : T(0);
+            a[i][c] = r < mt ? s_tile[(CW * wv + c) * LDT + r] : T(0);
         }
     __syncthreads();
-    node_qr_rows<T, NRW>(a, nbk, s_x, s_sc, s_tile, s_tau, s_beta, Tg);
+    node_qr_rows<T, NRW, CW>(a, nbk, s_x, s_sc, s_tile, s_tau, s_beta, Tg);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NRW; ++i)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) s_tile[(8 * wv + c) * LDT + l + 64 * i] = a[i][c];
+        for (int c = 0; c < CW; ++c) s_tile[(CW * wv + c) * LDT + l + 64 * i] = a[i][c];
     __syncthreads();
 }
 
-template <typename T>
+template <typename T, int NB>
 __device__ __forceinline__ void factor_node(T* s_tile, int mt, int nbk, T* s_x, T* s_sc, T* s_tau, T* s_beta, T* Tg) {
-    if (mt <= 64) factor_tile_rows<T, 1>(s_tile, mt, nbk, s_x, s_sc, s_tau, s_beta, Tg);
-    else if (mt <= 128) factor_tile_rows<T, 2>(s_tile, mt, nbk, s_x, s_sc, s_tau, s_beta, Tg);
-    else factor_tile_rows<T, 4>(s_tile, mt, nbk, s_x, s_sc, s_tau, s_beta, Tg);
+    if (mt <= 64) factor_tile_rows<T, 1, NB>(s_tile, mt, nbk, s_x, s_sc, s_tau, s_beta, Tg);
+    else if (mt <= 128) factor_tile_rows<T, 2, NB>(s_tile, mt, nbk, s_x, s_sc, s_tau, s_beta, Tg);
+    else factor_tile_rows<T, 4, NB>(s_tile, mt, nbk, s_x, s_sc, s_tau, s_beta, Tg);
 }
 
-template <typename T>
-__global__ __launch_bounds__(QrCfg<T>::PT) void k_panel(const QrDesc<T>* __restrict__ descs, int c0) {
-    using C = QrCfg<T>;
+template <typename T, int NBW>
+__global__ __launch_bounds__(256) void k_panel(const QrDesc<T>* __restrict__ descs, int c0) {
+    using C = QrCfg<T, NBW>;
     constexpr int NB = C::NB, LDT = C::MT_MAX + 1, PT = C::PT;
     __shared__ T s_tile[LDT * NB];
     __shared__ T s_x[2 * C::MT_MAX];  // published column, two steps in flight
@@ -372,7 +384,7 @@ __global__ __launch_bounds__(QrCfg<T>::PT) void k_panel(const QrDesc<T>* __restr
     if (!d.active || c0 >= d.nf) return;
     const int nbk = min(NB, d.nf - c0);
     const int mp = d.m - c0;
-    const auto g = tree_geom<T>(mp);
+    const auto g = tree_geom<T, NBW>(mp);
     int node = blockIdx.x;
     if (node >= g.L(0)) return;
     const int par = (c0 / NB) & 1;
@@ -400,7 +412,7 @@ __global__ __launch_bounds__(QrCfg<T>::PT) void k_panel(const QrDesc<T>* __restr
 #pragma unroll
         for (int col = 0; col < NB; ++col) s_tile[col * LDT + tid] = v[col];
         __syncthreads();
-        factor_node<T>(s_tile, mt, nbk, s_x, s_sc, s_tau, s_beta,
+        factor_node<T, NBW>(s_tile, mt, nbk, s_x, s_sc, s_tau, s_beta,
                        Tm + (size_t)node_index(g, 0, node, d.tm_leaves) * NB * NB);
 #pragma unroll
         for (int col = 0; col < NB; ++col) bw.store(s_tile[col * LDT + tid], vo + (unsigned)(col * ld * sizeof(T)));
@@ -439,7 +451,7 @@ __global__ __launch_bounds__(QrCfg<T>::PT) void k_panel(const QrDesc<T>* __restr
             for (int col = 0; col < NB; ++col) s_tile[col * LDT + s] = v[col];
         }
         __syncthreads();
-        factor_node<T>(s_tile, mt, nbk, s_x, s_sc, s_tau, s_beta,
+        factor_node<T, NBW>(s_tile, mt, nbk, s_x, s_sc, s_tau, s_beta,
                        Tm + (size_t)node_index(g, level, node, d.tm_leaves) * NB * NB);
         // explicit reflectors of this node, and its R into the top rows
         const RawBuf<T> bvi((par ? d.Vint[1] : d.Vint[0]) + (size_t)iidx * C::MT_MAX * NB,
@@ -478,7 +490,7 @@ __global__ __launch_bounds__(QrCfg<T>::PT) void k_panel(const QrDesc<T>* __restr
 constexpr int kUpdGroup = 2;
 template <typename T, int RB>
 __global__ __launch_bounds__(256, 2) void k_update(const QrDesc<T>* __restrict__ descs, int c0, int level) {
-    using C = QrCfg<T>;
+    using C = QrCfg<T, 32>;
     using M = Mfma<T>;
     typedef typename M::v4 v4;
     constexpr int NB = C::NB, VS = NB + 1, XS = 17;  // odd strides: conflict-free LDS access
@@ -496,7 +508,7 @@ __global__ __launch_bounds__(256, 2) void k_update(const QrDesc<T>* __restrict__
     if (col0 >= ce) return;
     const int par = (c0 / NB) & 1;
     const int mp = d.m - c0;
-    const auto g = tree_geom<T>(mp);
+    const auto g = tree_geom<T, 32>(mp);
     if (level >= g.levels) return;
     const int node = blockIdx.x;
     if (node >= g.L(level)) return;
@@ -679,6 +691,192 @@ __global__ __launch_bounds__(256, 2) void k_update(const QrDesc<T>* __restrict__
     }
 }
 
+// The trailing update for 64-column panels (twice the flops per byte of
+// the trailing matrix: above the FP64 machine balance, so the matrix cores
+// bound it).  Same layouts as k_update; the 64 reflector columns go through
+// LDS 32 at a time, so that two workgroups still fit a CU:
+//   stage V[:, 32:64], W_b = V_b^T C;  stage V[:, 0:32], W_a = V_a^T C;
+//   Y = T^T W (T upper triangular: the blocks below its diagonal skipped);
+//   C^T -= Y_a^T V_a^T;  stage V[:, 32:64] again, C^T -= Y_b^T V_b^T, store.
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_update64(const QrDesc<T>* __restrict__ descs, int c0, int level) {
+    using C = QrCfg<T, 64>;
+    using M = Mfma<T>;
+    typedef typename M::v4 v4;
+    constexpr int NB = C::NB, RB = C::MT_MAX / 16, VS = 33, XS = 17, NKB = NB / 16;
+    __shared__ T s_V[C::MT_MAX * VS];
+    __shared__ T s_X[4 * 16 * XS];
+    __shared__ int s_rb[C::F];
+
+    const QrDesc<T> d = descs[blockIdx.z];
+    if (!d.active || c0 >= d.nf) return;
+    const int nbk = min(NB, d.nf - c0);
+    const int cb = c0 + nbk + row_split_cols(NB, d.nf, c0);
+    const int ce = d.ncols;
+    const int col0 = cb + blockIdx.y * 64;
+    if (col0 >= ce) return;
+    const int par = (c0 / NB) & 1;
+    const int mp = d.m - c0;
+    const auto g = tree_geom<T, NB>(mp);
+    if (level >= g.levels) return;
+    const int node = blockIdx.x;
+    if (node >= g.L(level)) return;
+    const int tid = threadIdx.x;
+    const size_t ld = (size_t)d.ld;
+    T* W = d.W;
+
+    int mt, lo = 0;
+    if (level == 0) {
+        lo = c0 + leaf_lo(node, mp, g.L(0));
+        mt = c0 + leaf_lo(node + 1, mp, g.L(0)) - lo;
+    } else {
+        const int nch = min(C::F, g.L(level - 1) - node * C::F);
+        mt = nch * NB;
+        if (tid < nch) s_rb[tid] = c0 + leaf_lo((node * C::F + tid) * g.pw(level - 1), mp, g.L(0));
+        __syncthreads();
+    }
+    const int rbe = (mt + 15) >> 4;
+    const int wave = tid >> 6, lane = tid & 63, gq = lane >> 4, ln = lane & 15;
+    const int cbase = col0 + wave * 16;
+    static_assert(C::MT_MAX <= 256, "one reflector row per thread");
+    const int s = tid;
+    // reflector columns [32 h, 32 h + 32) into s_V, row s by thread s
+    // (explicit: unit diagonal, zero above it and beyond the node)
+    auto stage = [&](int h) {
+        T v[32];
+        if (level == 0) {
+            const RawBuf<T> bv(W + (size_t)c0 * ld, (unsigned)(nbk * ld * sizeof(T)));
+            const unsigned vo = s < mt ? (unsigned)((lo + s) * sizeof(T)) : kOob;
+#pragma unroll
+            for (int c = 0; c < 32; ++c) {
+                const int col = 32 * h + c;
+                const T x = bv.load(vo + (unsigned)(col * ld * sizeof(T)));
+                v[c] = s > col ? x : ((s == col && s < mt && col < nbk) ? T(1) : T(0));
+            }
+        } else {
+            const T* Vi = (par ? d.Vint[1] : d.Vint[0]) + (size_t)internal_index(g, level, node) * C::MT_MAX * NB;
+            const RawBuf<T> bv(Vi, (unsigned)(nbk * C::MT_MAX * sizeof(T)));
+            const unsigned vo = s < mt ? (unsigned)(s * sizeof(T)) : kOob;
+#pragma unroll
+            for (int c = 0; c < 32; ++c) v[c] = bv.load(vo + (unsigned)((32 * h + c) * C::MT_MAX * sizeof(T)));
+        }
+#pragma unroll
+        for (int c = 0; c < 32; ++c) s_V[s * VS + c] = v[c];
+    };
+    const RawBuf<T> bc(W + (size_t)cbase * ld, (unsigned)(max(0, min(16, ce - cbase)) * ld * sizeof(T)));
+    auto c_off = [&](int rb) -> unsigned {
+        const int sr = rb * 16 + ln;
+        const int wr = (rb >= rbe || sr >= mt) ? -1
+                       : level == 0 ? lo + sr
+                       : ((sr & (NB - 1)) < nbk ? s_rb[sr / NB] + (sr & (NB - 1)) : -1);
+        return wr >= 0 ? (unsigned)((M::row(gq, 0) * ld + wr) * sizeof(T)) : kOob;
+    };
+    v4 cr[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB / 2; ++rb) {
+        const unsigned o = c_off(rb);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cr[rb][q] = bc.load(o + (unsigned)(M::row(0, q) * ld * sizeof(T)));
+    }
+    stage(1);
+    __syncthreads();
+#pragma unroll
+    for (int rb = RB / 2; rb < RB; ++rb) {
+        const unsigned o = c_off(rb);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cr[rb][q] = bc.load(o + (unsigned)(M::row(0, q) * ld * sizeof(T)));
+    }
+    // W for the staged half h: rows [32 h, 32 h + 32) of W = V^T C (16
+    // columns per wave), C through the wave's LDS tile into the B layout
+    T* X = s_X + wave * 16 * XS;
+    v4 w[NKB];
+    auto wphase = [&](int h) {
+        v4 a0 = v4{0, 0, 0, 0}, a1 = v4{0, 0, 0, 0};
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            if (rb < rbe) {
+                T ob[4], ova[4], ovb[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) X[ln * XS + M::row(gq, v)] = cr[rb][v];
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    ob[kk] = X[(4 * kk + gq) * XS + ln];
+                    const T* vr = s_V + (rb * 16 + 4 * kk + gq) * VS;
+                    ova[kk] = vr[ln];
+                    ovb[kk] = vr[16 + ln];
+                }
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    a0 = M::mma(ova[kk], ob[kk], a0);
+                    a1 = M::mma(ovb[kk], ob[kk], a1);
+                }
+            }
+        }
+        w[2 * h] = a0;
+        w[2 * h + 1] = a1;
+    };
+    wphase(1);
+    __syncthreads();
+    stage(0);
+    __syncthreads();
+    wphase(0);
+    // Y = T^T W: output block o from the k-blocks kb <= o (T[k][m] = 0 for k > m)
+    const RawBuf<T> bt((par ? d.Tm[1] : d.Tm[0]) + (size_t)node_index(g, level, node, d.tm_leaves) * NB * NB,
+                       (unsigned)(NB * NB * sizeof(T)));
+    T ya[NKB][4];
+#pragma unroll
+    for (int o = 0; o < NKB; ++o) {
+        v4 y = v4{0, 0, 0, 0};
+#pragma unroll
+        for (int kb = 0; kb <= o; ++kb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = kb * 16 + M::row(gq, j);
+                y = M::mma(bt.load((unsigned)(((16 * o + ln) * NB + k) * sizeof(T))), w[kb][j], y);
+            }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ya[o][j] = -y[j];
+    }
+    // C^T -= Y_h^T V_h^T for the staged half h, two row blocks at a time;
+    // the last pass stores each pair as soon as it is done
+    auto uphase = [&](int h, bool store) {
+#pragma unroll
+        for (int rb = 0; rb < RB; rb += 2) {
+            if (rb < rbe) {
+                T vb[2][8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int kcol = (t >> 2) * 16 + M::row(gq, t & 3);
+#pragma unroll
+                    for (int g2 = 0; g2 < 2; ++g2)
+                        vb[g2][t] = rb + g2 < rbe ? s_V[((rb + g2) * 16 + ln) * VS + kcol] : T(0);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+#pragma unroll
+                    for (int g2 = 0; g2 < 2; ++g2)
+                        cr[rb + g2] = M::mma(ya[2 * h + (t >> 2)][t & 3], vb[g2][t], cr[rb + g2]);
+                __builtin_amdgcn_sched_barrier(0);
+                if (store) {
+#pragma unroll
+                    for (int g2 = 0; g2 < 2; ++g2) {
+                        const unsigned o = c_off(rb + g2);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            bc.store(cr[rb + g2][q], o + (unsigned)(M::row(0, q) * ld * sizeof(T)));
+                    }
+                }
+            }
+        }
+    };
+    uphase(0, false);
+    __syncthreads();
+    stage(1);
+    __syncthreads();
+    uphase(1, true);
+}
+
 // Row-split (look-ahead) update: the transpose of panel c0's orthogonal
 // factor (every tree level) applied, in one launch, to the next panel's
 // columns (row_split_cols).  A workgroup owns one node and one 16-column
@@ -691,7 +889,7 @@ __global__ __launch_bounds__(256, 2) void k_update(const QrDesc<T>* __restrict__
 // launches.  The MFMA layouts are those of k_update.
 template <typename T>
 __global__ __launch_bounds__(256) void k_la(const QrDesc<T>* __restrict__ descs, int c0) {
-    using C = QrCfg<T>;
+    using C = QrCfg<T, 32>;
     using M = Mfma<T>;
     typedef typename M::v4 v4;
     constexpr int NB = C::NB, VS = NB + 1, XS = 17, RBW = C::MT_MAX / 64;
@@ -710,7 +908,7 @@ __global__ __launch_bounds__(256) void k_la(const QrDesc<T>* __restrict__ descs,
     if (ce - cb <= 16 * cgrp) return;  // no columns in this group (for every node alike)
     const int cbase = cb + 16 * cgrp;
     const int mp = d.m - c0;
-    const auto g = tree_geom<T>(mp);
+    const auto g = tree_geom<T, 32>(mp);
     int node = blockIdx.x;
     if (node >= g.L(0)) return;
     // arrival counters of column group cgrp: after the panel factorization's
@@ -914,10 +1112,230 @@ __global__ __launch_bounds__(256) void k_la(const QrDesc<T>* __restrict__ descs,
     }
 }
 
+// Row-split (look-ahead) update for 64-column panels: as k_la, with the
+// node's 64 reflector columns in LDS at once (one workgroup per CU), W in
+// four 16-row blocks, and Y = T^T W formed one 16-row block per wave
+// (T upper triangular: the blocks below its diagonal skipped).
 template <typename T>
+__global__ __launch_bounds__(256) void k_la64(const QrDesc<T>* __restrict__ descs, int c0) {
+    using C = QrCfg<T, 64>;
+    using M = Mfma<T>;
+    typedef typename M::v4 v4;
+    constexpr int NB = C::NB, VS = NB + 1, XS = 17, RBW = C::MT_MAX / 64, NKB = NB / 16;
+    constexpr int SH = 64 * 4 * NKB;  // one wave's W (or all of Y) in the exchange buffer
+    __shared__ T s_V[C::MT_MAX * VS];
+    __shared__ T s_X[4 * 16 * XS];
+    __shared__ T s_E[2 * SH];
+    __shared__ int s_rb[C::F];
+    __shared__ int s_last;
+
+    const QrDesc<T> d = descs[blockIdx.z];
+    if (!d.active || c0 >= d.nf) return;
+    const int nbk = min(NB, d.nf - c0);
+    const int cb = c0 + nbk;
+    const int ce = cb + row_split_cols(NB, d.nf, c0);
+    const int cgrp = blockIdx.y;
+    if (ce - cb <= 16 * cgrp) return;  // no columns in this group (for every node alike)
+    const int cbase = cb + 16 * cgrp;
+    const int mp = d.m - c0;
+    const auto g = tree_geom<T, NB>(mp);
+    int node = blockIdx.x;
+    if (node >= g.L(0)) return;
+    const int nint = internal_index(g, g.levels, 0);
+    const int par = (c0 / NB) & 1;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, gq = lane >> 4, ln = lane & 15;
+    const int ld = d.ld;
+    T* W = d.W;
+    int level = 0;
+    const int lo = c0 + leaf_lo(node, mp, g.L(0));
+    int mt = c0 + leaf_lo(node + 1, mp, g.L(0)) - lo;
+    for (;;) {
+        const int rbe = (mt + 15) >> 4;
+        // explicit reflectors of the node, one row per thread, 32 columns at a time
+        {
+            const int s = tid;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                T v[32];
+                if (level == 0) {
+                    const RawBuf<T> bv(W + (size_t)c0 * ld, (unsigned)(nbk * ld * sizeof(T)));
+                    const unsigned vo = s < mt ? (unsigned)((lo + s) * sizeof(T)) : kOob;
+#pragma unroll
+                    for (int c = 0; c < 32; ++c) {
+                        const int col = 32 * h + c;
+                        const T x = bv.load(vo + (unsigned)(col * ld * sizeof(T)));
+                        v[c] = s > col ? x : ((s == col && s < mt && col < nbk) ? T(1) : T(0));
+                    }
+                } else {
+                    const T* Vi =
+                        (par ? d.Vint[1] : d.Vint[0]) + (size_t)internal_index(g, level, node) * C::MT_MAX * NB;
+                    const RawBuf<T> bv(Vi, (unsigned)(nbk * C::MT_MAX * sizeof(T)));
+                    const unsigned vo = s < mt ? (unsigned)(s * sizeof(T)) : kOob;
+#pragma unroll
+                    for (int c = 0; c < 32; ++c)
+                        v[c] = bv.load(vo + (unsigned)((32 * h + c) * C::MT_MAX * sizeof(T)));
+                }
+#pragma unroll
+                for (int c = 0; c < 32; ++c) s_V[s * VS + 32 * h + c] = v[c];
+            }
+        }
+        // this wave's rows of C^T (layout of k_update); the buffer covers the
+        // group's valid columns only
+        const RawBuf<T> bc(W + (size_t)cbase * ld, (unsigned)(max(0, min(16, ce - cbase)) * ld * sizeof(T)));
+        unsigned co[RBW];
+        v4 cr[RBW];
+#pragma unroll
+        for (int i = 0; i < RBW; ++i) {
+            const int rb = wave * RBW + i;
+            const int sr = rb * 16 + ln;
+            const int wr = (rb >= rbe || sr >= mt) ? -1
+                           : level == 0 ? lo + sr
+                           : ((sr & (NB - 1)) < nbk ? s_rb[sr / NB] + (sr & (NB - 1)) : -1);
+            co[i] = wr >= 0 ? (unsigned)((M::row(gq, 0) * ld + wr) * sizeof(T)) : kOob;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cr[i][q] = bc.load(co[i] + (unsigned)(M::row(0, q) * ld * sizeof(T)));
+        }
+        __syncthreads();  // s_V complete
+        // this wave's share of W = V^T C
+        T* X = s_X + wave * 16 * XS;
+        v4 w[NKB];
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb) w[kb] = v4{0, 0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < RBW; ++i) {
+            const int rb = wave * RBW + i;
+            if (rb < rbe) {
+                T ob[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) X[ln * XS + M::row(gq, v)] = cr[i][v];
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) ob[kk] = X[(4 * kk + gq) * XS + ln];
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const T* vr = s_V + (rb * 16 + 4 * kk + gq) * VS;
+#pragma unroll
+                    for (int kb = 0; kb < NKB; ++kb) w[kb] = M::mma(vr[16 * kb + ln], ob[kk], w[kb]);
+                }
+            }
+        }
+        // sum of the four shares, (P0 + P2) + (P1 + P3), in every wave
+        if (wave >= 2) {
+#pragma unroll
+            for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) s_E[(wave - 2) * SH + lane * 4 * NKB + 4 * kb + v] = w[kb][v];
+        }
+        __syncthreads();
+        if (wave < 2) {
+#pragma unroll
+            for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) w[kb][v] += s_E[wave * SH + lane * 4 * NKB + 4 * kb + v];
+        }
+        __syncthreads();
+        if (wave == 1) {
+#pragma unroll
+            for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) s_E[lane * 4 * NKB + 4 * kb + v] = w[kb][v];
+        }
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+            for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    w[kb][v] += s_E[lane * 4 * NKB + 4 * kb + v];
+                    s_E[SH + lane * 4 * NKB + 4 * kb + v] = w[kb][v];
+                }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) w[kb][v] = s_E[SH + lane * 4 * NKB + 4 * kb + v];
+        // Y block o = wave (rows [16 o, 16 o + 16) of Y = T^T W)
+        const RawBuf<T> bt((par ? d.Tm[1] : d.Tm[0]) + (size_t)node_index(g, level, node, d.tm_leaves) * NB * NB,
+                           (unsigned)(NB * NB * sizeof(T)));
+        v4 y = v4{0, 0, 0, 0};
+        const int wu = __builtin_amdgcn_readfirstlane(wave);  // wave-uniform
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb)
+            if (kb <= wu) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int k = kb * 16 + M::row(gq, j);
+                    y = M::mma(bt.load((unsigned)(((16 * wave + ln) * NB + k) * sizeof(T))), w[kb][j], y);
+                }
+            }
+        __syncthreads();  // every wave has read W
+#pragma unroll
+        for (int v = 0; v < 4; ++v) s_E[wave * 256 + lane * 4 + v] = y[v];
+        __syncthreads();
+        T yv[NKB][4];
+#pragma unroll
+        for (int o = 0; o < NKB; ++o)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) yv[o][v] = s_E[o * 256 + lane * 4 + v];
+        // C^T -= Y^T V^T on this wave's rows
+#pragma unroll
+        for (int pb = 0; pb < NKB; ++pb) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const T a = -yv[pb][j];
+                const int kcol = pb * 16 + M::row(gq, j);
+                T vb[RBW];
+#pragma unroll
+                for (int i = 0; i < RBW; ++i) {
+                    const int rb = wave * RBW + i;
+                    vb[i] = rb < rbe ? s_V[(rb * 16 + ln) * VS + kcol] : T(0);
+                }
+#pragma unroll
+                for (int i = 0; i < RBW; ++i)
+                    if (wave * RBW + i < rbe) cr[i] = M::mma(a, vb[i], cr[i]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < RBW; ++i)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) bc.store(cr[i][q], co[i] + (unsigned)(M::row(0, q) * ld * sizeof(T)));
+        // climb: the last child to arrive updates the parent's rows
+        if (level + 1 >= g.levels) return;
+        __threadfence();
+        __syncthreads();
+        const int parent = node / C::F;
+        const int iidx = internal_index(g, level + 1, parent);
+        const int nch = min(C::F, g.L(level) - parent * C::F);
+        if (tid == 0) {
+            unsigned* cnt = d.counters + kPanelCounters + cgrp * nint + iidx;
+            const unsigned old = atomicAdd(cnt, 1u);
+            s_last = (old == (unsigned)(nch - 1));
+            if (s_last) *cnt = 0u;
+        }
+        __syncthreads();
+        if (!s_last) return;
+        __threadfence();
+        node = parent;
+        ++level;
+        mt = nch * NB;
+        if (tid < nch) s_rb[tid] = c0 + leaf_lo((node * C::F + tid) * g.pw(level - 1), mp, g.L(0));
+        __syncthreads();
+    }
+}
+
+template <typename T, int NBW>
 static void launch_update(dim3 grid, hipStream_t s, const QrDesc<T>* d, int c0, int lev) {
-    constexpr int RB = QrCfg<T>::MT_MAX / 16;
-    hipLaunchKernelGGL((k_update<T, RB>), grid, dim3(256), 0, s, d, c0, lev);
+    if constexpr (NBW == 64) {
+        hipLaunchKernelGGL(k_update64<T>, grid, dim3(256), 0, s, d, c0, lev);
+    } else {
+        constexpr int RB = QrCfg<T, 32>::MT_MAX / 16;
+        hipLaunchKernelGGL((k_update<T, RB>), grid, dim3(256), 0, s, d, c0, lev);
+    }
+}
+template <typename T, int NBW>
+static void launch_la(dim3 grid, hipStream_t s, const QrDesc<T>* d, int c0) {
+    if constexpr (NBW == 64) hipLaunchKernelGGL(k_la64<T>, grid, dim3(256), 0, s, d, c0);
+    else hipLaunchKernelGGL(k_la<T>, grid, dim3(256), 0, s, d, c0);
 }
 
 // Batched augmented QR, panel by panel: panel factorization P(k), then the
@@ -934,9 +1352,10 @@ static void launch_update(dim3 grid, hipStream_t s, const QrDesc<T>* d, int c0, 
 // writes the other parity's T / reflector buffers while REST(k) reads
 // panel k's.  crit starts after the work already on s, and s waits for both
 // streams before returning.
-template <typename T>
-void qr_aug_batch(const QrDesc<T>* d_descs, const QrDesc<T>* h, int count, hipStream_t s, const QrStreams* la) {
-    using C = QrCfg<T>;
+template <typename T, int NBW>
+static void qr_aug_batch_nb(const QrDesc<T>* d_descs, const QrDesc<T>* h, int count, hipStream_t s,
+                            const QrStreams* la) {
+    using C = QrCfg<T, NBW>;
     int max_nf = 0;
     for (int i = 0; i < count; ++i)
         if (h[i].active) max_nf = max_nf > h[i].nf ? max_nf : h[i].nf;
@@ -961,7 +1380,7 @@ void qr_aug_batch(const QrDesc<T>* d_descs, const QrDesc<T>* h, int count, hipSt
         for (int i = 0; i < count; ++i) {
             if (!h[i].active || c0 >= h[i].nf) continue;
             const int mp = h[i].m - c0;
-            const auto g = tree_geom<T>(mp);
+            const auto g = tree_geom<T, NBW>(mp);
             for (int l = 0; l < g.levels; ++l) maxL[l] = maxL[l] > g.L(l) ? maxL[l] : g.L(l);
             maxlev = maxlev > g.levels ? maxlev : g.levels;
             const int nbk = h[i].nf - c0 < C::NB ? h[i].nf - c0 : C::NB;
@@ -991,7 +1410,7 @@ void qr_aug_batch(const QrDesc<T>* d_descs, const QrDesc<T>* h, int count, hipSt
         }
         if (maxL[0] == 0) continue;
         int pid = prof ? prof->begin(sc) : -1;
-        hipLaunchKernelGGL(k_panel<T>, dim3(maxL[0], count), dim3(C::PT), 0, sc, d_descs, c0);
+        hipLaunchKernelGGL((k_panel<T, NBW>), dim3(maxL[0], count), dim3(C::PT), 0, sc, d_descs, c0);
         if (prof) prof->end(pid, sc, PROF_PANEL, pf, pb);
         if (la_groups == 0 && rest_tiles == 0) continue;
         if (rest_pending) {  // REST(k-1) updated columns that LA(k) and REST(k) touch
@@ -1000,7 +1419,7 @@ void qr_aug_batch(const QrDesc<T>* d_descs, const QrDesc<T>* h, int count, hipSt
         }
         if (la_groups > 0) {
             const int lid = prof ? prof->begin(sc) : -1;
-            hipLaunchKernelGGL(k_la<T>, dim3(la_l0, la_groups, count), dim3(256), 0, sc, d_descs, c0);
+            launch_la<T, NBW>(dim3(la_l0, la_groups, count), sc, d_descs, c0);
             if (prof) prof->end(lid, sc, PROF_LA, lf, lb);
         }
         if (rest_tiles == 0) continue;
@@ -1015,7 +1434,7 @@ void qr_aug_batch(const QrDesc<T>* d_descs, const QrDesc<T>* h, int count, hipSt
         }
         for (int lev = 0; lev < maxlev; ++lev) {
             const int uid = prof ? prof->begin(st) : -1;
-            launch_update<T>(dim3(maxL[lev], rest_tiles, count), st, d_descs, c0, lev);
+            launch_update<T, NBW>(dim3(maxL[lev], rest_tiles, count), st, d_descs, c0, lev);
             if (prof) prof->end(uid, st, PROF_UPDATE, uf[lev], ub[lev]);
         }
         if (side) {
@@ -1028,6 +1447,13 @@ void qr_aug_batch(const QrDesc<T>* d_descs, const QrDesc<T>* h, int count, hipSt
         (void)hipEventRecord(la->evD, sc);
         (void)hipStreamWaitEvent(s, la->evD, 0);
     }
+}
+// Every problem of one call has the same panel width (the engine groups them).
+template <typename T>
+void qr_aug_batch(const QrDesc<T>* d_descs, const QrDesc<T>* h, int count, hipStream_t s, const QrStreams* la) {
+    if (count <= 0) return;
+    if (h[0].nb == 64) qr_aug_batch_nb<T, 64>(d_descs, h, count, s, la);
+    else qr_aug_batch_nb<T, 32>(d_descs, h, count, s, la);
 }
 template void qr_aug_batch<double>(const QrDesc<double>*, const QrDesc<double>*, int, hipStream_t,
                                    const QrStreams*);

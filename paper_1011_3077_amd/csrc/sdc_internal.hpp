@@ -18,37 +18,38 @@ namespace sdc {
 // (<= MT_MAX rows) is a single leaf.  Every node is at most MT_MAX rows by NB
 // columns and lives in one workgroup's registers.
 // ---------------------------------------------------------------------------
-template <typename T> struct QrCfg;
+template <typename T, int NBW> struct QrCfg {
+    // Panels are NBW = 32 or 64 columns wide.  The wider panel doubles the
+    // arithmetic intensity of the trailing update (flops per byte of the
+    // trailing matrix moved), at the price of a longer panel factorization
+    // per column and a shallower fan-in (F * NB <= MT_MAX).
+    static_assert(NBW == 32 || NBW == 64, "panel widths 32 and 64");
+    static constexpr int NB = NBW, MT_MAX = 256, H = 256, F = 256 / NBW, PT = 256;
+};
 // Panel workgroups have PT = 256 threads (four wavefronts, one per SIMD of a
 // CU); a node (at most MT_MAX rows, NB columns) is factored in registers
 // with each wavefront owning NB/4 columns and each lane up to MT_MAX/64 rows.
-// Every node (F * NB <= MT_MAX rows) fits the trailing-update kernel's
+// Every node (F * NB <= MT_MAX rows) fits the trailing-update kernels'
 // registers (256 rows x 16 columns per wave).
-template <> struct QrCfg<double> {
-    static constexpr int NB = 32, MT_MAX = 256, H = 256, F = 8, PT = 256;
-};
-template <> struct QrCfg<float> {
-    static constexpr int NB = 32, MT_MAX = 256, H = 256, F = 8, PT = 256;
-};
 
 constexpr int kMaxLevels = 5;
 // Tree arrival counters per problem (kMaxInternal of them, zero between
 // uses: each is reset by its last arrival): the panel factorization counts
 // arrivals at internal nodes in the first kPanelCounters, the row-split
-// update (k_la, two 16-column groups) after them, one per (column group,
-// internal node) of the panel's tree.
-constexpr int kMaxInternal = 96;
-constexpr int kPanelCounters = 32;
+// update (k_la, NB/16 column groups of 16) after them, one per (column
+// group, internal node) of the panel's tree.
+constexpr int kMaxInternal = 320;
+constexpr int kPanelCounters = 64;
 constexpr int kMaxPanelRows = 2 * 16384;  // augmented matrices of order <= 16384
 
 // Tree shape of a panel with mp rows: L0 leaves, levels levels, and
 // L(l) = ceil(L0 / F^l) nodes at level l.  Computed arithmetically (no
 // arrays indexed at run time, so kernels keep it in registers).
-template <typename T> struct TreeGeomT {
+template <typename T, int NBW> struct TreeGeomT {
     int L0, levels;
     __host__ __device__ int pw(int l) const {
         int p = 1;
-        for (int i = 0; i < l; ++i) p *= QrCfg<T>::F;
+        for (int i = 0; i < l; ++i) p *= QrCfg<T, NBW>::F;
         return p;
     }
     __host__ __device__ int L(int l) const {
@@ -58,10 +59,10 @@ template <typename T> struct TreeGeomT {
     }
 };
 
-template <typename T>
-__host__ __device__ inline TreeGeomT<T> tree_geom(int mp) {
-    using C = QrCfg<T>;
-    TreeGeomT<T> g;
+template <typename T, int NBW>
+__host__ __device__ inline TreeGeomT<T, NBW> tree_geom(int mp) {
+    using C = QrCfg<T, NBW>;
+    TreeGeomT<T, NBW> g;
     static_assert(C::H % 16 == 0, "leaves are whole 16-row blocks");
     g.L0 = mp <= C::MT_MAX ? 1 : ((mp + 15) / 16 + C::H / 16 - 1) / (C::H / 16);
     g.levels = 1;
@@ -81,9 +82,10 @@ __host__ __device__ inline int leaf_lo(int j, int mp, int L0) {
     return (int)((j * blocks) / L0) * 16;
 }
 
-// Internal nodes of the tallest supported panel (checked against the counters).
-template <typename T> constexpr int max_internal_nodes() {
-    using C = QrCfg<T>;
+// Internal nodes and levels of the tallest supported panel (checked
+// against the counters and kMaxLevels).
+template <typename T, int NBW> constexpr int max_internal_nodes() {
+    using C = QrCfg<T, NBW>;
     int n = ((kMaxPanelRows + 15) / 16 + C::H / 16 - 1) / (C::H / 16), total = 0;
     while (n > 1) {
         n = (n + C::F - 1) / C::F;
@@ -91,15 +93,27 @@ template <typename T> constexpr int max_internal_nodes() {
     }
     return total;
 }
-static_assert(max_internal_nodes<double>() <= kPanelCounters && max_internal_nodes<float>() <= kPanelCounters,
-              "panel counters");
-static_assert(kPanelCounters + 2 * max_internal_nodes<double>() <= kMaxInternal &&
-                  kPanelCounters + 2 * max_internal_nodes<float>() <= kMaxInternal,
-              "two column groups of look-ahead counters per internal node");
+template <typename T, int NBW> constexpr int max_levels() {
+    using C = QrCfg<T, NBW>;
+    int n = ((kMaxPanelRows + 15) / 16 + C::H / 16 - 1) / (C::H / 16), lv = 1;
+    while (n > 1) {
+        n = (n + C::F - 1) / C::F;
+        ++lv;
+    }
+    return lv;
+}
+template <typename T, int NBW> constexpr bool counters_fit() {
+    return max_internal_nodes<T, NBW>() <= kPanelCounters &&
+           kPanelCounters + (NBW / 16) * max_internal_nodes<T, NBW>() <= kMaxInternal &&
+           max_levels<T, NBW>() <= kMaxLevels;
+}
+static_assert(counters_fit<double, 32>() && counters_fit<float, 32>() && counters_fit<double, 64>() &&
+                  counters_fit<float, 64>(),
+              "tree counters and levels of the tallest panel");
 
 // Index of an internal node (level >= 1) in per-problem arrays.
-template <typename T>
-__host__ __device__ inline int internal_index(const TreeGeomT<T>& g, int level, int node) {
+template <typename T, int NBW>
+__host__ __device__ inline int internal_index(const TreeGeomT<T, NBW>& g, int level, int node) {
     int off = 0;
     for (int l = 1; l < level; ++l) off += g.L(l);
     return off + node;
@@ -120,8 +134,8 @@ __host__ __device__ inline int row_split_cols(int nb, int nf, int c0) {
 }
 
 // Index of any node in the per-problem T-factor array (leaves first).
-template <typename T>
-__host__ __device__ inline int node_index(const TreeGeomT<T>& g, int level, int node, int tm_leaves) {
+template <typename T, int NBW>
+__host__ __device__ inline int node_index(const TreeGeomT<T, NBW>& g, int level, int node, int tm_leaves) {
     return level == 0 ? node : tm_leaves + internal_index(g, level, node);
 }
 
@@ -139,15 +153,21 @@ template <typename T> struct QrDesc {
     T* diag;          // nf: diagonal of R as produced (before sign normalization)
     unsigned* counters; // kMaxInternal tree arrival counters (must start at zero)
     int active;
+    int nb;           // panel width (32 or 64); every problem of one batched call has the same
 };
 
-// Elements of one parity's side buffers for an m-row problem.
-template <typename T> size_t qr_aux_elems(int m) {
-    using C = QrCfg<T>;
-    const auto g = tree_geom<T>(m);
+// Elements of one parity's side buffers for an m-row problem and panel
+// width NBW, and the most either panel width needs.
+template <typename T, int NBW> size_t qr_aux_elems_nb(int m) {
+    using C = QrCfg<T, NBW>;
+    const auto g = tree_geom<T, NBW>(m);
     size_t internal = 0;
     for (int l = 1; l < g.levels; ++l) internal += (size_t)g.L(l);
     return ((size_t)g.L(0) + internal) * C::NB * C::NB + internal * C::MT_MAX * C::NB;
+}
+template <typename T> size_t qr_aux_elems(int m) {
+    const size_t a = qr_aux_elems_nb<T, 32>(m), b = qr_aux_elems_nb<T, 64>(m);
+    return a > b ? a : b;
 }
 
 // Streams and events for the look-ahead schedule of the QR (panel k+1

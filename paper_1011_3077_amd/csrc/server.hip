@@ -133,7 +133,7 @@ void sdc_server_s::loop() {
                 r->ws = nullptr;
                 st = SDC_ERR_NOMEM;
             } else {
-                r->run = sdc::job_run_create(&r->job, r->ws, r->bytes);
+                r->run = sdc::job_run_create(h, &r->job, r->ws, r->bytes);
                 if (!r->run) st = SDC_ERR_NOMEM;
             }
             if (st != SDC_OK) {

@@ -1,0 +1,295 @@
+"""The 64-column QR panels (opts.panel_width = 64, or the handle's table for
+large orders) against the FP64 oracle, element by element where the result
+is unique, at orders that reach every path of the wider kernels: a single
+node, several tree levels (fan-in 4 above 256-row leaves), the row-split
+look-ahead (>= 1200 factored columns), FP32 iterates, and batches that mix
+the two widths (each problem bitwise the same alone and in the batch)."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import sdc_synth as S
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+HALF0 = {"kind": "halfplane", "shift": 0.0, "scale": 1.0}
+
+
+@pytest.fixture(scope="module")
+def sdc():
+    import paper_1011_3077_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def handle(sdc):
+    h = sdc.Handle(0)
+    yield h
+    h.close()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def norm1(x):
+    return float(np.max(np.sum(np.abs(x), axis=0)))
+
+
+def sin_theta(x, y):
+    qx, _ = np.linalg.qr(x)
+    qy, _ = np.linalg.qr(y)
+    return float(np.linalg.norm(qy - qx @ (qx.T @ qy), 2))
+
+
+def gauss_stack(n, seed, attempts=3):
+    gs = [S.gaussian(n, seed + 10 * a + side) for a in range(attempts) for side in range(2)]
+    return gs, dev(np.concatenate([g.ravel(order="F") for g in gs]))
+
+
+def print_case(**kw):
+    print("CASE", kw, flush=True)
+
+
+@pytest.mark.parametrize("n", [1, 2, 33, 64, 65, 96, 130, 300, 700])
+def test_irs_panel64_matches_oracle_symmetric(handle, sdc, n):
+    """R_j (unique with a non-negative diagonal) entry by entry, p exactly,
+    and the Gram invariants of the iterates; 2n = 1400 rows give a
+    three-level tree with fan-in 4."""
+    import oracle as O
+    from oracle.split import premap
+    print_case(test="irs_sym_nb64", n=n)
+    a, d, q = S.sym_problem(n, S.family_seed(0, n))
+    st, ap, bp, r, p, rc = handle.irs(dev(a), None, sdc.region("halfplane", shift=0.0, scale=1.0),
+                                      sdc.opts(panel_width=64))
+    ap, bp, r = host(ap), host(bp), host(r)
+    a0, b0 = premap(a, np.eye(n), HALF0)
+    ref = O.irs(a0, b0, record=True)
+    assert st == sdc.SDC_OK and ref.converged and p == ref.p
+    rr = ref.R_history[-1]
+    assert np.abs(r - rr).max() <= 1e-11 * np.abs(rr).max()
+    for x, y in ((ap.T @ ap, ref.A.T @ ref.A), (bp.T @ bp, ref.B.T @ ref.B), (ap.T @ bp, ref.A.T @ ref.B)):
+        assert np.abs(x - y).max() <= 1e-10 * max(1.0, np.abs(y).max())
+
+
+@pytest.mark.parametrize("n,transpose", [(48, 1), (300, 0), (1250, 0)])
+def test_irs_panel64_matches_oracle_pencil(handle, sdc, n, transpose):
+    """Order 1250: 2500 stacked rows (ten leaves, three levels) and 1250
+    factored columns, so the look-ahead update of the 64-column panels runs."""
+    import oracle as O
+    print_case(test="irs_pencil_nb64", n=n, transpose=transpose)
+    pb = S.pencil_problem(n, S.family_seed(1, n))
+    a, b = pb["A"], pb["B"]
+    st, ap, bp, r, p, rc = handle.irs(dev(a), dev(b), sdc.region(), sdc.opts(panel_width=64),
+                                      transpose=bool(transpose))
+    ap, bp, r = host(ap), host(bp), host(r)
+    ref = O.irs(a.T if transpose else a, b.T if transpose else b, record=True)
+    assert st == sdc.SDC_OK and ref.converged and p == ref.p
+    rr = ref.R_history[-1]
+    assert np.abs(r - rr).max() <= 1e-10 * np.abs(rr).max()
+    for x, y in ((ap.T @ ap, ref.A.T @ ref.A), (bp.T @ bp, ref.B.T @ ref.B), (ap.T @ bp, ref.A.T @ ref.B)):
+        assert np.abs(x - y).max() <= 1e-9 * max(1.0, np.abs(y).max())
+
+
+@pytest.mark.parametrize("n", [5, 65, 300, 1300])
+def test_split_sym_panel64_matches_oracle(handle, sdc, n):
+    import oracle as O
+    print_case(test="split_sym_nb64", n=n)
+    seed = S.family_seed(0, 500 + n)
+    a, d, q = S.sym_problem(n, seed)
+    gs, gdev = gauss_stack(n, seed)
+    res = handle.split_sym(dev(a), sdc.region("halfplane", shift=0.0, scale=1.0),
+                           sdc.opts(G=gdev, diagnostics=1, panel_width=64))
+    ref = O.split_sym(a, HALF0, gauss=lambda nn, att, side: gs[2 * att + side])
+    info = res.info
+    assert res.status == ref.status == sdc.SDC_OK
+    k = info["k_lead"]
+    assert k == ref.k == int((d > 0).sum())
+    assert info["iters_right"] == ref.p_right and info["attempts"] == ref.attempts
+    Q, Ah = host(res.Q), host(res.Ahat)
+    assert np.abs(Q[:, :k] - ref.Q[:, :k]).max() <= 1e-10
+    assert np.abs(Ah[:k, :k] - ref.A_hat[:k, :k]).max() <= 1e-10 * norm1(a)
+    assert sin_theta(Q[:, k:], ref.Q[:, k:]) <= 1e-10
+    e_tol = max(1e-12, 10 * n * np.finfo(float).eps)
+    assert info["e21_rel"] <= e_tol and abs(info["e21_rel"] - ref.e) <= e_tol
+    assert info["orth_err"] <= 1e-13 * max(n, 10)
+    ev = np.sort(np.concatenate([np.linalg.eigvalsh(Ah[:k, :k]), np.linalg.eigvalsh(Ah[k:, k:])]))
+    assert np.abs(ev - np.sort(d)).max() <= 1e-10 * np.abs(d).max()
+
+
+@pytest.mark.parametrize("n", [48, 300])
+def test_split_pencil_panel64_matches_oracle(handle, sdc, n):
+    import oracle as O
+    print_case(test="split_pencil_nb64", n=n)
+    seed = S.family_seed(1, 600 + n)
+    pb = S.pencil_problem(n, seed)
+    a, b, lam = pb["A"], pb["B"], pb["lam"]
+    gs, gdev = gauss_stack(n, seed)
+    res = handle.split_pencil(dev(a), dev(b), sdc.region(), sdc.opts(G=gdev, diagnostics=1, panel_width=64))
+    ref = O.split_pencil(a, b, {"kind": "unit_disk"}, gauss=lambda nn, att, side: gs[2 * att + side])
+    info = res.info
+    assert res.status == ref.status == sdc.SDC_OK
+    k = info["k_lead"]
+    assert k == ref.k == int((np.abs(lam) > 1).sum())
+    assert info["iters_right"] == ref.p_right and info["iters_left"] == ref.p_left
+    QR, QL, Ah, Bh = host(res.Q), host(res.QL), host(res.Ahat), host(res.Bhat)
+    assert np.abs(QR[:, :k] - ref.Q[:, :k]).max() <= 1e-9
+    assert np.abs(QL[:, :k] - ref.QL[:, :k]).max() <= 1e-9
+    assert sin_theta(QR[:, k:], ref.Q[:, k:]) <= 1e-9
+    assert np.abs(Ah[:k, :k] - ref.A_hat[:k, :k]).max() <= 1e-9 * norm1(a)
+    assert info["e21_rel"] <= 1e-11 and abs(info["e21_rel"] - ref.e) <= 1e-11
+    got = np.sort_complex(np.concatenate([sla.eigvals(Ah[:k, :k], Bh[:k, :k]), sla.eigvals(Ah[k:, k:], Bh[k:, k:])]))
+    want = np.sort_complex(lam.astype(complex))
+    assert np.max(np.abs(got - want) / np.abs(want)) <= 1e-10
+
+
+@pytest.mark.parametrize("n", [300, 1300])
+def test_fp32_refine_panel64_matches_fp64_oracle(handle, sdc, n):
+    """FP32 iterates on the 64-column kernels (single node to three levels,
+    look-ahead at 1300), refined in FP64, against the FP64 oracle."""
+    import oracle as O
+    print_case(test="fp32_refine_nb64", n=n)
+    seed = S.family_seed(0, 700 + n)
+    a, d, q = S.sym_problem(n, seed)
+    res = handle.split_sym(dev(a), sdc.region("halfplane", shift=0.0, scale=1.0),
+                           sdc.opts(prec=sdc.SDC_FP32_REFINE, seed=3, diagnostics=1, panel_width=64))
+    ref = O.split_sym(a, HALF0, seed=3)
+    info = res.info
+    assert res.status == ref.status == sdc.SDC_OK and info["fp64_fallback"] == 0
+    k = info["k_lead"]
+    assert k == ref.k == int((d > 0).sum())
+    Q, Ah = host(res.Q), host(res.Ahat)
+    gap = float(np.min(d[d > 0]) - np.max(d[d < 0]))
+    e21 = np.linalg.norm(Ah[k:, :k])
+    assert sin_theta(Q[:, :k], ref.Q[:, :k]) <= max(1e-9, 2 * e21 / gap)
+    assert info["e21_rel"] <= 1e-10
+    ev = np.sort(np.concatenate([np.linalg.eigvalsh(Ah[:k, :k]), np.linalg.eigvalsh(Ah[k:, k:])]))
+    assert np.abs(ev - np.sort(d)).max() <= 1e-9 * np.abs(d).max()
+
+
+def test_panel_widths_agree(handle, sdc):
+    """The same split with 32- and 64-column panels: same p, k and status;
+    leading basis and block entries within the 1e-10 that each meets
+    against the oracle (the columns of eigenvalues nearest the split line
+    differ most: about 4e-12 at this order)."""
+    n = 500
+    print_case(test="nb32_vs_nb64", n=n)
+    seed = S.family_seed(0, 1500)
+    a, d, q = S.sym_problem(n, seed)
+    gs, gdev = gauss_stack(n, seed)
+    reg = sdc.region("halfplane", shift=0.0, scale=1.0)
+    r32 = handle.split_sym(dev(a), reg, sdc.opts(G=gdev, panel_width=32))
+    r64 = handle.split_sym(dev(a), reg, sdc.opts(G=gdev, panel_width=64))
+    assert r32.status == r64.status == sdc.SDC_OK
+    assert r32.info["k_lead"] == r64.info["k_lead"] and r32.info["iters_right"] == r64.info["iters_right"]
+    k = r32.info["k_lead"]
+    assert np.abs(host(r32.Q)[:, :k] - host(r64.Q)[:, :k]).max() <= 1e-10
+    assert np.abs(host(r32.Ahat)[:k, :k] - host(r64.Ahat)[:k, :k]).max() <= 1e-10 * norm1(a)
+
+
+def test_batch_mixing_panel_widths_equals_single_calls(handle, sdc):
+    """With a table that gives 64-column panels from order 1000 (set on a
+    handle of its own), a batch of orders 1300, 100 and 300 runs its QRs as
+    two width groups; each result is bitwise that of the problem alone."""
+    sizes = [1300, 100, 300]
+    print_case(test="batch_mixed_widths", sizes=sizes)
+    h = sdc.Handle(0)
+    try:
+        h.tune_set(1000, 1000)
+        assert h.tune_get() == (1000, 1000)
+        mats = [S.sym_problem(n, S.family_seed(2, 900 + i))[0] for i, n in enumerate(sizes)]
+        regs = [sdc.region("halfplane", shift=0.0, scale=1.0)] * len(sizes)
+        batch = h.split_sym_batched([dev(m) for m in mats], regs, sdc.opts(seed=31))
+        for i, m in enumerate(mats):
+            single = h.split_sym(dev(m), regs[i], sdc.opts(seed=31 + i * 1000003))
+            assert batch[i].status == single.status == sdc.SDC_OK
+            assert torch.equal(batch[i].Q, single.Q) and torch.equal(batch[i].Ahat, single.Ahat)
+        # the order-1300 problem took the 64-column kernels: same bits as forcing them
+        forced = handle.split_sym(dev(mats[0]), regs[0], sdc.opts(seed=31, panel_width=64))
+        assert torch.equal(batch[0].Q, forced.Q)
+    finally:
+        h.close()
+
+
+def test_batched_forced_panel64_equals_single_calls(handle, sdc):
+    sizes = [50, 200, 1300]
+    print_case(test="batch_nb64", sizes=sizes)
+    mats = [S.sym_problem(n, S.family_seed(2, 950 + i))[0] for i, n in enumerate(sizes)]
+    regs = [sdc.region("halfplane", shift=0.0, scale=1.0)] * len(sizes)
+    batch = handle.split_sym_batched([dev(m) for m in mats], regs, sdc.opts(seed=17, panel_width=64))
+    for i, m in enumerate(mats):
+        single = handle.split_sym(dev(m), regs[i], sdc.opts(seed=17 + i * 1000003, panel_width=64))
+        assert batch[i].status == single.status == sdc.SDC_OK
+        assert torch.equal(batch[i].Q, single.Q) and torch.equal(batch[i].Ahat, single.Ahat)
+
+
+def test_tune_table_save_load(sdc, tmp_path):
+    """sdc_tune_set/get, and the JSON cache: written, read back into a fresh
+    handle, keys missing from a file leave the table, a malformed file is
+    refused."""
+    print_case(test="tune_table")
+    h1, h2 = sdc.Handle(0), sdc.Handle(0)
+    try:
+        assert h1.tune_get() == (sdc.SDC_PANEL64_NEVER, sdc.SDC_PANEL64_NEVER)
+        h1.tune_set(4096, sdc.SDC_PANEL64_NEVER)
+        path = str(tmp_path / "tune.json")
+        h1.tune_save(path)
+        import json
+        with open(path) as f:
+            doc = json.load(f)
+        assert doc["nb64_min_fp64"] == 4096 and doc["nb64_min_fp32"] == sdc.SDC_PANEL64_NEVER
+        h2.tune_load(path)
+        assert h2.tune_get() == (4096, sdc.SDC_PANEL64_NEVER)
+        part = tmp_path / "part.json"
+        part.write_text('{"nb64_min_fp32": 2000}')
+        h2.tune_load(str(part))
+        assert h2.tune_get() == (4096, 2000)
+        bad = tmp_path / "bad.json"
+        bad.write_text('{"nb64_min_fp64": x}')
+        with pytest.raises(sdc.SdcError, match="INVALID"):
+            h2.tune_load(str(bad))
+        with pytest.raises(sdc.SdcError, match="INVALID"):
+            h2.tune_load(str(tmp_path / "missing.json"))
+        assert h2.tune_get() == (4096, 2000)
+    finally:
+        h1.close()
+        h2.close()
+
+
+def test_autotune_small_orders(sdc, tmp_path):
+    """The autotuner times both widths at each order and precision and sets
+    the table by its rule (the smallest order from which 64 wins at every
+    larger timed order); the cache holds the same table."""
+    orders = [96, 320]
+    print_case(test="autotune", orders=orders)
+    h = sdc.Handle(0)
+    try:
+        path = str(tmp_path / "auto.json")
+        res = h.autotune(orders, reps=1, cache=path)
+        assert [r["n"] for r in res] == orders + orders
+        assert [r["prec"] for r in res] == [sdc.SDC_FP64] * 2 + [sdc.SDC_FP32_REFINE] * 2
+        assert all(0 < r["ms_nb32"] < 1e4 and 0 < r["ms_nb64"] < 1e4 for r in res)
+        want = []
+        for p in range(2):
+            rows = sorted(res[2 * p:2 * p + 2], key=lambda r: r["n"])
+            lim = sdc.SDC_PANEL64_NEVER
+            for r in reversed(rows):
+                if r["ms_nb64"] < r["ms_nb32"]:
+                    lim = r["n"]
+                else:
+                    break
+            want.append(lim)
+        assert h.tune_get() == tuple(want)
+        h2 = sdc.Handle(0)
+        try:
+            h2.tune_load(path)
+            assert h2.tune_get() == tuple(want)
+        finally:
+            h2.close()
+    finally:
+        h.close()
