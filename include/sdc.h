@@ -115,7 +115,8 @@ typedef struct {
     int k_rho;           /* rank read off the GRURV diagonals */
     double rconv_last;   /* last relative R change of the right-side IRS */
     double e21_rel;      /* minimized ||E21||_1/||A||_1 (+ ||F21||_1/||B||_1) */
-    double orth_err;     /* ||Q^T Q - I||_F of Q (Q_R), if diagnostics */
+    double orth_err;     /* ||Q^T Q - I||_F of Q (Q_R), if diagnostics (summed over blocks
+                            atomically: its last bit may differ between runs) */
     double rank_gap;     /* ratio across the largest gap of the sorted diagonal ratios */
     double ms;           /* wall time of the call in milliseconds */
     int fp64_fallback;   /* SDC_FP32_REFINE: 1 if every FP32 attempt failed and the split
@@ -367,6 +368,21 @@ typedef struct {
     double flops;       /* summed algorithmic flops */
     double bytes;       /* summed algorithmic bytes */
 } sdc_kernel_stats_t;
+
+/* Replay the repeated-squaring iterations (Alg. 3) of sdc_split_sym,
+ * sdc_split_pencil, sdc_split_nonsym, sdc_split_svd, the batched call and
+ * the divide-and-conquer from a HIP graph (on != 0) instead of launching
+ * their kernels one by one: one iteration of every problem of the call is
+ * captured once (on a stream of the handle's own, after the descriptors are
+ * resident on the device) and replayed per iteration; problems whose
+ * convergence test has passed are switched off between replays.  Results
+ * are bitwise the same either way.  Only problems below 1200 factored
+ * columns are replayed (their QRs run on one stream; larger ones use the
+ * two-stream look-ahead schedule and keep the direct launches).  Not used
+ * while profiling is on, nor by the served form (its set of problems
+ * changes every iteration).
+ * SDC_ERR_INVALID for the no-allocation handle. */
+sdc_status_t sdc_graphs_enable(sdc_handle_t h, int on);
 
 /* Enable (on != 0) or disable profiling; either way the totals are reset. */
 sdc_status_t sdc_profile_enable(sdc_handle_t h, int on);

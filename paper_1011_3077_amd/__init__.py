@@ -20,6 +20,14 @@ LIB_PATH = os.path.join(_HERE, "libsdc.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} not built; run `python -m paper_1011_3077_amd.build`")
+# torch first: torch carries its own HIP runtime under the same soname as the
+# system's, and the first one loaded serves the whole process.  Loading
+# torch's before the library keeps one runtime, the one torch was built for,
+# whatever order the caller imports the two modules in (with the system's
+# loaded first and torch initializing the device first, creating a handle
+# failed with SDC_ERR_DEVICE).
+import torch  # noqa: E402,F401
+
 lib = C.CDLL(LIB_PATH)
 
 SDC_OK, SDC_NOT_CONVERGED, SDC_NO_SPLIT, SDC_RANK_AMBIGUOUS = 0, 1, 2, 3
@@ -32,6 +40,7 @@ EXPORTED = ["sdc_opts_default", "sdc_create", "sdc_destroy", "sdc_status_string"
             "sdc_eig_dc",
             "sdc_block_eigvals", "sdc_trevc",
             "sdc_gaussian", "sdc_tune_set", "sdc_tune_get", "sdc_autotune", "sdc_tune_save", "sdc_tune_load",
+            "sdc_graphs_enable",
             "sdc_profile_enable", "sdc_profile_read", "sdc_server_create", "sdc_server_submit",
             "sdc_server_poll", "sdc_server_wait", "sdc_server_stats", "sdc_server_destroy"]
 SDC_REQ_SYM, SDC_REQ_PENCIL = 0, 1
@@ -151,6 +160,8 @@ lib.sdc_profile_read.argtypes = [_P, _I, C.POINTER(KernelStats)]
 lib.sdc_profile_read.restype = _I
 lib.sdc_gaussian.argtypes = [_P, _I, C.c_uint64, _I, _P, _I]
 lib.sdc_gaussian.restype = _I
+lib.sdc_graphs_enable.argtypes = [_P, _I]
+lib.sdc_graphs_enable.restype = _I
 lib.sdc_tune_set.argtypes = [_P, _I, _I]
 lib.sdc_tune_set.restype = _I
 lib.sdc_tune_get.argtypes = [_P, C.POINTER(_I), C.POINTER(_I)]
@@ -418,6 +429,9 @@ class Handle:
         g = torch.empty((n, n), dtype=torch.float64, device=f"cuda:{self.device}")
         _check(lib.sdc_gaussian(self._h, n, seed, tag, g.data_ptr(), n))
         return g.t()
+
+    def graphs_enable(self, on: bool = True):
+        _check(lib.sdc_graphs_enable(self._h, 1 if on else 0))
 
     def tune_set(self, nb64_min_fp64: int, nb64_min_fp32: int):
         _check(lib.sdc_tune_set(self._h, nb64_min_fp64, nb64_min_fp32))

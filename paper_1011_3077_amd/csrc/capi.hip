@@ -163,6 +163,7 @@ sdc_status_t sdc_destroy(sdc_handle_t handle) {
     if (h.dstage) (void)hipFree(h.dstage);
     if (h.ev_sync) (void)hipEventDestroy(h.ev_sync);
     if (h.ev_desc) (void)hipEventDestroy(h.ev_desc);
+    sdc::release_graph_stream(h);
     sdc::release_streams(h);
     delete handle;
     return SDC_OK;
@@ -417,6 +418,18 @@ sdc_status_t sdc_gaussian(sdc_handle_t hd, int n, uint64_t seed, int tag, double
 // ---------------------------------------------------------------------------
 static int tune_to_api(int v) { return v >= sdc::kNb64Never ? SDC_PANEL64_NEVER : v; }
 static int tune_from_api(int v) { return v < 0 ? sdc::kNb64Never : v; }
+
+sdc_status_t sdc_graphs_enable(sdc_handle_t hd, int on) {
+    if (!hd) return SDC_ERR_INVALID;
+    Handle& h = hd->h;
+    if (on && h.no_alloc) return SDC_ERR_INVALID;
+    if (on) {
+        if (use_device(h) != SDC_OK) return SDC_ERR_DEVICE;
+        if (sdc::ensure_graph_stream(h) != SDC_OK) return SDC_ERR_DEVICE;
+    }
+    h.graphs = on != 0;
+    return SDC_OK;
+}
 
 sdc_status_t sdc_tune_set(sdc_handle_t hd, int nb64_min_fp64, int nb64_min_fp32) {
     if (!hd) return SDC_ERR_INVALID;

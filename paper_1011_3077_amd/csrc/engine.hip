@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <limits>
@@ -191,6 +192,156 @@ template <typename T> static int irs_tick(Handle& h, std::vector<IrsSide<T>*>& s
         if (!stop && it + 1 > s.maxit) stop = true;
         if (stop) s.done = 1;
         else ++*left;
+    }
+    return SDC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Replay of the repeated squaring from a HIP graph.  One iteration of every
+// side not yet done (the fill of the norm staging, the QRs of each panel
+// width with their two-stream look-ahead, the post kernel) is captured once
+// on the handle's graph stream and replayed per tick.  Everything the graph
+// reads stays where it was at capture: the descriptors are uploaded before
+// the capture and kept in the arena until the loop ends, the norms go to
+// the same staging slots, and nothing inside the capture copies memory,
+// records or waits for an event, or synchronizes: it holds kernel launches
+// on one stream only.  A side whose test has passed is
+// switched off between replays by a four-byte copy of the `active` field of
+// its resident descriptors (kernels skip inactive problems), so every
+// replay runs the same launches as the direct path over the remaining sides
+// and each side's result is bitwise the same.
+// ---------------------------------------------------------------------------
+template <typename T> struct IrsGraph {
+    std::vector<IrsSide<T>*> act;
+    std::vector<size_t> qoff;  // arena offset of each uploaded QrDesc (width-32 group first)
+    std::vector<int> qside;    // its side (index into act)
+    size_t poff = 0;           // arena offset of the IrsDesc array (one per side, act order)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    IrsGraph() = default;
+    IrsGraph(const IrsGraph&) = delete;
+    IrsGraph& operator=(const IrsGraph&) = delete;
+    ~IrsGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+static bool use_graphs(const Handle& h) { return h.graphs && !h.prof.on && !h.no_alloc; }
+
+// Only QRs on one stream are captured: every side below kLookaheadMinN
+// factored columns.  (Capturing the two-stream look-ahead schedule, whose
+// second and third streams join the capture through event waits, ended in a
+// host segmentation fault at order 1300, in the runtime; larger problems
+// keep the direct launches, where the launch rate matters least.)
+template <typename T> static bool graphable(const std::vector<IrsSide<T>*>& sides) {
+    for (const IrsSide<T>* sp : sides)
+        if (sp->started && !sp->done && sp->n >= kLookaheadMinN) return false;
+    return true;
+}
+
+template <typename T> static int irs_graph_build(Handle& h, std::vector<IrsSide<T>*>& sides, IrsGraph<T>& g) {
+    if (!graphable(sides)) return SDC_ERR_INVALID;  // never captures the two-stream schedule
+    for (IrsSide<T>* sp : sides)
+        if (sp->started && !sp->done) g.act.push_back(sp);
+    const int cnt = (int)g.act.size();
+    if (!cnt) return SDC_OK;
+    CHK(ensure_dnorm(h, 4 * (size_t)cnt));
+    CHK(ensure_host(h, sizeof(double) * 4 * cnt));
+    CHK(ensure_graph_stream(h));
+    std::vector<QrDesc<T>> all(cnt);
+    std::vector<IrsDesc<T>> pd(cnt);
+    for (int i = 0; i < cnt; ++i) {
+        IrsSide<T>& s = *g.act[i];
+        s.norms = h.dnorm + 4 * i;
+        all[i] = qr_desc<T>(s.W, s.ld, 2 * s.n, s.n, 3 * s.n, s.Tm, s.diag, s.counters, s.nb);
+        pd[i] = IrsDesc<T>{s.W, s.n, s.ld, s.Rprev, s.diag, s.norms, 1};
+    }
+    std::vector<QrDesc<T>> grp[2];
+    const QrDesc<T>* dgrp[2] = {nullptr, nullptr};
+    for (int w = 0; w < 2; ++w) {
+        for (int i = 0; i < cnt; ++i)
+            if ((all[i].nb == 64) == (w == 1)) {
+                grp[w].push_back(all[i]);
+                g.qside.push_back(i);
+            }
+        if (grp[w].empty()) continue;
+        UPLOAD(dv, grp[w]);
+        dgrp[w] = dv;
+        for (size_t j = 0; j < grp[w].size(); ++j)
+            g.qoff.push_back((size_t)(reinterpret_cast<const char*>(dv + j) - h.desc_d));
+    }
+    UPLOAD(dp, pd);
+    g.poff = (size_t)(reinterpret_cast<const char*>(dp) - h.desc_d);
+    // the uploads have run before the capture starts
+    HIPCHK(hipStreamSynchronize(h.stream));
+    h.desc_dirty = 0;
+    HIPCHK(hipStreamBeginCapture(h.gstream, hipStreamCaptureModeThreadLocal));
+    fill<double>(h.dnorm, 4 * (size_t)cnt, 0.0, h.gstream);
+    for (int w = 0; w < 2; ++w)
+        if (!grp[w].empty()) qr_aug_batch<T>(dgrp[w], grp[w].data(), (int)grp[w].size(), h.gstream, nullptr);
+    irs_post_batch<T>(dp, pd.data(), cnt, 0, h.gstream);
+    const hipError_t launch = hipGetLastError();
+    const hipError_t end = hipStreamEndCapture(h.gstream, &g.graph);
+    if (launch != hipSuccess || end != hipSuccess || !g.graph) return SDC_ERR_DEVICE;
+    HIPCHK(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+    return SDC_OK;
+}
+
+// One replay: the same bookkeeping as irs_tick for the sides not yet done.
+template <typename T> static int irs_graph_tick(Handle& h, IrsGraph<T>& g, int* left) {
+    *left = 0;
+    const int cnt = (int)g.act.size();
+    bool any = false;
+    for (IrsSide<T>* s : g.act) any = any || !s->done;
+    if (!any) return SDC_OK;
+    HIPCHK(hipEventRecord(h.gev[0], h.stream));
+    HIPCHK(hipStreamWaitEvent(h.gstream, h.gev[0], 0));
+    HIPCHK(hipGraphLaunch(g.exec, h.gstream));
+    HIPCHK(hipEventRecord(h.gev[1], h.gstream));
+    HIPCHK(hipStreamWaitEvent(h.stream, h.gev[1], 0));
+    double* hn = reinterpret_cast<double*>(h.host);
+    HIPCHK(hipMemcpyAsync(hn, h.dnorm, sizeof(double) * 4 * cnt, hipMemcpyDeviceToHost, h.stream));
+    CHK(sync_spin(h));
+    std::vector<int> fin;
+    for (int i = 0; i < cnt; ++i) {
+        IrsSide<T>& s = *g.act[i];
+        if (s.done) continue;
+        const int it = s.p;  // iteration index j of Alg. 3
+        const double diff = hn[4 * i], ref = hn[4 * i + 1], cur = hn[4 * i + 2];
+        s.p = it + 1;
+        bool stop = false;
+        if (!std::isfinite(cur) || (it > 0 && !std::isfinite(diff))) {
+            s.nonfinite = 1;
+            stop = true;
+        } else if (it > 0) {
+            s.rconv = ref > 0 ? diff / ref : INFINITY;
+            if (diff <= s.tau * ref) {
+                s.converged = 1;
+                stop = true;
+            }
+        }
+        if (!stop && it + 1 > s.maxit) stop = true;
+        if (stop) {
+            s.done = 1;
+            fin.push_back(i);
+        } else {
+            ++*left;
+        }
+    }
+    if (*left == 0 || fin.empty()) return SDC_OK;
+    // switch the finished sides off before the next replay (it waits for h.stream)
+    auto off = [&](size_t at) -> int {
+        const int zero = 0;
+        std::memcpy(h.desc_h + at, &zero, sizeof zero);
+        HIPCHK(hipMemcpyAsync(h.desc_d + at, h.desc_h + at, sizeof zero, hipMemcpyHostToDevice, h.stream));
+        h.desc_dirty = std::max(h.desc_dirty, at + sizeof zero);
+        return SDC_OK;
+    };
+    for (int i : fin) {
+        CHK(off(g.poff + (size_t)i * sizeof(IrsDesc<T>) + offsetof(IrsDesc<T>, active)));
+        for (size_t j = 0; j < g.qside.size(); ++j)
+            if (g.qside[j] == i) CHK(off(g.qoff[j] + offsetof(QrDesc<T>, active)));
     }
     return SDC_OK;
 }
@@ -983,9 +1134,24 @@ int run_split_jobs(Handle& h, std::vector<SplitJob>& jobs) {
     collect_sides(wsp, sd, sf);
     CHK(irs_start<double>(h, sd));
     CHK(irs_start<float>(h, sf));
-    for (int l64 = 1, l32 = 1; l64 || l32;) {
-        CHK(irs_tick<double>(h, sd, &l64));
-        CHK(irs_tick<float>(h, sf, &l32));
+    if (use_graphs(h)) {
+        // per precision: replayed from a graph, or launched directly
+        IrsGraph<double> g64;
+        IrsGraph<float> g32;
+        const bool gr64 = graphable(sd), gr32 = graphable(sf);
+        if (gr64) CHK(irs_graph_build<double>(h, sd, g64));
+        if (gr32) CHK(irs_graph_build<float>(h, sf, g32));
+        for (int l64 = 1, l32 = 1; l64 || l32;) {
+            if (gr64) CHK(irs_graph_tick<double>(h, g64, &l64));
+            else CHK(irs_tick<double>(h, sd, &l64));
+            if (gr32) CHK(irs_graph_tick<float>(h, g32, &l32));
+            else CHK(irs_tick<float>(h, sf, &l32));
+        }
+    } else {
+        for (int l64 = 1, l32 = 1; l64 || l32;) {
+            CHK(irs_tick<double>(h, sd, &l64));
+            CHK(irs_tick<float>(h, sf, &l32));
+        }
     }
     h.desc_off = 0;
     CHK(finish_jobs(h, wsp));

@@ -63,6 +63,12 @@ struct Handle {
     // every buffer above was handed in from preallocated memory: the
     // ensure_* helpers report SDC_ERR_NOMEM instead of allocating
     bool no_alloc = false;
+    // replay of the repeated-squaring iterations from a HIP graph
+    // (sdc_graphs_enable): graphs on; the capture / replay stream and the
+    // events that order it after and before `stream` (created on first use)
+    bool graphs = false;
+    hipStream_t gstream = nullptr;
+    hipEvent_t gev[2] = {nullptr, nullptr};
     // QR panel width table: problems with at least nb64_min[p] factored
     // columns use 64-column panels ([0] FP64 iterates, [1] FP32 iterates);
     // set by sdc_tune_set / sdc_autotune

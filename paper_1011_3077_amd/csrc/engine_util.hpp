@@ -95,6 +95,24 @@ inline int ensure_streams(Handle& h) {
         if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return SDC_ERR_DEVICE;
     return SDC_OK;
 }
+// Stream and events of the graph replay.
+inline int ensure_graph_stream(Handle& h) {
+    if (h.gstream) return SDC_OK;
+    if (h.no_alloc) return SDC_ERR_DEVICE;
+    if (hipStreamCreateWithFlags(&h.gstream, hipStreamNonBlocking) != hipSuccess) return SDC_ERR_DEVICE;
+    for (hipEvent_t& e : h.gev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return SDC_ERR_DEVICE;
+    return SDC_OK;
+}
+inline void release_graph_stream(Handle& h) {
+    if (h.gstream) (void)hipStreamSynchronize(h.gstream);
+    for (hipEvent_t& e : h.gev) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+    }
+    if (h.gstream) (void)hipStreamDestroy(h.gstream);
+    h.gstream = nullptr;
+}
 inline void release_streams(Handle& h) {
     if (h.qs.crit) (void)hipStreamSynchronize(h.qs.crit);
     if (h.qs.rest) (void)hipStreamSynchronize(h.qs.rest);
