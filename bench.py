@@ -370,24 +370,34 @@ def other_configs(P, h):
         "runs": len(ts)}
     log(f"[bench] order 128: {ms:.2f} ms")
 
-    # order-2048 pencil divide-and-conquer to blocks <= 64, FP64
+    # order-2048 pencil divide-and-conquer to blocks <= 64, then the leaf
+    # blocks' eigenvalues (the whole eigenvalue solve on the GPU), FP64
     pb = S.pencil_problem(2048, S.family_seed(1))
     A, B = dev(pb["A"]), dev(pb["B"])
-    r, ts = timed(lambda: h.eig_dc(A, B, leaf_max=64, o=P.opts(seed=1)), 3, 1)
+
+    def c1_solve():
+        rr = h.eig_dc(A, B, leaf_max=64, o=P.opts(seed=1))
+        return rr, h.block_eigvals(rr[1], rr[2], rr[5], symmetric=False)
+
+    (r, (wr, wi)), ts = timed(c1_solve, 3, 1)
     st, t, s_, ql, qr, starts, info = r
+    got = np.sort_complex(wr.cpu().numpy() + 1j * wi.cpu().numpy())
     t, s_ = t.cpu().numpy(), s_.cpu().numpy()
-    got = np.sort_complex(np.concatenate([sla.eigvals(t[a0:a1, a0:a1], s_[a0:a1, a0:a1])
+    lap = np.sort_complex(np.concatenate([sla.eigvals(t[a0:a1, a0:a1], s_[a0:a1, a0:a1])
                                           for a0, a1 in zip(starts[:-1], starts[1:])]))
     want = np.sort_complex(pb["lam"].astype(complex))
     ms = statistics.mean(ts)
     out["pencil2048_dc_fp64"] = {
-        "workload": "divide-and-conquer of the order-2048 real pencil (unit circle, then blocks <= 64), FP64",
+        "workload": "divide-and-conquer of the order-2048 real pencil (unit circle, then blocks <= 64) and the "
+                    "blocks' eigenvalues, FP64",
         "ms": ms, "gflops": info["nominal_flops"] / ms / 1e6,
         "pct_fp64_peak": info["nominal_flops"] / ms / 1e6 / (PEAK["fp64_tflops"] * 1e3),
         "nominal_flops": info["nominal_flops"], "splits": info["splits"], "accepted": info["accepted"],
         "blocks": info["nblocks"], "unsplit": info["unsplit"],
-        "nominal_flops_note": "every split attempt counted, including those that divided nothing",
-        "eig_rel_err_vs_construction": float(np.max(np.abs(got - want) / np.abs(want))), "runs": len(ts)}
+        "nominal_flops_note": "every split attempt counted, including those that divided nothing; the leaf "
+                              "eigenvalue solve is timed but not credited",
+        "eig_rel_err_vs_construction": float(np.max(np.abs(got - want) / np.abs(want))),
+        "eig_rel_err_lapack_on_same_blocks": float(np.max(np.abs(lap - want) / np.abs(want))), "runs": len(ts)}
     log(f"[bench] order-2048 pencil recursion: {ms:.1f} ms")
     del A, B
 

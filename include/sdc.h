@@ -316,12 +316,17 @@ sdc_status_t sdc_split_svd(sdc_handle_t h, int m, int n, const double* A, int ld
  *     off-diagonal norm of 1e-15 of the block's); its eigenvalues go to
  *     wr[start .. start + m) in ascending order, wi = 0.  S is not read.
  *   symmetric == 0: each block pair (T_bb, S_bb) of order 1 or 2 gives the
- *     roots of det(T_bb - lambda S_bb) = 0 (order 2: real roots ascending; a
- *     complex pair as (re, +im), (re, -im); an infinite eigenvalue, for a
- *     singular S_bb, as +-inf).  Run sdc_eig_dc with leaf_max = 2 to reduce
- *     a pencil that far.
- *   Any other block (symmetric above order 128, pencil above order 2) gets
- *   NaN in wr and wi.
+ *     roots of det(T_bb - lambda S_bb) = 0 in closed form (order 2: real
+ *     roots ascending; a complex pair as (re, +im), (re, -im); an infinite
+ *     eigenvalue, for a singular S_bb, as +-inf); a block of order 3 to 64
+ *     gives the eigenvalues of S_bb^{-1} T_bb (or the inverted ones of
+ *     T_bb^{-1} S_bb when S_bb is the worse conditioned; an eigenvalue that
+ *     is infinite in exact arithmetic comes out very large) by the
+ *     double-shift QR algorithm, ordered the same way (real ones ascending,
+ *     then the complex pairs by real part); NaN for a block whose matrices
+ *     are both exactly singular or whose iteration did not converge.
+ *   Any other block (symmetric above order 128, pencil above order 64) gets
+ *   NaN in wr and wi (sdc_eig_dc with a smaller leaf_max reduces it).
  * V (optional, symmetric only; n x n, ldv >= n): the diagonal block
  * V[start .. start + m, start .. start + m] receives the block's orthonormal
  * eigenvectors, column i for wr[start + i], for blocks of order <= 64 (NaN for

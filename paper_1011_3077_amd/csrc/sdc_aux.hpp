@@ -62,10 +62,13 @@ void gersh_batch(const GershDesc* d, const GershDesc* h, int count, hipStream_t 
 
 // Eigenvalues of one diagonal block of a block upper-triangular pair
 // (leaf_kernels.hip): a symmetric block of order <= kJacobiMax by cyclic
-// Jacobi, a pencil block (T, S) of order 1 or 2 in closed form, NaN for any
-// other block.  T and S point at the block's first element (column-major).
+// Jacobi, a pencil block (T, S) of order 1 or 2 in closed form and of order
+// <= kPencilMax by the double-shift QR algorithm on S^{-1} T (or on T^{-1} S
+// when S is the worse conditioned of the two), NaN for any other block.  T
+// and S point at the block's first element (column-major).
 constexpr int kJacobiMax = 128;
 constexpr int kJacobiVecMax = 64;  // blocks whose eigenvectors are accumulated too
+constexpr int kPencilMax = 64;
 struct BlockEigDesc {
     const double* T; int ldt;
     const double* S; int lds;   // pencil only
