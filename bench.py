@@ -300,7 +300,10 @@ def sym_flops(n, p):
 
 def cpu_baseline_sym(n: int = 1536):
     """The FP64 oracle on the host's cores: split_sym of one clustered
-    symmetric problem of the headline family at order n (a bounded sample)."""
+    symmetric problem of the headline family at order n (a bounded sample).
+    The same leg also runs the oracle's split of the order-128 problem that
+    other_configs checks the library against (the only place the bench runs
+    the oracle); it is returned beside the timing, untimed."""
     import sdc_synth as S
     import oracle as O
     try:
@@ -313,16 +316,19 @@ def cpu_baseline_sym(n: int = 1536):
     r = O.split_sym(a, {"kind": "halfplane", "shift": 0.0, "scale": 1.0}, seed=1)
     dt = time.perf_counter() - t0
     flops = sym_flops(n, r.p_right)
+    a128, _, _ = S.sym_problem(128, S.family_seed(0))
+    ref128 = O.split_sym(a128, {"kind": "halfplane", "shift": 0.0, "scale": 1.0}, seed=1)
     return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
             "sample": f"oracle split_sym (half plane Re z < 0) of one clustered symmetric order-{n} problem of "
                       f"the same family, p={r.p_right}, {dt:.1f} s, nominal {flops:.3e} flops",
-            "seconds": dt}
+            "seconds": dt}, {"sym128": (ref128.k, ref128.Q, ref128.A_hat)}
 
 
-def other_configs(P, h):
+def other_configs(P, h, refs=None):
     """The other configurations, measured briefly beside the headline line:
     the order-128 symmetric split (latency, FP64; median of 10 after 3
-    warm-ups, checked against the oracle), the order-2048 pencil
+    warm-ups, checked against the oracle's split of the same problem when
+    the CPU leg has run it: `refs`), the order-2048 pencil
     divide-and-conquer to blocks <= 64 (FP64; mean of 3 after 1 warm-up), and
     512 symmetric problems with n log-uniform in [32, 256] in one batched
     FP32+refine call (median of 3 after 1 warm-up).  Inputs resident in HBM;
@@ -332,7 +338,6 @@ def other_configs(P, h):
     import scipy.linalg as sla
     import torch
     import sdc_synth as S
-    import oracle as O
     dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
     half = P.region("halfplane", shift=0.0, scale=1.0)
     out = {}
@@ -353,21 +358,24 @@ def other_configs(P, h):
     A = dev(a)
     r, ts = timed(lambda: h.split_sym(A, half, P.opts(seed=1)), 10, 3)
     k = r.info["k_lead"]
-    ref = O.split_sym(a, {"kind": "halfplane", "shift": 0.0, "scale": 1.0}, seed=1)
     ah = r.Ahat.cpu().numpy()
     ev = np.sort(np.concatenate([np.linalg.eigvalsh(ah[:k, :k]), np.linalg.eigvalsh(ah[k:, k:])]))
-    ev_ref = np.sort(np.concatenate([np.linalg.eigvalsh(ref.A_hat[:k, :k]), np.linalg.eigvalsh(ref.A_hat[k:, k:])]))
-    qs, qo = r.Q.cpu().numpy()[:, :k], ref.Q[:, :k]
+    vs_oracle = {"eig_abs_err_vs_oracle": None, "subspace_sin_vs_oracle": None, "oracle_k": None}
+    if refs and "sym128" in refs:
+        k_o, q_o, ah_o = refs["sym128"]
+        ev_ref = np.sort(np.concatenate([np.linalg.eigvalsh(ah_o[:k, :k]), np.linalg.eigvalsh(ah_o[k:, k:])]))
+        qs, qo = r.Q.cpu().numpy()[:, :k], q_o[:, :k]
+        vs_oracle = {"eig_abs_err_vs_oracle": float(np.abs(ev - ev_ref).max()),
+                     "subspace_sin_vs_oracle": float(np.linalg.norm(qo - qs @ (qs.T @ qo), 2)), "oracle_k": int(k_o)}
     ms = statistics.median(ts)
     fl = sym_flops(128, r.info["iters_right"])
     out["sym128_fp64"] = {
         "workload": "symmetric split of one order-128 problem at Re z < 0 (FP64)", "ms": ms,
         "gflops": fl / ms / 1e6, "pct_fp64_peak": fl / ms / 1e6 / (PEAK["fp64_tflops"] * 1e3),
-        "iters": r.info["iters_right"], "k": k, "exact_rank": r.status == 0 and k == int((d > 0).sum()) == ref.k,
-        "e21_rel": r.info["e21_rel"],
-        "eig_abs_err_vs_oracle": float(np.abs(ev - ev_ref).max()),
-        "subspace_sin_vs_oracle": float(np.linalg.norm(qo - qs @ (qs.T @ qo), 2)),
-        "runs": len(ts)}
+        "iters": r.info["iters_right"], "k": k,
+        "exact_rank": r.status == 0 and k == int((d > 0).sum()) and vs_oracle["oracle_k"] in (None, k),
+        "e21_rel": r.info["e21_rel"], "eig_abs_err_vs_construction": float(np.abs(ev - np.sort(d)).max()),
+        **vs_oracle, "runs": len(ts)}
     log(f"[bench] order 128: {ms:.2f} ms")
 
     # order-2048 pencil divide-and-conquer to blocks <= 64, then the leaf
@@ -435,6 +443,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-launch events")
     ap.add_argument("--no-extras", action="store_true", help="skip the other configurations")
+    ap.add_argument("--extras-only", action="store_true",
+                    help="only the other configurations (order 128, the order-2048 pencil recursion and its leaf "
+                         "eigenvalues, the 512-problem batch), one JSON line; for profiling them alone")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (reference kernel for HBM counters)")
     ap.add_argument("--serve", action="store_true", help="serving benchmark instead (see serve_main)")
@@ -460,6 +471,11 @@ def main():
         return serve_main(args)
     if args.suite:
         return suite_main(args)
+    if args.extras_only:
+        h = P.Handle(0)
+        print(json.dumps({"other_configs": other_configs(P, h), "n_gpus": 1, "data": "synthetic"}), flush=True)
+        h.close()
+        return 0
     if args.calibrate_copy:
         x = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
         y = torch.empty_like(x)
@@ -530,11 +546,17 @@ def main():
         torch.cuda.synchronize()
         stats32 = {k: h.profile_read(k) for k in (P.KERNEL_UPDATE, P.KERNEL_PANEL, P.KERNEL_GEMM, P.KERNEL_LA)}
         h.profile_enable(False)
+    # the CPU leg (the oracle on the host cores; it also gives the oracle's
+    # reference for the order-128 check below)
+    cpu, refs = None, None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        cpu, refs = cpu_baseline_sym()
     extras = None
     if not args.no_extras:
         del A
         torch.cuda.empty_cache()
-        extras = other_configs(P, h)
+        extras = other_configs(P, h, refs)
     h.close()
 
     value = flops / dt / 1e9
@@ -545,10 +567,6 @@ def main():
         tr = TRAFFIC if (TRAFFIC and TRAFFIC.get("sha256") == kernel_sources_sha() and TRAFFIC.get("n") == n) else None
         roof = _roofline(P, stats64, P.KERNEL_UPDATE, names, PEAK["fp64_tflops"], tr)
         roof32 = _roofline(P, stats32, P.KERNEL_UPDATE, kernel_names(P, "f32"), PEAK["fp32_tflops"])
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle)")
-        cpu = cpu_baseline_sym()
     out = {
         "metric": "split GFLOP/s (nominal split flops / wall time), FP64; FP32+refine beside it",
         "value": value,
