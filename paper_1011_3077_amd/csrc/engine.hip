@@ -1135,7 +1135,16 @@ int run_split_jobs(Handle& h, std::vector<SplitJob>& jobs) {
     CHK(irs_start<double>(h, sd));
     CHK(irs_start<float>(h, sf));
     if (use_graphs(h)) {
-        // per precision: replayed from a graph, or launched directly
+        // per precision: replayed from a graph, or launched directly.  The
+        // norm staging is sized for both precisions first: a graph keeps the
+        // address it was captured with, so nothing may reallocate it while
+        // the loop runs (the direct ticks then find it large enough).
+        size_t most = 0, c64 = 0, c32 = 0;
+        for (IrsSide<double>* sp : sd) c64 += (sp->started && !sp->done) ? 1 : 0;
+        for (IrsSide<float>* sp : sf) c32 += (sp->started && !sp->done) ? 1 : 0;
+        most = std::max(c64, c32);
+        CHK(ensure_dnorm(h, 4 * most));
+        CHK(ensure_host(h, sizeof(double) * 4 * most));
         IrsGraph<double> g64;
         IrsGraph<float> g32;
         const bool gr64 = graphable(sd), gr32 = graphable(sf);
