@@ -389,6 +389,15 @@ typedef struct {
  * SDC_ERR_INVALID for the no-allocation handle. */
 sdc_status_t sdc_graphs_enable(sdc_handle_t h, int on);
 
+/* QR schedule of the repeated squaring and the rank-revealing QRs (Alg. 3,
+ * Alg. 1; the TSQR panel of Sec. 4.2): with on != 0 (the default), a
+ * 32-column panel whose reduction tree has more than one level and that has
+ * no look-ahead part (problems below 1200 factored columns) has the levels
+ * above its leaves factored in the same launch as the leaves' trailing
+ * update, which does not depend on them; with on == 0 the whole tree is
+ * factored first.  Results are bitwise the same either way. */
+sdc_status_t sdc_tree_overlap_enable(sdc_handle_t h, int on);
+
 /* Enable (on != 0) or disable profiling; either way the totals are reset. */
 sdc_status_t sdc_profile_enable(sdc_handle_t h, int on);
 /* Totals of `kernel` (0 to 3 as above) since the last enable. */

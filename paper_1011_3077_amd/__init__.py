@@ -41,6 +41,7 @@ EXPORTED = ["sdc_opts_default", "sdc_create", "sdc_destroy", "sdc_status_string"
             "sdc_block_eigvals", "sdc_trevc",
             "sdc_gaussian", "sdc_tune_set", "sdc_tune_get", "sdc_autotune", "sdc_tune_save", "sdc_tune_load",
             "sdc_graphs_enable",
+            "sdc_tree_overlap_enable",
             "sdc_profile_enable", "sdc_profile_read", "sdc_server_create", "sdc_server_submit",
             "sdc_server_poll", "sdc_server_wait", "sdc_server_stats", "sdc_server_destroy"]
 SDC_REQ_SYM, SDC_REQ_PENCIL = 0, 1
@@ -162,6 +163,8 @@ lib.sdc_gaussian.argtypes = [_P, _I, C.c_uint64, _I, _P, _I]
 lib.sdc_gaussian.restype = _I
 lib.sdc_graphs_enable.argtypes = [_P, _I]
 lib.sdc_graphs_enable.restype = _I
+lib.sdc_tree_overlap_enable.argtypes = [_P, _I]
+lib.sdc_tree_overlap_enable.restype = _I
 lib.sdc_tune_set.argtypes = [_P, _I, _I]
 lib.sdc_tune_set.restype = _I
 lib.sdc_tune_get.argtypes = [_P, C.POINTER(_I), C.POINTER(_I)]
@@ -432,6 +435,11 @@ class Handle:
 
     def graphs_enable(self, on: bool = True):
         _check(lib.sdc_graphs_enable(self._h, 1 if on else 0))
+
+    def tree_overlap_enable(self, on: bool = True):
+        """Factor a QR panel's tree above its leaves beside the leaves'
+        trailing update (on, the default) or before it; bitwise the same."""
+        _check(lib.sdc_tree_overlap_enable(self._h, 1 if on else 0))
 
     def tune_set(self, nb64_min_fp64: int, nb64_min_fp32: int):
         _check(lib.sdc_tune_set(self._h, nb64_min_fp64, nb64_min_fp32))

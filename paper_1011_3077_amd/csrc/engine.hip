@@ -116,7 +116,7 @@ template <typename T> static int run_qr_grouped(Handle& h, const std::vector<QrD
             if (d.nb == nb) g.push_back(d);
         if (g.empty()) continue;
         UPLOAD(dg, g);
-        qr_aug_batch<T>(dg, g.data(), (int)g.size(), h.stream, lookahead(h, g));
+        qr_aug_batch<T>(dg, g.data(), (int)g.size(), h.stream, lookahead(h, g), h.tree_overlap);
     }
     return SDC_OK;
 }
@@ -279,7 +279,8 @@ template <typename T> static int irs_graph_build(Handle& h, std::vector<IrsSide<
     HIPCHK(hipStreamBeginCapture(h.gstream, hipStreamCaptureModeThreadLocal));
     fill<double>(h.dnorm, 4 * (size_t)cnt, 0.0, h.gstream);
     for (int w = 0; w < 2; ++w)
-        if (!grp[w].empty()) qr_aug_batch<T>(dgrp[w], grp[w].data(), (int)grp[w].size(), h.gstream, nullptr);
+        if (!grp[w].empty())
+            qr_aug_batch<T>(dgrp[w], grp[w].data(), (int)grp[w].size(), h.gstream, nullptr, h.tree_overlap);
     irs_post_batch<T>(dp, pd.data(), cnt, 0, h.gstream);
     const hipError_t launch = hipGetLastError();
     const hipError_t end = hipStreamEndCapture(h.gstream, &g.graph);

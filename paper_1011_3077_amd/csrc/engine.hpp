@@ -73,6 +73,9 @@ struct Handle {
     // columns use 64-column panels ([0] FP64 iterates, [1] FP32 iterates);
     // set by sdc_tune_set / sdc_autotune
     int nb64_min[2] = {kNb64MinFp64, kNb64MinFp32};
+    // QR schedule (sdc_tree_overlap_enable): the panel tree above the leaves
+    // factored in the launch of the leaf-level trailing update
+    bool tree_overlap = true;
 };
 
 // Panel width (32 or 64) of a QR with nf factored columns: `forced` (the

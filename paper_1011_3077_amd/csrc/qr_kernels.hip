@@ -52,8 +52,20 @@ template <typename T> struct RawBuf {
 // ---------------------------------------------------------------------------
 // Cross-lane moves inside one wavefront (T = float or double).
 // ---------------------------------------------------------------------------
+// Every control used here (quad permutes and row mirrors, all rows and banks
+// enabled) writes every lane from a valid source lane, so the move needs no
+// old value: a plain DPP move per 32-bit half, without the register
+// initialisation (and its hazard wait) that an update with an old value of
+// zero costs.
 template <int CTRL, typename T> __device__ __forceinline__ T lane_dpp(T v) {
-    return __builtin_amdgcn_update_dpp(T(0), v, CTRL, 0xF, 0xF, false);
+    if constexpr (sizeof(T) == 8) {
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+        const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, false);
+        const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+        return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+    } else {
+        return __builtin_bit_cast(T, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+    }
 }
 constexpr int kDppXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]: lane ^ 1
 constexpr int kDppXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]: lane ^ 2
@@ -370,8 +382,104 @@ __device__ __forceinline__ void factor_node(T* s_tile, int mt, int nbk, T* s_x, 
     else factor_tile_rows<T, 4, NB>(s_tile, mt, nbk, s_x, s_sc, s_tau, s_beta, Tg);
 }
 
+// LDS of one panel workgroup: the node tile (column-major, stride
+// MT_MAX + 1), the published column (two steps in flight), the step scalars
+// and the reflector scalars.
+template <typename T> struct PanelSmem {
+    T* tile;
+    T* x;
+    T* sc;
+    T* tau;
+    T* beta;
+};
+
+// Internal node `node` at tree level `level` (>= 1), whose nch children are
+// factored: their stacked upper-triangular R factors are factored in place,
+// its T goes to the T buffer, its explicit reflectors to the internal
+// reflector buffer and its R into the first child's top rows.
 template <typename T, int NBW>
-__global__ __launch_bounds__(256) void k_panel(const QrDesc<T>* __restrict__ descs, int c0) {
+__device__ __forceinline__ void panel_internal_node(const QrDesc<T>& d, const RawBuf<T>& bw,
+                                                    const TreeGeomT<T, NBW>& g, int c0, int mp, int nbk, int level,
+                                                    int node, int nch, const PanelSmem<T>& sm) {
+    using C = QrCfg<T, NBW>;
+    constexpr int NB = C::NB, LDT = C::MT_MAX + 1;
+    T* const s_tile = sm.tile;
+    const int tid = threadIdx.x;
+    const int ld = d.ld;
+    const int par = (c0 / NB) & 1;
+    const int iidx = internal_index(g, level, node);
+    const int mt = nch * NB;
+    // stacked upper-triangular R factors of the children (row s of the
+    // stack is row s % NB of child s / NB)
+    {
+        const int s = tid, t = s / NB, r = s % NB;
+        const int rb = s < mt ? c0 + leaf_lo((node * C::F + t) * g.pw(level - 1), mp, g.L(0)) : 0;
+        const unsigned vo = s < mt ? (unsigned)((rb + r) * sizeof(T)) : kOob;
+        T v[NB];
+#pragma unroll
+        for (int col = 0; col < NB; ++col) {
+            const T x = bw.load(vo + (unsigned)(col * ld * sizeof(T)));
+            v[col] = r <= col ? x : T(0);
+        }
+#pragma unroll
+        for (int col = 0; col < NB; ++col) s_tile[col * LDT + s] = v[col];
+    }
+    __syncthreads();
+    factor_node<T, NBW>(s_tile, mt, nbk, sm.x, sm.sc, sm.tau, sm.beta,
+                        (par ? d.Tm[1] : d.Tm[0]) + (size_t)node_index(g, level, node, d.tm_leaves) * NB * NB);
+    // explicit reflectors of this node, and its R into the top rows
+    const RawBuf<T> bvi((par ? d.Vint[1] : d.Vint[0]) + (size_t)iidx * C::MT_MAX * NB,
+                        (unsigned)(C::MT_MAX * NB * sizeof(T)));
+    const int rbase = c0 + leaf_lo(node * g.pw(level), mp, g.L(0));
+    {
+        const int s = tid;
+#pragma unroll
+        for (int col = 0; col < NB; ++col) {
+            const T x = s_tile[col * LDT + s];
+            const T v = (s < mt && col < nbk) ? (s > col ? x : (s == col ? T(1) : T(0))) : T(0);
+            bvi.store(v, (unsigned)((col * C::MT_MAX + s) * sizeof(T)));
+            // R: the upper triangle into the first child's top rows
+            if (s < NB) bw.store(x, s <= col ? (unsigned)(((size_t)col * ld + rbase + s) * sizeof(T)) : kOob);
+        }
+    }
+}
+
+// Climb from a node factored by this workgroup at `level`: the last child
+// to arrive at each parent (counted with an atomic) factors it; the
+// workgroup that factors the root writes the diagonal of R.
+template <typename T, int NBW>
+__device__ __forceinline__ void panel_climb(const QrDesc<T>& d, const RawBuf<T>& bw, const TreeGeomT<T, NBW>& g,
+                                            int c0, int mp, int nbk, int level, int node, const PanelSmem<T>& sm,
+                                            int* s_last) {
+    using C = QrCfg<T, NBW>;
+    const int tid = threadIdx.x;
+    for (++level; level < g.levels; ++level) {
+        __threadfence();
+        __syncthreads();
+        const int parent = node / C::F;
+        const int iidx = internal_index(g, level, parent);
+        const int nch = min(C::F, g.L(level - 1) - parent * C::F);
+        if (tid == 0) {
+            const unsigned old = atomicAdd(&d.counters[iidx], 1u);
+            *s_last = (old == (unsigned)(nch - 1));
+            if (*s_last) d.counters[iidx] = 0u;
+        }
+        __syncthreads();
+        if (!*s_last) return;
+        __threadfence();
+        node = parent;
+        panel_internal_node<T, NBW>(d, bw, g, c0, mp, nbk, level, node, nch, sm);
+    }
+    if (tid < nbk) d.diag[c0 + tid] = sm.beta[tid];
+}
+
+// Panel factorization of columns [c0, c0 + NB): one workgroup per leaf
+// (blockIdx.x) and problem (blockIdx.y).  With leaves_only set and a tree of
+// more than one level, the workgroups stop after their leaves and the
+// levels above are left to the leaf-level trailing update's launch
+// (k_update with CLIMB), which factors them beside the update.
+template <typename T, int NBW>
+__global__ __launch_bounds__(256) void k_panel(const QrDesc<T>* __restrict__ descs, int c0, int leaves_only) {
     using C = QrCfg<T, NBW>;
     constexpr int NB = C::NB, LDT = C::MT_MAX + 1, PT = C::PT;
     __shared__ T s_tile[LDT * NB];
@@ -379,31 +487,31 @@ __global__ __launch_bounds__(256) void k_panel(const QrDesc<T>* __restrict__ des
     __shared__ T s_sc[4];
     __shared__ T s_tau[NB], s_beta[NB];
     __shared__ int s_last;
+    const PanelSmem<T> sm{s_tile, s_x, s_sc, s_tau, s_beta};
 
     const QrDesc<T> d = descs[blockIdx.y];
     if (!d.active || c0 >= d.nf) return;
     const int nbk = min(NB, d.nf - c0);
     const int mp = d.m - c0;
     const auto g = tree_geom<T, NBW>(mp);
-    int node = blockIdx.x;
+    const int node = blockIdx.x;
     if (node >= g.L(0)) return;
     const int par = (c0 / NB) & 1;
     T* const Tm = (par ? d.Tm[1] : d.Tm[0]);
     const int tid = threadIdx.x;
     const int ld = d.ld;
-    T* W = d.W;
     static_assert(C::MT_MAX <= PT, "one node row per thread");
     // the panel's columns as a raw buffer (reads outside it give zero,
     // writes there are dropped: no branches for the columns >= nbk or the
     // rows beyond a node)
-    const RawBuf<T> bw(W + (size_t)c0 * ld, (unsigned)(nbk * ld * sizeof(T)));
+    const RawBuf<T> bw(d.W + (size_t)c0 * ld, (unsigned)(nbk * ld * sizeof(T)));
 
     // ---- leaf: rows [row0, row0 + mt) of the panel columns
     // Each thread moves one whole row (all NB columns), so its global
     // accesses are independent and in flight together; across threads every
     // column access is a contiguous run of rows.
     const int row0 = c0 + leaf_lo(node, mp, g.L(0));
-    int mt = c0 + leaf_lo(node + 1, mp, g.L(0)) - row0;
+    const int mt = c0 + leaf_lo(node + 1, mp, g.L(0)) - row0;
     {
         const unsigned vo = tid < mt ? (unsigned)((row0 + tid) * sizeof(T)) : kOob;
         T v[NB];
@@ -413,63 +521,35 @@ __global__ __launch_bounds__(256) void k_panel(const QrDesc<T>* __restrict__ des
         for (int col = 0; col < NB; ++col) s_tile[col * LDT + tid] = v[col];
         __syncthreads();
         factor_node<T, NBW>(s_tile, mt, nbk, s_x, s_sc, s_tau, s_beta,
-                       Tm + (size_t)node_index(g, 0, node, d.tm_leaves) * NB * NB);
+                            Tm + (size_t)node_index(g, 0, node, d.tm_leaves) * NB * NB);
 #pragma unroll
         for (int col = 0; col < NB; ++col) bw.store(s_tile[col * LDT + tid], vo + (unsigned)(col * ld * sizeof(T)));
     }
-
+    if (leaves_only && g.levels > 1) return;
     // ---- climb the tree: the last child to arrive factors the parent
-    for (int level = 1; level < g.levels; ++level) {
-        __threadfence();
-        __syncthreads();
-        const int parent = node / C::F;
-        const int iidx = internal_index(g, level, parent);
-        const int nch = min(C::F, g.L(level - 1) - parent * C::F);
-        if (tid == 0) {
-            const unsigned old = atomicAdd(&d.counters[iidx], 1u);
-            s_last = (old == (unsigned)(nch - 1));
-            if (s_last) d.counters[iidx] = 0u;
-        }
-        __syncthreads();
-        if (!s_last) return;
-        __threadfence();
-        node = parent;
-        mt = nch * NB;
-        // stacked upper-triangular R factors of the children (row s of the
-        // stack is row s % NB of child s / NB)
-        {
-            const int s = tid, t = s / NB, r = s % NB;
-            const int rb = s < mt ? c0 + leaf_lo((node * C::F + t) * g.pw(level - 1), mp, g.L(0)) : 0;
-            const unsigned vo = s < mt ? (unsigned)((rb + r) * sizeof(T)) : kOob;
-            T v[NB];
-#pragma unroll
-            for (int col = 0; col < NB; ++col) {
-                const T x = bw.load(vo + (unsigned)(col * ld * sizeof(T)));
-                v[col] = r <= col ? x : T(0);
-            }
-#pragma unroll
-            for (int col = 0; col < NB; ++col) s_tile[col * LDT + s] = v[col];
-        }
-        __syncthreads();
-        factor_node<T, NBW>(s_tile, mt, nbk, s_x, s_sc, s_tau, s_beta,
-                       Tm + (size_t)node_index(g, level, node, d.tm_leaves) * NB * NB);
-        // explicit reflectors of this node, and its R into the top rows
-        const RawBuf<T> bvi((par ? d.Vint[1] : d.Vint[0]) + (size_t)iidx * C::MT_MAX * NB,
-                            (unsigned)(C::MT_MAX * NB * sizeof(T)));
-        const int rbase = c0 + leaf_lo(node * g.pw(level), mp, g.L(0));
-        {
-            const int s = tid;
-#pragma unroll
-            for (int col = 0; col < NB; ++col) {
-                const T x = s_tile[col * LDT + s];
-                const T v = (s < mt && col < nbk) ? (s > col ? x : (s == col ? T(1) : T(0))) : T(0);
-                bvi.store(v, (unsigned)((col * C::MT_MAX + s) * sizeof(T)));
-                // R: the upper triangle into the first child's top rows
-                if (s < NB) bw.store(x, s <= col ? (unsigned)(((size_t)col * ld + rbase + s) * sizeof(T)) : kOob);
-            }
-        }
-    }
-    if (tid < nbk) d.diag[c0 + tid] = s_beta[tid];
+    panel_climb<T, NBW>(d, bw, g, c0, mp, nbk, 0, node, sm, &s_last);
+}
+
+// The climbing role of k_update (climb set): level-1 node `node` of problem
+// descs[z], then the levels above it.  Not inlined, so that its registers
+// are allocated apart from the trailing update's (which uses the whole
+// budget of two workgroups per CU).
+template <typename T>
+__device__ __noinline__ void panel_tree_from_level1(const QrDesc<T>* __restrict__ descs, int z, int c0, int node,
+                                                    T* s_v, T* s_xs, int* s_i) {
+    using C = QrCfg<T, 32>;
+    const QrDesc<T> d = descs[z];
+    if (!d.active || c0 >= d.nf) return;
+    const int nbk = min(C::NB, d.nf - c0);
+    const int mp = d.m - c0;
+    const auto g = tree_geom<T, 32>(mp);
+    if (g.levels < 2 || node >= g.L(1)) return;
+    // the node tile in the update's reflector array, the rest in its staging
+    // tiles
+    const PanelSmem<T> sm{s_v, s_xs, s_xs + 2 * C::MT_MAX, s_xs + 2 * C::MT_MAX + 4, s_xs + 2 * C::MT_MAX + 4 + C::NB};
+    const RawBuf<T> bw(d.W + (size_t)c0 * d.ld, (unsigned)(nbk * d.ld * sizeof(T)));
+    panel_internal_node<T, 32>(d, bw, g, c0, mp, nbk, 1, node, min(C::F, g.L(0) - node * C::F), sm);
+    panel_climb<T, 32>(d, bw, g, c0, mp, nbk, 1, node, sm, s_i);
 }
 
 // Apply the transpose of one tree level's block reflectors to a 64-column
@@ -488,7 +568,18 @@ __global__ __launch_bounds__(256) void k_panel(const QrDesc<T>* __restrict__ des
 // Row blocks per group of the update phase of k_update (1, 2 and 4 were
 // measured; 2 was fastest, 1 spills)
 constexpr int kUpdGroup = 2;
-template <typename T, int RB>
+// One workgroup's share of k_update: node `node` of tree level `level`
+// applied to trailing column tile `tile` of problem d.
+// With CLIMB (leaf level only), the workgroups of blockIdx.y = 0 factor
+// the panel's tree above its leaves instead (level-1 node blockIdx.x, then
+// the levels above; k_panel ran with leaves_only) and blockIdx.y = t + 1
+// updates column tile t.  The two touch disjoint data: the update reads the
+// leaves' reflectors below their diagonals and the leaves' T factors and
+// writes only trailing columns; the climb reads and writes the upper
+// triangles of the leaves' top rows, the internal nodes' T factors and
+// reflectors and the tree counters.  The climb works in this kernel's LDS
+// arrays, so two workgroups still fit a CU.
+template <typename T, int RB, bool CLIMB>
 __global__ __launch_bounds__(256, 2) void k_update(const QrDesc<T>* __restrict__ descs, int c0, int level) {
     using C = QrCfg<T, 32>;
     using M = Mfma<T>;
@@ -497,6 +588,14 @@ __global__ __launch_bounds__(256, 2) void k_update(const QrDesc<T>* __restrict__
     __shared__ T s_V[RB * 16 * VS];
     __shared__ T s_X[4 * 16 * XS];
     __shared__ int s_rb[32];
+    static_assert((C::MT_MAX + 1) * C::NB <= RB * 16 * VS && 2 * C::MT_MAX + 4 + 2 * C::NB <= 4 * 16 * XS,
+                  "the panel's LDS fits the update's");
+    if constexpr (CLIMB) {
+        if (blockIdx.y == 0) {
+            panel_tree_from_level1<T>(descs, blockIdx.z, c0, blockIdx.x, s_V, s_X, s_rb);
+            return;
+        }
+    }
 
     const QrDesc<T> d = descs[blockIdx.z];
     if (!d.active || c0 >= d.nf) return;
@@ -504,7 +603,7 @@ __global__ __launch_bounds__(256, 2) void k_update(const QrDesc<T>* __restrict__
     // column range: the trailing columns after those of the row-split kernel
     const int cb = c0 + nbk + row_split_cols(NB, d.nf, c0);
     const int ce = d.ncols;
-    const int col0 = cb + blockIdx.y * 64;
+    const int col0 = cb + (blockIdx.y - (CLIMB ? 1 : 0)) * 64;
     if (col0 >= ce) return;
     const int par = (c0 / NB) & 1;
     const int mp = d.m - c0;
@@ -1329,7 +1428,7 @@ static void launch_update(dim3 grid, hipStream_t s, const QrDesc<T>* d, int c0, 
         hipLaunchKernelGGL(k_update64<T>, grid, dim3(256), 0, s, d, c0, lev);
     } else {
         constexpr int RB = QrCfg<T, 32>::MT_MAX / 16;
-        hipLaunchKernelGGL((k_update<T, RB>), grid, dim3(256), 0, s, d, c0, lev);
+        hipLaunchKernelGGL((k_update<T, RB, false>), grid, dim3(256), 0, s, d, c0, lev);
     }
 }
 template <typename T, int NBW>
@@ -1352,9 +1451,13 @@ static void launch_la(dim3 grid, hipStream_t s, const QrDesc<T>* d, int c0) {
 // writes the other parity's T / reflector buffers while REST(k) reads
 // panel k's.  crit starts after the work already on s, and s waits for both
 // streams before returning.
+// With tree_overlap, a 32-column panel of more than one tree level and no
+// LA part runs as: the leaves of P(k) (k_panel, leaves_only), then one
+// launch with the rest of P(k)'s tree beside REST(k)'s leaf level
+// (k_update with CLIMB), then REST(k)'s upper levels.
 template <typename T, int NBW>
 static void qr_aug_batch_nb(const QrDesc<T>* d_descs, const QrDesc<T>* h, int count, hipStream_t s,
-                            const QrStreams* la) {
+                            const QrStreams* la, bool tree_overlap) {
     using C = QrCfg<T, NBW>;
     int max_nf = 0;
     for (int i = 0; i < count; ++i)
@@ -1409,13 +1512,28 @@ static void qr_aug_batch_nb(const QrDesc<T>* d_descs, const QrDesc<T>* h, int co
             }
         }
         if (maxL[0] == 0) continue;
+        // the tree above the leaves factored beside the leaf-level update
+        // (one launch) when no problem has a row-split part
+        const bool fuse = NBW == 32 && tree_overlap && la_groups == 0 && maxlev > 1 && rest_tiles > 0;
         int pid = prof ? prof->begin(sc) : -1;
-        hipLaunchKernelGGL((k_panel<T, NBW>), dim3(maxL[0], count), dim3(C::PT), 0, sc, d_descs, c0);
+        hipLaunchKernelGGL((k_panel<T, NBW>), dim3(maxL[0], count), dim3(C::PT), 0, sc, d_descs, c0, fuse ? 1 : 0);
         if (prof) prof->end(pid, sc, PROF_PANEL, pf, pb);
         if (la_groups == 0 && rest_tiles == 0) continue;
         if (rest_pending) {  // REST(k-1) updated columns that LA(k) and REST(k) touch
             (void)hipStreamWaitEvent(sc, la->evR, 0);
             rest_pending = false;
+        }
+        if (fuse) {
+            const int uid = prof ? prof->begin(sc) : -1;
+            hipLaunchKernelGGL((k_update<T, QrCfg<T, 32>::MT_MAX / 16, true>), dim3(maxL[0], rest_tiles + 1, count),
+                               dim3(256), 0, sc, d_descs, c0, 0);
+            if (prof) prof->end(uid, sc, PROF_UPDATE, uf[0], ub[0]);
+            for (int lev = 1; lev < maxlev; ++lev) {
+                const int lid = prof ? prof->begin(sc) : -1;
+                launch_update<T, NBW>(dim3(maxL[lev], rest_tiles, count), sc, d_descs, c0, lev);
+                if (prof) prof->end(lid, sc, PROF_UPDATE, uf[lev], ub[lev]);
+            }
+            continue;
         }
         if (la_groups > 0) {
             const int lid = prof ? prof->begin(sc) : -1;
@@ -1450,15 +1568,16 @@ static void qr_aug_batch_nb(const QrDesc<T>* d_descs, const QrDesc<T>* h, int co
 }
 // Every problem of one call has the same panel width (the engine groups them).
 template <typename T>
-void qr_aug_batch(const QrDesc<T>* d_descs, const QrDesc<T>* h, int count, hipStream_t s, const QrStreams* la) {
+void qr_aug_batch(const QrDesc<T>* d_descs, const QrDesc<T>* h, int count, hipStream_t s, const QrStreams* la,
+                  bool tree_overlap) {
     if (count <= 0) return;
-    if (h[0].nb == 64) qr_aug_batch_nb<T, 64>(d_descs, h, count, s, la);
-    else qr_aug_batch_nb<T, 32>(d_descs, h, count, s, la);
+    if (h[0].nb == 64) qr_aug_batch_nb<T, 64>(d_descs, h, count, s, la, tree_overlap);
+    else qr_aug_batch_nb<T, 32>(d_descs, h, count, s, la, tree_overlap);
 }
 template void qr_aug_batch<double>(const QrDesc<double>*, const QrDesc<double>*, int, hipStream_t,
-                                   const QrStreams*);
+                                   const QrStreams*, bool);
 template void qr_aug_batch<float>(const QrDesc<float>*, const QrDesc<float>*, int, hipStream_t,
-                                  const QrStreams*);
+                                  const QrStreams*, bool);
 
 thread_local Profiler* g_prof = nullptr;
 

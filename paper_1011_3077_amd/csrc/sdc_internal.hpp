@@ -213,9 +213,12 @@ template <typename T> struct IrsInit {
 };
 
 // Host-side launchers (defined in the .hip files).
+// tree_overlap: for panels without a row-split part, factor the tree above
+// the leaves in the same launch as the leaf-level trailing update
+// (k_update with CLIMB) instead of before it (32-column panels).
 template <typename T>
 void qr_aug_batch(const QrDesc<T>* d_descs, const QrDesc<T>* h_descs, int count, hipStream_t s,
-                  const QrStreams* la = nullptr);
+                  const QrStreams* la = nullptr, bool tree_overlap = true);
 template <typename T>
 void gemm_batch(const GemmDesc<T>* d_descs, const GemmDesc<T>* h_descs, int count, hipStream_t s);
 template <typename T>
