@@ -126,30 +126,48 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v) {
     return pair_sum<true>(v);
 }
 
-// Sums over the 64 lanes of eight values q[0..7] at once: each exchange
-// stage halves the values a lane carries (it keeps one half, adds the
-// partner's copy of it, and hands over the other half), so that after the
-// three 16-lane stages lane l carries column c(l) = (l >> 1) & 7 summed over
-// its 16-lane row; three plain stages finish the sum over the wave.  The
-// total of column c is then in lane 2c (among others).
+// Sum of x over lanes l and l ^ 32 (R32) or l ^ 16 (R16) in the lanes with
+// that lane bit clear, and of y in the lanes with it set: one gfx950 row swap
+// exchanges x's upper rows with y's lower ones, so x + y holds both pair sums
+// (an exchange stage of a transposed reduction, without selects).
+template <bool R32, typename T> __device__ __forceinline__ T swap_sum(T x, T y) {
+    if constexpr (sizeof(T) == 8) {
+        const unsigned long long bx = __builtin_bit_cast(unsigned long long, x);
+        const unsigned long long by = __builtin_bit_cast(unsigned long long, y);
+        unsigned xl = (unsigned)bx, xh = (unsigned)(bx >> 32), yl = (unsigned)by, yh = (unsigned)(by >> 32);
+        row_swap<R32>(xl, yl);
+        row_swap<R32>(xh, yh);
+        return __builtin_bit_cast(T, ((unsigned long long)xh << 32) | xl) +
+               __builtin_bit_cast(T, ((unsigned long long)yh << 32) | yl);
+    } else {
+        unsigned a = __builtin_bit_cast(unsigned, x), b = __builtin_bit_cast(unsigned, y);
+        row_swap<R32>(a, b);
+        return __builtin_bit_cast(T, a) + __builtin_bit_cast(T, b);
+    }
+}
+
+// Sums over the 64 lanes of eight values q[0..7] at once, as a transposed
+// reduction: each exchange stage pairs two of a lane's values with a
+// partner lane, keeps one of them summed over both lanes and hands the other
+// over, halving the values a lane carries.  The first two stages exchange
+// across 32-lane halves and 16-lane rows by row swaps (bits 5 and 4 of the
+// lane pick the value kept), the third within each row over the DPP mirror
+// (bit 3, with selects); three plain stages finish the sum over the eight
+// lanes that carry the same value.  Lane l ends with the total of column
+// c(l) = (l >> 3) & 7, so column c's total is in lane 8 c (among others).
 template <typename T> __device__ __forceinline__ T wave_sum8(const T (&q)[8], int lane) {
-    const bool b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+    const bool b3 = (lane >> 3) & 1;
     T h[4], g[2];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {  // partner lane ^ 15: columns by bit 3
-        const T keep = b3 ? q[k + 4] : q[k], send = b3 ? q[k] : q[k + 4];
-        h[k] = keep + lane_dpp<kDppMirror>(send);
-    }
+    for (int k = 0; k < 4; ++k) h[k] = swap_sum<true>(q[k], q[k + 4]);  // column k, or k + 4 if bit 5
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {  // partner lane ^ 7: by bit 2
-        const T keep = b2 ? h[k + 2] : h[k], send = b2 ? h[k] : h[k + 2];
-        g[k] = keep + lane_dpp<kDppHalfMirror>(send);
-    }
-    const T keep = b1 ? g[1] : g[0], send = b1 ? g[0] : g[1];  // partner lane ^ 2: by bit 1
-    T f = keep + lane_dpp<kDppXor2>(send);
+    for (int k = 0; k < 2; ++k) g[k] = swap_sum<false>(h[k], h[k + 2]);  // + 2 if bit 4
+    const T keep = b3 ? g[1] : g[0], send = b3 ? g[0] : g[1];          // partner lane ^ 15: + 1 if bit 3
+    T f = keep + lane_dpp<kDppMirror>(send);
+    f += lane_dpp<kDppHalfMirror>(f);
+    f += lane_dpp<kDppXor2>(f);
     f += lane_dpp<kDppXor1>(f);
-    f = pair_sum<false>(f);
-    return pair_sum<true>(f);
+    return f;
 }
 
 // ---------------------------------------------------------------------------
@@ -261,7 +279,7 @@ __device__ __forceinline__ bool qr_step(T (&a)[NRW][CW], T (&tc)[CW], T& tau_pre
         for (int c = 0; c < 8; ++c) q8[c] = q[8 * h + c];
         const T f = wave_sum8(q8, l);
 #pragma unroll
-        for (int c = 0; c < 8; ++c) sc8[8 * h + c] = lane_read(f, 2 * c);
+        for (int c = 0; c < 8; ++c) sc8[8 * h + c] = lane_read(f, 8 * c);
     }
     // this wave's share of T column j, scale sum_c T[i][c] S_c (tc is zero
     // for columns >= j)
