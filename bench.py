@@ -45,7 +45,7 @@ PEAK = {"fp64_tflops": 78.6, "fp32_tflops": 157.3, "hbm_gbs": 8000.0}
 # counter scaled by what it reads for a plain 256 MiB device copy
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), divided by the number of dispatches.  Valid only for the kernel sources it was measured
 # on (their SHA-256 below); otherwise reported as null.
-TRAFFIC = {"bytes_per_launch": 1579465462, "sha256": "acc714a0884db2c50058083a278229ec3bb94ae91df4f01202eec169613c3f63", "n": 8192, "note": "rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 over the 10536 update dispatches of one FP64 split"}
+TRAFFIC = {"bytes_per_launch": 1579465462, "sha256": "e443928ae1aebd5b7173e0ad28b3981fde7deb7517f8a0eff83d963ab3ba63b3", "n": 8192, "note": "rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 over the 10536 update dispatches of one FP64 split"}
 
 
 def log(*a):
@@ -55,7 +55,7 @@ def log(*a):
 def kernel_sources_sha():
     import hashlib
     hsh = hashlib.sha256()
-    for f in ("qr_kernels.hip", "sdc_internal.hpp", "mfma.hpp"):
+    for f in ("qr_kernels.hip", "sdc_internal.hpp", "mfma.hpp", "rawbuf.hpp"):
         with open(os.path.join(ROOT, "paper_1011_3077_amd", "csrc", f), "rb") as fh:
             hsh.update(fh.read())
     return hsh.hexdigest()

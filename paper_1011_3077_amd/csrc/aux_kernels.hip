@@ -7,6 +7,7 @@
 #include "sdc_internal.hpp"
 #include "sdc_aux.hpp"
 #include "mfma.hpp"
+#include "rawbuf.hpp"
 #include "profiler.hpp"
 
 namespace sdc {
@@ -136,6 +137,118 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc<T>* __restrict__ de
         }
 }
 
+// The same product with a 128 x 128 output tile per 256-thread block (2 x 2
+// waves of 64 x 64, sixteen 16x16x4 MFMAs per wave per k-step): each
+// element of A and B staged in LDS feeds twice the multiply-adds of the
+// 64 x 64 tile, which halves the operand traffic per flop (32 flop/B in
+// FP32, 16 in FP64, both above the chip's balance, so the matrix cores
+// rather than the memory bound it).  Operands are read through raw buffers
+// (32-bit offsets from one scalar resource; an element outside the matrix
+// is given the out-of-range offset and reads zero), so the loads need
+// neither 64-bit addresses nor branches.  Same k order as k_gemm, so the
+// results are the same bits.  For products whose M and N are both large and
+// whose operands span less than 2^31 bytes.
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_gemm128(const GemmDesc<T>* __restrict__ descs) {
+    using M = Mfma<T>;
+    typedef typename M::v4 v4;
+    // K chunk: 32 (FP32) or 16 (FP64) rows of A and B in LDS, the same bytes
+    constexpr int TM = 128, KC = sizeof(T) == 8 ? 16 : 32, PER = TM * KC / 256;
+    const GemmDesc<T> d = descs[blockIdx.z];
+    if (!d.active) return;
+    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TM;
+    if (m0 >= d.M || n0 >= d.N) return;
+    __shared__ T sA[KC][TM + 4];
+    __shared__ T sB[KC][TM + 4];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, gq = lane >> 4, ln = lane & 15;
+    const int wm = wave >> 1, wn = wave & 1;
+    const RawBuf<T> ba(d.A, (unsigned)((size_t)d.lda * (d.ta ? d.M : d.K) * sizeof(T)));
+    const RawBuf<T> bb(d.B, (unsigned)((size_t)d.ldb * (d.tb ? d.K : d.N) * sizeof(T)));
+    v4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = v4{0, 0, 0, 0};
+    T ra[PER], rb[PER];
+    // Thread tid moves elements e = tid + 256 t (t < PER) of each chunk: A as
+    // (m, k) with m fastest unless A is transposed, B as (k, n) with k
+    // fastest unless B is transposed, so that consecutive threads read
+    // consecutive addresses.  Either way element t sits at a fixed step from
+    // element 0 (256 is a multiple of TM and KC), so the geometry is set once.
+    int am, ak, adm, adk, bk, bn, bdk, bdn;
+    if (!d.ta) { am = tid & (TM - 1); ak = tid / TM; adm = 0; adk = 256 / TM; }
+    else { ak = tid & (KC - 1); am = tid / KC; adk = 0; adm = 256 / KC; }
+    if (!d.tb) { bk = tid & (KC - 1); bn = tid / KC; bdk = 0; bdn = 256 / KC; }
+    else { bn = tid & (TM - 1); bk = tid / TM; bdn = 0; bdk = 256 / TM; }
+    // element strides of m and k in A, of k and n in B
+    const unsigned a_sm = d.ta ? d.lda : 1, a_sk = d.ta ? 1 : d.lda;
+    const unsigned b_sk = d.tb ? d.ldb : 1, b_sn = d.tb ? 1 : d.ldb;
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            const int m = m0 + am + t * adm, ka = k0 + ak + t * adk;
+            ra[t] = ba.load(m < d.M && ka < d.K ? ((unsigned)m * a_sm + (unsigned)ka * a_sk) * (unsigned)sizeof(T)
+                                                : kOob);
+            const int n = n0 + bn + t * bdn, kb = k0 + bk + t * bdk;
+            rb[t] = bb.load(n < d.N && kb < d.K ? ((unsigned)kb * b_sk + (unsigned)n * b_sn) * (unsigned)sizeof(T)
+                                                : kOob);
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            sA[ak + t * adk][am + t * adm] = ra[t];
+            sB[bk + t * bdk][bn + t * bdn] = rb[t];
+        }
+    };
+    load(0);
+    stash();
+    __syncthreads();
+    for (int k0 = 0; k0 < d.K; k0 += KC) {
+        const bool more = k0 + KC < d.K;
+        if (more) load(k0 + KC);
+#pragma unroll
+        for (int kk = 0; kk < KC / 4; ++kk) {
+            T a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                a[i] = sA[kk * 4 + gq][wm * 64 + i * 16 + ln];
+                b[i] = sB[kk * 4 + gq][wn * 64 + i * 16 + ln];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = M::mma(a[i], b[j], acc[i][j]);
+        }
+        __syncthreads();
+        if (more) {
+            stash();
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int n = n0 + wn * 64 + j * 16 + ln;
+            if (n >= d.N) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int m = m0 + wm * 64 + i * 16 + M::row(gq, v);
+                if (m >= d.M) continue;
+                T* cp = d.C + (size_t)n * d.ldc + m;
+                T r = d.alpha * acc[i][j][v];
+                if (d.beta != T(0)) r += d.beta * *cp;
+                *cp = r;
+            }
+        }
+}
+
+// Products whose M and N are at least this take the 128 x 128 tile (enough
+// tiles to fill the chip at order 2048 and up; smaller ones keep the 64 x 64
+// tile's parallelism).
+constexpr int kGemmBigMin = 1024;
+
 template <typename T>
 void gemm_batch(const GemmDesc<T>* d_descs, const GemmDesc<T>* h, int count, hipStream_t s) {
     int M = 0, N = 0;
@@ -153,8 +266,20 @@ void gemm_batch(const GemmDesc<T>* d_descs, const GemmDesc<T>* h, int count, hip
                 fl += 2.0 * h[i].M * h[i].N * h[i].K;
                 by += ((double)h[i].M * h[i].K + (double)h[i].K * h[i].N + (double)h[i].M * h[i].N) * sizeof(T);
             }
+    int mn_min = 1 << 30;
+    bool small_span = true;  // every operand within the raw buffers' 2^31-byte range
+    for (int i = 0; i < count; ++i)
+        if (h[i].active) {
+            mn_min = std::min(mn_min, std::min(h[i].M, h[i].N));
+            const double sa = (double)h[i].lda * (h[i].ta ? h[i].M : h[i].K) * sizeof(T);
+            const double sb = (double)h[i].ldb * (h[i].tb ? h[i].K : h[i].N) * sizeof(T);
+            small_span = small_span && sa <= 2147483648.0 && sb <= 2147483648.0;
+        }
     const int id = prof ? prof->begin(s) : -1;
-    hipLaunchKernelGGL(k_gemm<T>, dim3((N + 63) / 64, (M + 63) / 64, count), dim3(256), 0, s, d_descs);
+    if (mn_min >= kGemmBigMin && small_span)
+        hipLaunchKernelGGL(k_gemm128<T>, dim3((N + 127) / 128, (M + 127) / 128, count), dim3(256), 0, s, d_descs);
+    else
+        hipLaunchKernelGGL(k_gemm<T>, dim3((N + 63) / 64, (M + 63) / 64, count), dim3(256), 0, s, d_descs);
     if (prof) prof->end(id, s, PROF_GEMM, fl, by);
 }
 template void gemm_batch<double>(const GemmDesc<double>*, const GemmDesc<double>*, int, hipStream_t);
