@@ -573,7 +573,7 @@ constexpr int kUpdGroup = 2;
 // reflectors and the tree counters.  The climb works in this kernel's LDS
 // arrays, so two workgroups still fit a CU.
 template <typename T, int RB, bool CLIMB>
-__global__ __launch_bounds__(256, 2) void k_update(const QrDesc<T>* __restrict__ descs, int c0, int level) {
+__global__ __launch_bounds__(256, (sizeof(T) == 4 && CLIMB) ? 3 : 2) void k_update(const QrDesc<T>* __restrict__ descs, int c0, int level) {
     using C = QrCfg<T, 32>;
     using M = Mfma<T>;
     typedef typename M::v4 v4;
