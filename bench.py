@@ -458,7 +458,7 @@ def main():
     ap.add_argument("--nmax", type=int, default=2048)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
               f"(the independent subproblems would shard across GPUs; a single large split would split its rows)", file=sys.stderr)
         sys.exit(2)
 
