@@ -381,9 +381,9 @@ typedef struct {
  * captured once (on a stream of the handle's own, after the descriptors are
  * resident on the device) and replayed per iteration; problems whose
  * convergence test has passed are switched off between replays.  Results
- * are bitwise the same either way.  Only problems below 1200 factored
- * columns are replayed (their QRs run on one stream; larger ones use the
- * two-stream look-ahead schedule and keep the direct launches).  Not used
+ * are bitwise the same either way.  Calls with a problem that takes the
+ * two-stream look-ahead schedule (sdc_lookahead_set; by default none) keep
+ * the direct launches (only one-stream QRs are captured).  Not used
  * while profiling is on, nor by the served form (its set of problems
  * changes every iteration).
  * SDC_ERR_INVALID for the no-allocation handle. */
@@ -392,11 +392,23 @@ sdc_status_t sdc_graphs_enable(sdc_handle_t h, int on);
 /* QR schedule of the repeated squaring and the rank-revealing QRs (Alg. 3,
  * Alg. 1; the TSQR panel of Sec. 4.2): with on != 0 (the default), a
  * 32-column panel whose reduction tree has more than one level and that has
- * no look-ahead part (problems below 1200 factored columns) has the levels
+ * no look-ahead part (see sdc_lookahead_set; by default none) has the levels
  * above its leaves factored in the same launch as the leaves' trailing
  * update, which does not depend on them; with on == 0 the whole tree is
  * factored first.  Results are bitwise the same either way. */
 sdc_status_t sdc_tree_overlap_enable(sdc_handle_t h, int on);
+
+/* QR schedule: problems with at least min_cols factored columns (min_cols
+ * > 0) take the two-stream look-ahead schedule (the trailing update of
+ * panel k split so that the next panel's columns are updated first and
+ * panel k + 1 is factored on a second stream beside the rest; Alg. 3's QRs
+ * and the rank-revealing ones); min_cols <= 0 (the default) sends every
+ * problem through the one-stream schedule, which measured faster at every
+ * order up to 8192 once the panel's tree is factored beside its leaves'
+ * update.  Results differ from the one-stream schedule's in rounding only
+ * (the look-ahead columns are updated by another kernel); a problem's bits
+ * depend on its own shape and this setting, not on the rest of a batch. */
+sdc_status_t sdc_lookahead_set(sdc_handle_t h, int min_cols);
 
 /* Enable (on != 0) or disable profiling; either way the totals are reset. */
 sdc_status_t sdc_profile_enable(sdc_handle_t h, int on);

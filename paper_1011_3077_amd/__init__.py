@@ -41,7 +41,7 @@ EXPORTED = ["sdc_opts_default", "sdc_create", "sdc_destroy", "sdc_status_string"
             "sdc_block_eigvals", "sdc_trevc",
             "sdc_gaussian", "sdc_tune_set", "sdc_tune_get", "sdc_autotune", "sdc_tune_save", "sdc_tune_load",
             "sdc_graphs_enable",
-            "sdc_tree_overlap_enable",
+            "sdc_tree_overlap_enable", "sdc_lookahead_set",
             "sdc_profile_enable", "sdc_profile_read", "sdc_server_create", "sdc_server_submit",
             "sdc_server_poll", "sdc_server_wait", "sdc_server_stats", "sdc_server_destroy"]
 SDC_REQ_SYM, SDC_REQ_PENCIL = 0, 1
@@ -165,6 +165,8 @@ lib.sdc_graphs_enable.argtypes = [_P, _I]
 lib.sdc_graphs_enable.restype = _I
 lib.sdc_tree_overlap_enable.argtypes = [_P, _I]
 lib.sdc_tree_overlap_enable.restype = _I
+lib.sdc_lookahead_set.argtypes = [_P, _I]
+lib.sdc_lookahead_set.restype = _I
 lib.sdc_tune_set.argtypes = [_P, _I, _I]
 lib.sdc_tune_set.restype = _I
 lib.sdc_tune_get.argtypes = [_P, C.POINTER(_I), C.POINTER(_I)]
@@ -440,6 +442,11 @@ class Handle:
         """Factor a QR panel's tree above its leaves beside the leaves'
         trailing update (on, the default) or before it; bitwise the same."""
         _check(lib.sdc_tree_overlap_enable(self._h, 1 if on else 0))
+
+    def lookahead_set(self, min_cols: int):
+        """Problems of at least min_cols factored columns take the two-stream
+        look-ahead QR schedule; min_cols <= 0 (the default): none."""
+        _check(lib.sdc_lookahead_set(self._h, int(min_cols)))
 
     def tune_set(self, nb64_min_fp64: int, nb64_min_fp32: int):
         _check(lib.sdc_tune_set(self._h, nb64_min_fp64, nb64_min_fp32))

@@ -437,6 +437,12 @@ sdc_status_t sdc_tree_overlap_enable(sdc_handle_t hd, int on) {
     return SDC_OK;
 }
 
+sdc_status_t sdc_lookahead_set(sdc_handle_t hd, int min_cols) {
+    if (!hd) return SDC_ERR_INVALID;
+    hd->h.la_min = min_cols > 0 ? min_cols : sdc::kLookaheadNever;
+    return SDC_OK;
+}
+
 sdc_status_t sdc_tune_set(sdc_handle_t hd, int nb64_min_fp64, int nb64_min_fp32) {
     if (!hd) return SDC_ERR_INVALID;
     hd->h.nb64_min[0] = tune_from_api(nb64_min_fp64);

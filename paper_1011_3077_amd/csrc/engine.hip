@@ -85,10 +85,11 @@ template <typename T, int NBW> static void qr_desc_aux(QrDesc<T>& d, int m, T* a
     d.tm_leaves = g.L(0);
 }
 template <typename T> static QrDesc<T> qr_desc(T* W, int ld, int m, int nf, int ncols, T* aux, T* diag,
-                                               unsigned* counters, int nb) {
+                                               unsigned* counters, int nb, int la_min) {
     QrDesc<T> d;
     d.W = W; d.ld = ld; d.m = m; d.nf = nf; d.ncols = ncols;
     d.nb = nb == 64 ? 64 : 32;
+    d.la_min = la_min;
     if (d.nb == 64) qr_desc_aux<T, 64>(d, m, aux);
     else qr_desc_aux<T, 32>(d, m, aux);
     d.diag = diag; d.counters = counters; d.active = 1;
@@ -96,14 +97,13 @@ template <typename T> static QrDesc<T> qr_desc(T* W, int ld, int m, int nf, int 
 }
 
 // Look-ahead streams for a batch of QRs, or none: only problems of at least
-// kLookaheadMinN factored columns are updated with look-ahead, and a single
-// stream saves the host the event calls of every panel (at smaller sizes the
-// host's launch rate is on the critical path).
+// the handle's look-ahead threshold (factored columns; by default none) are
+// updated with look-ahead, and a single stream saves the host the event
+// calls of every panel.
 template <typename T> static const QrStreams* lookahead(Handle& h, const std::vector<QrDesc<T>>& q) {
-    int nf = 0;
     for (const QrDesc<T>& d : q)
-        if (d.active) nf = std::max(nf, d.nf);
-    return nf >= kLookaheadMinN ? &h.qs : nullptr;
+        if (d.active && d.nf >= d.la_min) return &h.qs;
+    return nullptr;
 }
 
 // The QRs of a batch, one batched call per panel width (32 first): every
@@ -159,7 +159,7 @@ template <typename T> static int irs_tick(Handle& h, std::vector<IrsSide<T>*>& s
     for (int i = 0; i < cnt; ++i) {
         IrsSide<T>& s = *act[i];
         s.norms = h.dnorm + 4 * i;
-        qd[i] = qr_desc<T>(s.W, s.ld, 2 * s.n, s.n, 3 * s.n, s.Tm, s.diag, s.counters, s.nb);
+        qd[i] = qr_desc<T>(s.W, s.ld, 2 * s.n, s.n, 3 * s.n, s.Tm, s.diag, s.counters, s.nb, h.la_min);
         pd[i] = IrsDesc<T>{s.W, s.n, s.ld, s.Rprev, s.diag, s.norms, 1};
     }
     const size_t mark = h.desc_off;
@@ -229,19 +229,19 @@ template <typename T> struct IrsGraph {
 
 static bool use_graphs(const Handle& h) { return h.graphs && !h.prof.on && !h.no_alloc; }
 
-// Only QRs on one stream are captured: every side below kLookaheadMinN
-// factored columns.  (Capturing the two-stream look-ahead schedule, whose
-// second and third streams join the capture through event waits, ended in a
-// host segmentation fault at order 1300, in the runtime; larger problems
-// keep the direct launches, where the launch rate matters least.)
-template <typename T> static bool graphable(const std::vector<IrsSide<T>*>& sides) {
+// Only QRs on one stream are captured: every side below the handle's
+// look-ahead threshold.  (Capturing the two-stream look-ahead schedule,
+// whose second and third streams join the capture through event waits,
+// ended in a host segmentation fault at order 1300, in the runtime; sides
+// that take the look-ahead keep the direct launches.)
+template <typename T> static bool graphable(const Handle& h, const std::vector<IrsSide<T>*>& sides) {
     for (const IrsSide<T>* sp : sides)
-        if (sp->started && !sp->done && sp->n >= kLookaheadMinN) return false;
+        if (sp->started && !sp->done && sp->n >= h.la_min) return false;
     return true;
 }
 
 template <typename T> static int irs_graph_build(Handle& h, std::vector<IrsSide<T>*>& sides, IrsGraph<T>& g) {
-    if (!graphable(sides)) return SDC_ERR_INVALID;  // never captures the two-stream schedule
+    if (!graphable(h, sides)) return SDC_ERR_INVALID;  // never captures the two-stream schedule
     for (IrsSide<T>* sp : sides)
         if (sp->started && !sp->done) g.act.push_back(sp);
     const int cnt = (int)g.act.size();
@@ -254,7 +254,7 @@ template <typename T> static int irs_graph_build(Handle& h, std::vector<IrsSide<
     for (int i = 0; i < cnt; ++i) {
         IrsSide<T>& s = *g.act[i];
         s.norms = h.dnorm + 4 * i;
-        all[i] = qr_desc<T>(s.W, s.ld, 2 * s.n, s.n, 3 * s.n, s.Tm, s.diag, s.counters, s.nb);
+        all[i] = qr_desc<T>(s.W, s.ld, 2 * s.n, s.n, 3 * s.n, s.Tm, s.diag, s.counters, s.nb, h.la_min);
         pd[i] = IrsDesc<T>{s.W, s.n, s.ld, s.Rprev, s.diag, s.norms, 1};
     }
     std::vector<QrDesc<T>> grp[2];
@@ -511,7 +511,7 @@ static int run_qr(Handle& h, std::vector<JobWs*>& js, int dgi) {
     std::vector<QrDesc<double>> q;
     for (JobWs* w : js) {
         const int n = w->job->n;
-        q.push_back(qr_desc<double>(w->X, n, n, n, 2 * n, w->qaux, w->dg[dgi], w->qcnt, w->qnb));
+        q.push_back(qr_desc<double>(w->X, n, n, n, 2 * n, w->qaux, w->dg[dgi], w->qcnt, w->qnb, h.la_min));
     }
     if (q.empty()) return SDC_OK;
     CHK(ensure_streams(h));
@@ -1148,7 +1148,7 @@ int run_split_jobs(Handle& h, std::vector<SplitJob>& jobs) {
         CHK(ensure_host(h, sizeof(double) * 4 * most));
         IrsGraph<double> g64;
         IrsGraph<float> g32;
-        const bool gr64 = graphable(sd), gr32 = graphable(sf);
+        const bool gr64 = graphable(h, sd), gr32 = graphable(h, sf);
         if (gr64) CHK(irs_graph_build<double>(h, sd, g64));
         if (gr32) CHK(irs_graph_build<float>(h, sf, g32));
         for (int l64 = 1, l32 = 1; l64 || l32;) {

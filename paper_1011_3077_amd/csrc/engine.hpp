@@ -76,6 +76,9 @@ struct Handle {
     // QR schedule (sdc_tree_overlap_enable): the panel tree above the leaves
     // factored in the launch of the leaf-level trailing update
     bool tree_overlap = true;
+    // QR schedule (sdc_lookahead_set): problems of at least this many
+    // factored columns take the two-stream look-ahead schedule
+    int la_min = kLookaheadNever;
 };
 
 // Panel width (32 or 64) of a QR with nf factored columns: `forced` (the

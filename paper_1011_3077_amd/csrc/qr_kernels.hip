@@ -594,7 +594,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && CLIMB) ? 3 : 2) void k_upda
     if (!d.active || c0 >= d.nf) return;
     const int nbk = min(NB, d.nf - c0);
     // column range: the trailing columns after those of the row-split kernel
-    const int cb = c0 + nbk + row_split_cols(NB, d.nf, c0);
+    const int cb = c0 + nbk + row_split_cols(NB, d.nf, c0, d.la_min);
     const int ce = d.ncols;
     const int col0 = cb + (blockIdx.y - (CLIMB ? 1 : 0)) * 64;
     if (col0 >= ce) return;
@@ -803,7 +803,7 @@ __global__ __launch_bounds__(256, 2) void k_update64(const QrDesc<T>* __restrict
     const QrDesc<T> d = descs[blockIdx.z];
     if (!d.active || c0 >= d.nf) return;
     const int nbk = min(NB, d.nf - c0);
-    const int cb = c0 + nbk + row_split_cols(NB, d.nf, c0);
+    const int cb = c0 + nbk + row_split_cols(NB, d.nf, c0, d.la_min);
     const int ce = d.ncols;
     const int col0 = cb + blockIdx.y * 64;
     if (col0 >= ce) return;
@@ -995,7 +995,7 @@ __global__ __launch_bounds__(256) void k_la(const QrDesc<T>* __restrict__ descs,
     if (!d.active || c0 >= d.nf) return;
     const int nbk = min(NB, d.nf - c0);
     const int cb = c0 + nbk;
-    const int ce = cb + row_split_cols(NB, d.nf, c0);
+    const int ce = cb + row_split_cols(NB, d.nf, c0, d.la_min);
     const int cgrp = blockIdx.y;
     if (ce - cb <= 16 * cgrp) return;  // no columns in this group (for every node alike)
     const int cbase = cb + 16 * cgrp;
@@ -1225,7 +1225,7 @@ __global__ __launch_bounds__(256) void k_la64(const QrDesc<T>* __restrict__ desc
     if (!d.active || c0 >= d.nf) return;
     const int nbk = min(NB, d.nf - c0);
     const int cb = c0 + nbk;
-    const int ce = cb + row_split_cols(NB, d.nf, c0);
+    const int ce = cb + row_split_cols(NB, d.nf, c0, d.la_min);
     const int cgrp = blockIdx.y;
     if (ce - cb <= 16 * cgrp) return;  // no columns in this group (for every node alike)
     const int cbase = cb + 16 * cgrp;
@@ -1481,7 +1481,7 @@ static void qr_aug_batch_nb(const QrDesc<T>* d_descs, const QrDesc<T>* h, int co
             maxlev = maxlev > g.levels ? maxlev : g.levels;
             const int nbk = h[i].nf - c0 < C::NB ? h[i].nf - c0 : C::NB;
             const int trail = h[i].ncols - c0 - nbk;
-            const int nla = row_split_cols(C::NB, h[i].nf, c0);
+            const int nla = row_split_cols(C::NB, h[i].nf, c0, h[i].la_min);
             if (nla > 0) {
                 la_l0 = la_l0 > g.L(0) ? la_l0 : g.L(0);
                 la_groups = la_groups > (nla + 15) / 16 ? la_groups : (nla + 15) / 16;

@@ -121,15 +121,18 @@ __host__ __device__ inline int internal_index(const TreeGeomT<T, NBW>& g, int le
 // Which kernel updates which trailing columns after the panel at column c0
 // of a QR with nf factored columns: columns [c0 + nbk, c0 + nbk + la) go to
 // the row-split kernel (k_la), the rest to the wide kernel (k_update).  With
-// nf >= kLookaheadMinN the row-split kernel takes the next panel's columns
-// (look-ahead: they are done first, so that the next panel can be factored
-// beside the bulk update; below that size the bulk update is too short to
-// hide a panel).  The choice depends on the problem's own shape only, so a
-// problem rounds the same alone and in any batch.
-constexpr int kLookaheadMinN = 1200;
-__host__ __device__ inline int row_split_cols(int nb, int nf, int c0) {
+// nf >= la_min (the handle's look-ahead threshold, sdc_lookahead_set) the
+// row-split kernel takes the next panel's columns (look-ahead: they are done
+// first, so that the next panel can be factored on a second stream beside
+// the bulk update).  By default no problem takes it: with the panel's tree
+// above its leaves factored beside the leaf-level update on one stream, the
+// one-stream schedule measured faster at every order up to 8192.  The choice
+// depends on the problem's own shape and the handle only, so a problem
+// rounds the same alone and in any batch of the handle.
+constexpr int kLookaheadNever = 1 << 30;
+__host__ __device__ inline int row_split_cols(int nb, int nf, int c0, int la_min) {
     const int cb = c0 + (nf - c0 < nb ? nf - c0 : nb);
-    if (nf < kLookaheadMinN || cb >= nf) return 0;
+    if (nf < la_min || cb >= nf) return 0;
     return nf - cb < nb ? nf - cb : nb;
 }
 
@@ -154,6 +157,7 @@ template <typename T> struct QrDesc {
     unsigned* counters; // kMaxInternal tree arrival counters (must start at zero)
     int active;
     int nb;           // panel width (32 or 64); every problem of one batched call has the same
+    int la_min;       // look-ahead from this many factored columns (row_split_cols)
 };
 
 // Elements of one parity's side buffers for an m-row problem and panel

@@ -4,8 +4,8 @@ single splits (one panel to two-level trees), pencils, FP32 iterates, a
 batch whose problems finish at different iterations (switched off between
 replays), and the divide-and-conquer (one graph per level); graph calls
 interleaved with eager work and with each other, and the fallbacks to
-direct launches (profiling on; orders of 1200 and more, whose QRs run the
-two-stream look-ahead schedule, which is not captured)."""
+direct launches (profiling on; a handle whose QRs from 1200 factored
+columns run the two-stream look-ahead schedule, which is not captured)."""
 import numpy as np
 import pytest
 
@@ -130,3 +130,26 @@ def test_profiling_falls_back_to_direct_launches(sdc, handles):
     finally:
         hg.profile_enable(False)
     same(hd.split_sym(A, reg, sdc.opts(seed=1)), hg.split_sym(A, reg, sdc.opts(seed=1)))
+
+
+def test_lookahead_falls_back_to_direct_launches(sdc):
+    """With the look-ahead schedule enabled from 1200 factored columns, an
+    order-1300 split is not captured: the graph handle launches it directly,
+    with the same bits as a direct-launch handle of the same schedule."""
+    hd, hg = sdc.Handle(0), sdc.Handle(0)
+    try:
+        for h in (hd, hg):
+            h.lookahead_set(1200)
+        hg.graphs_enable(True)
+        n = 1300
+        print_case(test="graph_lookahead_fallback", n=n)
+        a, d, q = S.sym_problem(n, S.family_seed(0, 2400))
+        A = dev(a)
+        reg = sdc.region("halfplane", shift=0.0, scale=1.0)
+        o = sdc.opts(seed=4, diagnostics=1)
+        r_d = hd.split_sym(A, reg, o)
+        assert r_d.status == sdc.SDC_OK and r_d.info["k_lead"] == int((d > 0).sum())
+        same(r_d, hg.split_sym(A, reg, o))
+    finally:
+        hd.close()
+        hg.close()

@@ -2,7 +2,8 @@
 large orders) against the FP64 oracle, element by element where the result
 is unique, at orders that reach every path of the wider kernels: a single
 node, several tree levels (fan-in 4 above 256-row leaves), the row-split
-look-ahead (>= 1200 factored columns), FP32 iterates, and batches that mix
+look-ahead (the handle's schedule from 1200 factored columns), FP32
+iterates, and batches that mix
 the two widths (each problem bitwise the same alone and in the batch)."""
 import numpy as np
 import pytest
@@ -24,7 +25,10 @@ def sdc():
 
 @pytest.fixture(scope="module")
 def handle(sdc):
+    # the look-ahead schedule from 1200 factored columns, so that the order-1300
+    # cases run the 64-column row-split kernel
     h = sdc.Handle(0)
+    h.lookahead_set(1200)
     yield h
     h.close()
 
@@ -200,6 +204,7 @@ def test_batch_mixing_panel_widths_equals_single_calls(handle, sdc):
     print_case(test="batch_mixed_widths", sizes=sizes)
     h = sdc.Handle(0)
     try:
+        h.lookahead_set(1200)  # as the module's handle
         h.tune_set(1000, 1000)
         assert h.tune_get() == (1000, 1000)
         mats = [S.sym_problem(n, S.family_seed(2, 900 + i))[0] for i, n in enumerate(sizes)]

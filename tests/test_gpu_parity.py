@@ -191,21 +191,30 @@ def test_batched_equals_single_calls(handle, sdc):
         assert torch.equal(r.Q, single.Q) and torch.equal(r.Ahat, single.Ahat)
 
 
-def test_batched_mixed_with_lookahead_size_equals_single(handle, sdc):
+@pytest.mark.parametrize("lookahead", [0, 1200])
+def test_batched_mixed_with_lookahead_size_equals_single(sdc, lookahead):
     """A batch that mixes a problem large enough for the look-ahead schedule
-    (two streams) with small ones that take the row-split or the wide
-    update: each result is still bitwise the one of a single call, since
-    the kernel that updates a column is chosen from its own problem's shape."""
+    (two streams, when the handle enables it from 1200 factored columns)
+    with small ones that take the wide update, and, with the default
+    one-stream schedule, a problem of three tree levels with ones of one
+    and two: each result is still bitwise the one of a single call, since
+    the kernel that updates a column is chosen from its own problem's shape
+    and the handle."""
     sizes = [1300, 100, 300]
     mats = [S.sym_problem(n, S.family_seed(2, 40 + i))[0] for i, n in enumerate(sizes)]
     regs = [sdc.region("halfplane", shift=0.0, scale=1.0) for _ in sizes]
-    print_case(test="batched_mixed_lookahead", sizes=sizes)
-    batch = handle.split_sym_batched([dev(m) for m in mats], regs, sdc.opts(seed=91))
-    for i, (m, r) in enumerate(zip(mats, batch)):
-        single = handle.split_sym(dev(m), regs[i], sdc.opts(seed=91 + i * 1000003))
-        assert r.status == single.status == sdc.SDC_OK
-        assert r.info["k_lead"] == single.info["k_lead"]
-        assert torch.equal(r.Q, single.Q) and torch.equal(r.Ahat, single.Ahat)
+    print_case(test="batched_mixed_lookahead", sizes=sizes, lookahead=lookahead)
+    h = sdc.Handle(0)
+    try:
+        h.lookahead_set(lookahead)
+        batch = h.split_sym_batched([dev(m) for m in mats], regs, sdc.opts(seed=91))
+        for i, (m, r) in enumerate(zip(mats, batch)):
+            single = h.split_sym(dev(m), regs[i], sdc.opts(seed=91 + i * 1000003))
+            assert r.status == single.status == sdc.SDC_OK
+            assert r.info["k_lead"] == single.info["k_lead"]
+            assert torch.equal(r.Q, single.Q) and torch.equal(r.Ahat, single.Ahat)
+    finally:
+        h.close()
 
 
 def test_batched_many_equal_sizes(handle, sdc):

@@ -3,9 +3,12 @@ kernel paths of the full-size workloads.
 
 Orders 1250-1300 give 2n > 2048 stacked rows, so every panel's TSQR tree has
 leaves of up to 256 rows and internal levels (the tree of the order-2048 and
-order-8192 problems), and at least 1200 factored columns, so the QRs run the
-two-stream look-ahead schedule (next panel factored while the bulk of the
-trailing matrix is updated).  Same caller Gaussians on both sides, so the
+order-8192 problems).  Each case runs on two handles against one oracle
+result: the default one-stream schedule (the tree above the leaves factored
+beside the leaf-level update), and the two-stream look-ahead schedule
+(sdc_lookahead_set(1200): the next panel factored while the bulk of the
+trailing matrix is updated, the row-split kernel on its columns).  Same
+caller Gaussians on both sides, so the
 leading bases are unique and compared entry by entry; what is unique of the
 rest (subspaces, block spectra, E21) is compared as in the small-size tests.
 The FP32+refine path is held to the FP64 oracle at the same order.
@@ -29,10 +32,12 @@ def sdc():
 
 
 @pytest.fixture(scope="module")
-def handle(sdc):
-    h = sdc.Handle(0)
-    yield h
-    h.close()
+def handles(sdc):
+    one, la = sdc.Handle(0), sdc.Handle(0)
+    la.lookahead_set(1200)
+    yield [("one-stream", one), ("look-ahead", la)]
+    one.close()
+    la.close()
 
 
 def dev(x):
@@ -62,15 +67,20 @@ def print_case(**kw):
     print("CASE", kw, flush=True)
 
 
-def test_split_sym_matches_oracle_order_1300(handle, sdc):
+def test_split_sym_matches_oracle_order_1300(handles, sdc):
     import oracle as O
     n = 1300
-    print_case(test="split_sym_large", n=n)
     seed = S.family_seed(0, 1300)
     a, d, q = S.sym_problem(n, seed)
     gs, gdev = gauss_stack(n, seed)
-    res = handle.split_sym(dev(a), sdc.region("halfplane", shift=0.0, scale=1.0), sdc.opts(G=gdev, diagnostics=1))
     ref = O.split_sym(a, HALF0, gauss=lambda nn, att, side: gs[2 * att + side])
+    for name, handle in handles:
+        print_case(test="split_sym_large", n=n, schedule=name)
+        check_split_sym_1300(sdc, handle, a, d, gdev, ref, n)
+
+
+def check_split_sym_1300(sdc, handle, a, d, gdev, ref, n):
+    res = handle.split_sym(dev(a), sdc.region("halfplane", shift=0.0, scale=1.0), sdc.opts(G=gdev, diagnostics=1))
     info = res.info
     assert res.status == ref.status == sdc.SDC_OK
     k = info["k_lead"]
@@ -89,33 +99,39 @@ def test_split_sym_matches_oracle_order_1300(handle, sdc):
     assert np.abs(ev - np.sort(d)).max() <= 1e-10 * np.abs(d).max()
 
 
-def test_irs_pencil_matches_oracle_order_1250(handle, sdc):
+def test_irs_pencil_matches_oracle_order_1250(handles, sdc):
     """R_j of the last iteration (unique with a non-negative diagonal) entry
     by entry, the count p, and the Gram invariants of the iterates."""
     import oracle as O
     n = 1250
-    print_case(test="irs_pencil_large", n=n)
     pb = S.pencil_problem(n, S.family_seed(1, 1250))
-    st, ap, bp, r, p, rc = handle.irs(dev(pb["A"]), dev(pb["B"]), sdc.region())
     ref = O.irs(pb["A"], pb["B"], record=True)
-    assert st == sdc.SDC_OK and ref.converged and p == ref.p
     rr = ref.R_history[-1]
-    assert np.abs(host(r) - rr).max() <= 1e-10 * np.abs(rr).max()
-    ap, bp = host(ap), host(bp)
-    for x, y in ((ap.T @ ap, ref.A.T @ ref.A), (bp.T @ bp, ref.B.T @ ref.B), (ap.T @ bp, ref.A.T @ ref.B)):
-        assert np.abs(x - y).max() <= 1e-9 * max(1.0, np.abs(y).max())
+    for name, handle in handles:
+        print_case(test="irs_pencil_large", n=n, schedule=name)
+        st, ap, bp, r, p, rc = handle.irs(dev(pb["A"]), dev(pb["B"]), sdc.region())
+        assert st == sdc.SDC_OK and ref.converged and p == ref.p
+        assert np.abs(host(r) - rr).max() <= 1e-10 * np.abs(rr).max()
+        ap, bp = host(ap), host(bp)
+        for x, y in ((ap.T @ ap, ref.A.T @ ref.A), (bp.T @ bp, ref.B.T @ ref.B), (ap.T @ bp, ref.A.T @ ref.B)):
+            assert np.abs(x - y).max() <= 1e-9 * max(1.0, np.abs(y).max())
 
 
-def test_split_pencil_matches_oracle_order_1250(handle, sdc):
+def test_split_pencil_matches_oracle_order_1250(handles, sdc):
     import oracle as O
     n = 1250
-    print_case(test="split_pencil_large", n=n)
     seed = S.family_seed(1, 1250)
     pb = S.pencil_problem(n, seed)
     a, b, lam = pb["A"], pb["B"], pb["lam"]
     gs, gdev = gauss_stack(n, seed)
-    res = handle.split_pencil(dev(a), dev(b), sdc.region(), sdc.opts(G=gdev, diagnostics=1))
     ref = O.split_pencil(a, b, {"kind": "unit_disk"}, gauss=lambda nn, att, side: gs[2 * att + side])
+    for name, handle in handles:
+        print_case(test="split_pencil_large", n=n, schedule=name)
+        check_split_pencil_1250(sdc, handle, a, b, lam, gdev, ref)
+
+
+def check_split_pencil_1250(sdc, handle, a, b, lam, gdev, ref):
+    res = handle.split_pencil(dev(a), dev(b), sdc.region(), sdc.opts(G=gdev, diagnostics=1))
     info = res.info
     assert res.status == ref.status == sdc.SDC_OK
     k = info["k_lead"]
@@ -141,20 +157,25 @@ def test_split_pencil_matches_oracle_order_1250(handle, sdc):
     assert err <= max(1e-10, 2 * err_ref), (err, err_ref)
 
 
-def test_fp32_refine_matches_fp64_oracle_order_1300(handle, sdc):
+def test_fp32_refine_matches_fp64_oracle_order_1300(handles, sdc):
     """FP32 repeated squaring (the FP32 panel and update kernels on the
-    three-level tree and the look-ahead schedule) + FP64 refinement, against
+    three-level tree, both schedules) + FP64 refinement, against
     the FP64 oracle's split of the same matrix: exact rank, the outside
     subspace within 1e-9 (or the Davis-Kahan bound of the remaining E21),
     block eigenvalues within 1e-9 |A|_2, E21 within split_tol."""
     import oracle as O
     n = 1300
-    print_case(test="fp32_refine_large", n=n)
     seed = S.family_seed(0, 1301)
     a, d, q = S.sym_problem(n, seed)
+    ref = O.split_sym(a, HALF0, seed=3)
+    for name, handle in handles:
+        print_case(test="fp32_refine_large", n=n, schedule=name)
+        check_fp32_refine_1300(sdc, handle, a, d, ref, n)
+
+
+def check_fp32_refine_1300(sdc, handle, a, d, ref, n):
     res = handle.split_sym(dev(a), sdc.region("halfplane", shift=0.0, scale=1.0),
                            sdc.opts(prec=sdc.SDC_FP32_REFINE, seed=3, diagnostics=1))
-    ref = O.split_sym(a, HALF0, seed=3)
     info = res.info
     assert res.status == ref.status == sdc.SDC_OK and info["fp64_fallback"] == 0
     k = info["k_lead"]

@@ -2,7 +2,7 @@
 the same launch as the leaves' trailing update (sdc_tree_overlap_enable, the
 default) against the schedule that factors the whole tree first: every
 output bitwise equal, for trees of two and three levels (stacked heights up
-to 2200 rows, below the look-ahead size), FP64 and FP32 iterates, pencils,
+to 2200 rows), FP64 and FP32 iterates, pencils,
 a batch of mixed orders, the divide-and-conquer, and with the iterations
 replayed from a HIP graph."""
 import numpy as np
