@@ -1,10 +1,10 @@
 """The QR schedule that factors a panel's reduction tree above its leaves in
 the same launch as the leaves' trailing update (sdc_tree_overlap_enable, the
 default) against the schedule that factors the whole tree first: every
-output bitwise equal, for trees of two and three levels (stacked heights up
-to 2200 rows), FP64 and FP32 iterates, pencils,
-a batch of mixed orders, the divide-and-conquer, and with the iterations
-replayed from a HIP graph."""
+output bitwise equal, for trees of two, three and four levels (stacked
+heights up to 16400 rows), FP64 and FP32 iterates, pencils, a batch of
+mixed orders, the divide-and-conquer, and with the iterations replayed from
+a HIP graph."""
 import numpy as np
 import pytest
 
@@ -125,3 +125,28 @@ def test_graph_replay_overlap_equals_serial(sdc, handles):
         same(hg.split_sym(A, reg, o), r_off)
     finally:
         hg.close()
+
+
+def test_four_level_tree_overlap_equals_serial(sdc, handles):
+    """Order 8200: a stacked height of 16400 rows gives 65 leaves and four
+    tree levels (the climb beside the leaf-level update goes through two
+    level-2 nodes to the root).  The matrix is built on the device (seeded):
+    the comparison is between the two schedules, whose outputs must be
+    bitwise equal."""
+    h_on, h_off = handles
+    n = 8200
+    print_case(test="tree_overlap_four_levels", n=n)
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(S.family_seed(0, 3400))
+    q, _ = torch.linalg.qr(torch.randn(n, n, device="cuda:0", dtype=torch.float64, generator=gen))
+    d = torch.linspace(-1.0, 1.0, n, device="cuda:0", dtype=torch.float64)
+    d = torch.where(d.abs() < 0.05, torch.sign(d + 1e-300) * 0.05, d)
+    A = (q * d) @ q.T
+    A = 0.5 * (A + A.T)
+    del q
+    reg = sdc.region("halfplane", shift=0.0, scale=1.0)
+    o = sdc.opts(seed=5)
+    r_on = h_on.split_sym(A, reg, o)
+    assert r_on.status == sdc.SDC_OK and r_on.info["k_lead"] == int((d > 0).sum())
+    r_off = h_off.split_sym(A, reg, o)
+    same(r_on, r_off)
