@@ -45,7 +45,7 @@ PEAK = {"fp64_tflops": 78.6, "fp32_tflops": 157.3, "hbm_gbs": 8000.0}
 # counter scaled by what it reads for a plain 256 MiB device copy
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), divided by the number of dispatches.  Valid only for the kernel sources it was measured
 # on (their SHA-256 below); otherwise reported as null.
-TRAFFIC = {"bytes_per_launch": 1598398994, "sha256": "f03cdcdef8d0f8ee315c589573b371a52f8d6d323bcce3bde193bda2dc0ada81", "n": 8192, "note": "rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 over the 10536 update dispatches of one FP64 split"}
+TRAFFIC = {"bytes_per_launch": 1598099948, "sha256": "38306c9eab3fe1d73d0f6b50df873936e5b9e4246de662133c7df75ef389af6f", "n": 8192, "note": "rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 over the 10536 update dispatches of one FP64 split"}
 
 
 def log(*a):

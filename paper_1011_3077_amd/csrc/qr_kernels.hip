@@ -621,7 +621,15 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && CLIMB) ? 3 : 2) void k_upda
     const int rows_pad = ((mt + 15) >> 4) << 4;
     const int wave = tid >> 6, lane = tid & 63, gq = lane >> 4, ln = lane & 15;
     const int cbase = col0 + wave * 16;
-    const int rbe = rows_pad >> 4;
+    // FP32 leaf level: the node's rows are taken in row-block pairs (rows
+    // 32 p + 2 j and 32 p + 2 j + 1 at position j of blocks 2 p and 2 p + 1),
+    // so that a lane moves both with one 8-byte access, whole 128-byte lines
+    // per column as in FP64; the reflectors are staged with the same
+    // permutation (the sum over rows only changes its order).  Only nodes of
+    // even height (every leaf but possibly the last of an odd-height panel),
+    // so that a pair's rows are both in the node or both out of it.
+    const bool pair = sizeof(T) == 4 && level == 0 && (mt & 1) == 0;
+    const int rbe = pair ? ((mt + 31) >> 5) * 2 : rows_pad >> 4;
     // Global traffic goes through raw buffers (reads outside a range give
     // zero, writes there are dropped), so it has no branches: the compiler
     // counts the loads exactly and each consumer waits only for its own
@@ -660,22 +668,60 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && CLIMB) ? 3 : 2) void k_upda
                        : ((sr & (NB - 1)) < nbk ? s_rb[sr / NB] + (sr & (NB - 1)) : -1);
         return wr >= 0 ? (unsigned)((M::row(gq, 0) * ld + wr) * sizeof(T)) : kOob;
     };
+    // the pair (2 p, 2 p + 1) of the FP32 leaf level: rows lo + 32 p + 2 ln
+    // and the next (the height is even, so both or neither are in the node)
+    auto c_off2 = [&](int p) -> unsigned {
+        const int sr = p * 32 + 2 * ln;
+        return 2 * p < rbe && sr < mt ? (unsigned)((M::row(gq, 0) * ld + lo + sr) * sizeof(T)) : kOob;
+    };
     v4 cr[RB];
+    if constexpr (sizeof(T) == 4) {
+        auto load_half = [&](int rb0) {
+            if (pair) {
 #pragma unroll
-    for (int rb = 0; rb < RB / 2; ++rb) {
-        const unsigned o = c_off(rb);
+                for (int p = rb0 / 2; p < (rb0 + RB / 2) / 2; ++p) {
+                    const unsigned o = c_off2(p);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) cr[rb][q] = bc.load(o + (unsigned)(M::row(0, q) * ld * sizeof(T)));
-    }
-    // every row of s_V (zero beyond the node), without a branch
+                    for (int q = 0; q < 4; ++q) {
+                        const auto x = bc.load2(o + (unsigned)(M::row(0, q) * ld * sizeof(T)));
+                        cr[2 * p][q] = x[0];
+                        cr[2 * p + 1][q] = x[1];
+                    }
+                }
+            } else {
 #pragma unroll
-    for (int col = 0; col < NB; ++col) s_V[s * VS + col] = v[col];
-    __syncthreads();
+                for (int rb = rb0; rb < rb0 + RB / 2; ++rb) {
+                    const unsigned o = c_off(rb);
 #pragma unroll
-    for (int rb = RB / 2; rb < RB; ++rb) {
-        const unsigned o = c_off(rb);
+                    for (int q = 0; q < 4; ++q) cr[rb][q] = bc.load(o + (unsigned)(M::row(0, q) * ld * sizeof(T)));
+                }
+            }
+        };
+        load_half(0);
+        // every row of s_V (zero beyond the node), without a branch; in pair
+        // mode row s goes to position (s mod 32) / 2 of block 2 (s / 32) + s mod 2
+        const int sv = pair ? ((s >> 5) * 2 + (s & 1)) * 16 + ((s & 31) >> 1) : s;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) cr[rb][q] = bc.load(o + (unsigned)(M::row(0, q) * ld * sizeof(T)));
+        for (int col = 0; col < NB; ++col) s_V[sv * VS + col] = v[col];
+        __syncthreads();
+        load_half(RB / 2);
+    } else {
+#pragma unroll
+        for (int rb = 0; rb < RB / 2; ++rb) {
+            const unsigned o = c_off(rb);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cr[rb][q] = bc.load(o + (unsigned)(M::row(0, q) * ld * sizeof(T)));
+        }
+        // every row of s_V (zero beyond the node), without a branch
+#pragma unroll
+        for (int col = 0; col < NB; ++col) s_V[s * VS + col] = v[col];
+        __syncthreads();
+#pragma unroll
+        for (int rb = RB / 2; rb < RB; ++rb) {
+            const unsigned o = c_off(rb);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cr[rb][q] = bc.load(o + (unsigned)(M::row(0, q) * ld * sizeof(T)));
+        }
     }
     // T factor of this node, as the A operand of Y = T^T W: lane (gq, ln)
     // needs T[k][ln] for k = kb * 16 + row(gq, j); through a buffer (a
@@ -772,12 +818,34 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && CLIMB) ? 3 : 2) void k_upda
 #pragma unroll
                 for (int g = 0; g < G; ++g) cr[rb + g] = M::mma(ya[t], vb[g][t], cr[rb + g]);
             __builtin_amdgcn_sched_barrier(0);
+            if constexpr (sizeof(T) == 4) {
+                static_assert(G == 2, "a group is one row-block pair");
+                if (pair) {
+                    const unsigned o = c_off2(rb / 2);
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const unsigned o = c_off(rb + g);
+                    for (int q = 0; q < 4; ++q) {
+                        typename RawBuf<T>::f2 x;
+                        x[0] = cr[rb][q];
+                        x[1] = cr[rb + 1][q];
+                        bc.store2(x, o + (unsigned)(M::row(0, q) * ld * sizeof(T)));
+                    }
+                } else {
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    bc.store(cr[rb + g][q], o + (unsigned)(M::row(0, q) * ld * sizeof(T)));
+                    for (int g = 0; g < G; ++g) {
+                        const unsigned o = c_off(rb + g);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            bc.store(cr[rb + g][q], o + (unsigned)(M::row(0, q) * ld * sizeof(T)));
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const unsigned o = c_off(rb + g);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        bc.store(cr[rb + g][q], o + (unsigned)(M::row(0, q) * ld * sizeof(T)));
+                }
             }
         }
     }

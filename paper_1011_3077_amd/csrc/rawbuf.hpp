@@ -28,6 +28,18 @@ template <typename T> struct RawBuf {
             __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, off, 0, 0);
         }
     }
+    // two adjacent FP32 elements in one 8-byte access (both in range or both
+    // out of it: the callers pass kOob for a pair outside the data)
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    __device__ f2 load2(unsigned off) const {
+        static_assert(sizeof(T) == 4, "pairs of FP32 elements");
+        return __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    }
+    __device__ void store2(f2 x, unsigned off) const {
+        static_assert(sizeof(T) == 4, "pairs of FP32 elements");
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, off, 0, 0);
+    }
 };
 
 }  // namespace sdc
